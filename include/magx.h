@@ -1,0 +1,202 @@
+/*
+ * magx -- effective field and LLG time stepping on a uniform cell grid, on one
+ * AMD Instinct MI355X (gfx950).  C ABI.
+ *
+ * The operations follow the paper's problem statement (Section II-A/II-B,
+ * Eqs. (1)-(10)):
+ *   H_eff = H_bias + H_demag + H_ani + H_exch + H_DMI                 Eq. (2)
+ *   dm/dt = mu0 gamma_L [m x H_eff + alpha m x (m x H_eff)]           Eq. (1), M = Ms m
+ * with the demagnetising field evaluated as a zero-padded FFT convolution
+ * with a cell-averaged demag tensor (Section II-B, Eq. (3)), second-order
+ * central differences for exchange and DMI with the DMI boundary condition of
+ * Eq. (10), classical RK4 (Section III-C) and per-cell renormalisation of |m|
+ * after every stage and step (Section II-B).  The reverse mode (gradients of a
+ * scalar loss with respect to the initial m and to H_bias) is not in the
+ * paper; it is the exact adjoint of the forward algorithm.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Vector fields (m, H, dm/dt, gradients) are contiguous arrays of the
+ *    context's element type (float for MAGX_F32, double for MAGX_F64) laid out
+ *    (3, nz, ny, nx): component-major, then z, then y, with x fastest.
+ *  - All pointers named "device" point to memory on the context's GPU, owned
+ *    by the caller.  The library never allocates or frees device memory; the
+ *    sizes it needs are reported by magx_sizes().
+ *  - `stream` is a hipStream_t (NULL = default stream).  Calls only enqueue
+ *    work on that stream and return; they do not synchronise.
+ *  - Return value: MAGX_OK (0) or a negative MAGX_E* code.  Arguments are
+ *    validated before any HIP call; on an argument error nothing is enqueued.
+ *    MAGX_EHIP means a HIP launch or copy reported an error; the stream's
+ *    state is then undefined.
+ *  - Overlapping calls on one context from several host threads are not
+ *    supported (the context holds no device state other than what the caller
+ *    passes in, but its evaluation counter is not atomic).
+ */
+#ifndef MAGX_H
+#define MAGX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes -------------------------------------------------------- */
+#define MAGX_OK          0
+#define MAGX_EINVAL     -1   /* null pointer, non-positive size or spacing, bad flag, DMI without exchange */
+#define MAGX_ESIZE      -2   /* n > 4096 on an axis, or an extended-grid length P = next power of two
+                                >= 2n exceeds the FFT passes' limits: Py <= 4096; Px <= 4096 (float)
+                                or 2048 (double); Pz <= 2048 (float) or 1024 (double) */
+#define MAGX_EDTYPE     -3   /* unknown element type */
+#define MAGX_EWORKSPACE -4   /* reserved: buffer sizes are the caller's contract (see magx_sizes) */
+#define MAGX_EHIP       -5   /* a HIP call failed */
+#define MAGX_ENONFINITE -6   /* reserved: non-finite state */
+#define MAGX_ESTATE     -7   /* reserved */
+
+/* ---- field terms (bit mask), Eq. (2) -------------------------------------- */
+#define MAGX_DEMAG   1u   /* Eq. (3): demagnetising field                    */
+#define MAGX_EXCH    2u   /* Eq. (7): exchange, uniform A                    */
+#define MAGX_DMI     4u   /* Eq. (9) with the boundary condition Eq. (10)    */
+#define MAGX_ANIS    8u   /* Eq. (5): uniaxial anisotropy                    */
+#define MAGX_ZEEMAN 16u   /* uniform bias field H_bias                       */
+
+typedef enum { MAGX_F32 = 0, MAGX_F64 = 1 } magx_dtype;
+
+/* Cell grid (Section II-B): nx*ny*nz cells of dx*dy*dz metres, cell-centred. */
+typedef struct {
+    int nx, ny, nz;
+    double dx, dy, dz;
+} magx_grid;
+
+/* Material and physics constants, SI units (Section II-A).
+ *   Ms     saturation magnetisation, A/m (> 0)
+ *   A      exchange constant, J/m (>= 0; > 0 when MAGX_DMI is set)
+ *   D      interfacial DMI constant, J/m^2, used with the sign of Eq. (9)
+ *   Ku     uniaxial anisotropy constant, J/m^3, easy axis eK (unit vector)
+ *   Hbias  uniform bias field, A/m
+ *   alpha  Gilbert damping; gamma gyromagnetic ratio (the paper's -1.759e11);
+ *   mu0    vacuum permeability (4 pi 1e-7)
+ *   terms  bit mask of MAGX_* field terms
+ *   renorm 0: never renormalise; 1: renormalise the new state only;
+ *          2: renormalise every RK stage input and the new state (default)
+ *   check_finite  reserved, must be 0 or 1 */
+typedef struct {
+    double Ms, A, D, Ku;
+    double eK[3];
+    double Hbias[3];
+    double alpha, gamma, mu0;
+    unsigned terms;
+    int renorm;
+    int check_finite;
+} magx_params;
+
+/* Buffer sizes in bytes for a grid and element type. */
+typedef struct {
+    size_t spectrum_bytes;      /* demag tensor spectrum (persistent, magx_tensor_init) */
+    size_t init_scratch_bytes;  /* scratch used only during magx_tensor_init            */
+    size_t workspace_bytes;     /* workspace of every other call                          */
+    size_t tape_bytes_per_step; /* per recorded RK4 step (magx_step with a tape)          */
+    size_t tape_bytes_extra;    /* plus this once per tape                                */
+    size_t field_bytes;         /* one vector field: 3*nx*ny*nz elements                  */
+} magx_size_info;
+
+typedef struct magx_ctx magx_ctx;
+
+/* Sizes of every buffer for grid g and element type dt.  Host only. */
+int magx_sizes(const magx_grid* g, magx_dtype dt, magx_size_info* out);
+
+/* Creates a context and builds the demag tensor spectrum (Section II-B: the
+ * real-space tensor on the extended grid of twice the problem size, then its
+ * discrete Fourier transform).  The tensor is evaluated in double precision
+ * (cell-averaged Newell closed forms near the source cell, Gauss-Legendre
+ * quadrature of the dipole kernel against the cell-cell autocorrelation
+ * elsewhere), transformed in double precision and, for MAGX_F32, rounded once
+ * to float.  `spectrum` (device, spectrum_bytes) is kept by the context and
+ * must stay valid until magx_destroy; `scratch` (device, init_scratch_bytes)
+ * is free again when the stream reaches the end of this call's work.
+ * On success *ctx is set; on failure *ctx is NULL. */
+int magx_tensor_init(magx_ctx** ctx, const magx_grid* g, magx_dtype dt,
+                     void* spectrum, void* scratch, void* stream);
+
+/* Effective field, Eq. (2), of the unit field m (device, read) into H (device,
+ * written), in A/m.  `ws`: device workspace of workspace_bytes. */
+int magx_heff(magx_ctx* ctx, const void* m, const magx_params* p, void* H,
+              void* ws, void* stream);
+
+/* Right-hand side of Eq. (1) for unit m: dmdt = mu0 gamma_L [m x H + alpha
+ * m x (m x H)], gamma_L = gamma/(1+alpha^2), from m and a given field H
+ * (device, read).  Pointwise; dmdt must not overlap m or H. */
+int magx_llg_rhs(magx_ctx* ctx, const void* m, const void* H,
+                 const magx_params* p, void* dmdt, void* stream);
+
+/* Advances m (device, read and written in place) by nsteps classical RK4
+ * steps of size dt (Section III-C: four right-hand-side evaluations per
+ * step), renormalising per p->renorm.  If `tape` is not NULL (device,
+ * nsteps*tape_bytes_per_step + tape_bytes_extra) every stage input, stage
+ * field and pre-normalisation length is recorded for magx_step_backward. */
+int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps,
+              void* tape, void* ws, void* stream);
+
+/* Reverse mode of the linear part of the field: for a cotangent gH of H_eff
+ * (device, read), gm = K^T gH = K gH, where H_eff(m) = K m + H_bias (K is
+ * symmetric: the demag tensor is, and the ghost-cell DMI boundary condition
+ * makes exchange + DMI symmetric), and gHbias[0..2] = sum over cells of gH
+ * (device, 3 elements of the context type) when MAGX_ZEEMAN is set, else 0.
+ * gm and gHbias are overwritten. */
+int magx_heff_backward(magx_ctx* ctx, const void* gH, const magx_params* p,
+                       void* gm, void* gHbias, void* ws, void* stream);
+
+/* Reverse of magx_step over the same nsteps, from the tape it recorded with
+ * the same p and dt.  On entry gm (device) holds the cotangent of the final
+ * state; on return, that of the initial state.  gHbias (device, 3 elements)
+ * is incremented by the gradient with respect to H_bias. */
+int magx_step_backward(magx_ctx* ctx, const void* tape, int nsteps,
+                       const magx_params* p, double dt, void* gm, void* gHbias,
+                       void* ws, void* stream);
+
+/* Checkpointed rollout.  Forward: advances m by nsteps, storing the state at
+ * every multiple of `ckpt` steps (the start of each segment) in ckpt_store
+ * (device, ceil(nsteps/ckpt) fields).  Backward: walks the segments in
+ * reverse, re-running each with a tape (device, ckpt steps of tape) and
+ * reversing it; gm is the cotangent of the final state on entry and of the
+ * initial state on return; gHbias (device, 3) is overwritten with dL/dH_bias.
+ * `mwork` (device, one field) is scratch for the re-run segment. */
+int magx_rollout_forward(magx_ctx* ctx, void* m, const magx_params* p, double dt,
+                         int nsteps, int ckpt, void* ckpt_store, void* ws, void* stream);
+int magx_rollout_backward(magx_ctx* ctx, const void* ckpt_store, const magx_params* p,
+                          double dt, int nsteps, int ckpt, void* gm, void* gHbias,
+                          void* tape, void* mwork, void* ws, void* stream);
+
+/* Energies in joules of state m, written as 6 doubles to e_out (device):
+ * demag, exchange, DMI, anisotropy, Zeeman, total.  Densities of Eqs. (4),
+ * (6), (8), the DMI density whose variational derivative is Eq. (9), and
+ * -mu0 Ms m.H_bias, summed over cells times the cell volume.  Eq. (4) is used
+ * as -(mu0 Ms/2) m.H_demag. */
+int magx_energy(magx_ctx* ctx, const void* m, const magx_params* p, void* e_out,
+                void* ws, void* stream);
+
+/* Number of effective-field evaluations (FFT convolutions of a state)
+ * enqueued through this context so far. */
+long long magx_heff_count(const magx_ctx* ctx);
+
+/* Grid and type of a context (host). */
+int magx_ctx_info(const magx_ctx* ctx, magx_grid* g, magx_dtype* dt);
+
+/* Diagnostics: from magx_profile_start until magx_profile_stop, every launch
+ * of one kernel family enqueued through ctx is bracketed by a pair of HIP
+ * events on its stream.  kind: 0 none, 1 forward x pass, 2 forward y pass,
+ * 3 z pass with the spectral product, 4 inverse y pass, 5 RK4 stage (inverse
+ * x pass + local field + LLG + stage update + next forward x pass), 6 field
+ * output (inverse x pass + local field), 7 reverse-step start, 8 reverse RK4
+ * stage.  magx_profile_stop waits for the recorded events and returns the
+ * number of timed launches and their summed duration in milliseconds. */
+int magx_profile_start(magx_ctx* ctx, int kind);
+int magx_profile_stop(magx_ctx* ctx, long long* launches, double* total_ms);
+
+const char* magx_strerror(int code);
+void magx_destroy(magx_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MAGX_H */

@@ -1,0 +1,169 @@
+// Strided passes of the demag FFT convolution (Section II-B, Eq. (3)).
+//
+// Each block owns a tile of T consecutive kx columns (contiguous in memory,
+// coalesced row segments) and transforms them along y or z in LDS.
+//  * yfwd : rows y < ny are loaded, rows ny..Py-1 are the zero padding and
+//           never read from memory; all Py output rows are written.
+//  * zconv: for one ky, all three components: forward z FFT (rows z >= nz
+//           are zero padding), then the pointwise product with the real
+//           symmetric tensor spectrum, H_a = -Ms sum_b N_ab M_b, then the
+//           inverse z FFT; only rows z < nz are written back (in place).
+//  * yinv : inverse y FFT; only rows y < ny (inside the box) are written.
+#include "magx_internal.hpp"
+
+namespace magx {
+
+template <typename R> constexpr int emax() { return sizeof(R) == 4 ? 32 : 16; }
+
+template <typename R>
+__global__ void __launch_bounds__(kNT) yfwd_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
+                                                   int lgPy, int Hx, int Sx, int lgT, int ntx) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    const int T = 1 << lgT;
+    const int Py = 1 << lgPy;
+    const int tx = blockIdx.x % ntx;
+    const long long plane = blockIdx.x / ntx;    // c * nz + z
+    const int kx0 = tx * T;
+    const cx<R>* src = X1 + plane * ny * (long long)Sx;
+    cx<R>* dst = X2 + plane * Py * (long long)Sx;
+    const cx<R> zero = mk<R>(0, 0);
+    for (int e = threadIdx.x; e < (Py << lgT); e += kNT) {
+        const int row = e >> lgT, col = e & (T - 1);
+        const int kx = kx0 + col;
+        cx<R> v = zero;
+        if (row < ny && kx < Hx) v = src[(long long)row * Sx + kx];
+        buf[e] = v;
+    }
+    lds_fft<R, false, emax<R>()>(buf, lgPy, T, 1, T, true);
+    for (int e = threadIdx.x; e < (Py << lgT); e += kNT) {
+        const int row = e >> lgT, col = e & (T - 1);
+        const int kx = kx0 + col;
+        if (kx < Hx) dst[(long long)row * Sx + kx] = buf[e];
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
+                                                   int lgPy, int Hx, int Sx, int lgT, int ntx) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    const int T = 1 << lgT;
+    const int Py = 1 << lgPy;
+    const int tx = blockIdx.x % ntx;
+    const long long plane = blockIdx.x / ntx;
+    const int kx0 = tx * T;
+    const cx<R>* src = X2 + plane * Py * (long long)Sx;
+    cx<R>* dst = Y1 + plane * ny * (long long)Sx;
+    const cx<R> zero = mk<R>(0, 0);
+    for (int e = threadIdx.x; e < (Py << lgT); e += kNT) {
+        const int row = e >> lgT, col = e & (T - 1);
+        const int kx = kx0 + col;
+        buf[e] = kx < Hx ? src[(long long)row * Sx + kx] : zero;
+    }
+    lds_fft<R, true, emax<R>()>(buf, lgPy, T, 1, T, true);
+    for (int e = threadIdx.x; e < (ny << lgT); e += kNT) {
+        const int row = e >> lgT, col = e & (T - 1);
+        const int kx = kx0 + col;
+        if (kx < Hx) dst[(long long)row * Sx + kx] = buf[e];
+    }
+}
+
+// LDS layout: element (z, c, col) at (z * 3 + c) * T + col, i.e. sequence
+// b = c*T + col with unit sequence stride and element stride 3T.
+template <typename R>
+__global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
+                                                    int nz, int lgPz, int Py, int Hx, int Hy, int Hz, int Sx,
+                                                    int lgT, int ntx) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    const int T = 1 << lgT;
+    const int T3 = 3 * T;
+    const int Pz = 1 << lgPz;
+    const int tx = blockIdx.x % ntx;
+    const int ky = blockIdx.x / ntx;
+    const int kx0 = tx * T;
+    const long long plane_stride = (long long)Py * Sx;     // one z row of X2
+    const long long comp_stride = (long long)nz * plane_stride;
+    cx<R>* base = X2 + (long long)ky * Sx;
+    const cx<R> zero = mk<R>(0, 0);
+    for (int e = threadIdx.x; e < Pz * T3; e += kNT) {
+        const int z = e / T3, r = e - z * T3;
+        const int c = r >> lgT, col = r & (T - 1);
+        const int kx = kx0 + col;
+        cx<R> v = zero;
+        if (z < nz && kx < Hx) v = base[c * comp_stride + z * plane_stride + kx];
+        buf[e] = v;
+    }
+    lds_fft<R, false, emax<R>()>(buf, lgPz, T3, 1, T3, true);
+    // pointwise 3x3 symmetric product with the real spectrum (octant + parity)
+    const int kyo = ky <= Py / 2 ? ky : Py - ky;
+    const R sy = ky <= Py / 2 ? (R)1 : (R)-1;
+    const long long cstride = (long long)Hz * Hy * Sx;
+    for (int e = threadIdx.x; e < Pz * T; e += kNT) {
+        const int kz = e >> lgT, col = e & (T - 1);
+        const int kx = kx0 + col;
+        if (kx >= Hx) continue;
+        const int kzo = kz <= Pz / 2 ? kz : Pz - kz;
+        const R sz = kz <= Pz / 2 ? (R)1 : (R)-1;
+        const R* sp = spec + ((long long)kzo * Hy + kyo) * Sx + kx;
+        const R nxx = sp[0], nyy = sp[cstride], nzz = sp[2 * cstride];
+        const R nxy = sy * sp[3 * cstride], nxz = sz * sp[4 * cstride], nyz = sy * sz * sp[5 * cstride];
+        cx<R>* p = buf + kz * T3 + col;
+        const cx<R> mx = p[0], my = p[T], mz = p[2 * T];
+        const R s = -Ms;
+        p[0] = mk<R>(s * (nxx * mx.x + nxy * my.x + nxz * mz.x), s * (nxx * mx.y + nxy * my.y + nxz * mz.y));
+        p[T] = mk<R>(s * (nxy * mx.x + nyy * my.x + nyz * mz.x), s * (nxy * mx.y + nyy * my.y + nyz * mz.y));
+        p[2 * T] = mk<R>(s * (nxz * mx.x + nyz * my.x + nzz * mz.x), s * (nxz * mx.y + nyz * my.y + nzz * mz.y));
+    }
+    lds_fft<R, true, emax<R>()>(buf, lgPz, T3, 1, T3, true);
+    for (int e = threadIdx.x; e < nz * T3; e += kNT) {
+        const int z = e / T3, r = e - z * T3;
+        const int c = r >> lgT, col = r & (T - 1);
+        const int kx = kx0 + col;
+        if (kx < Hx) base[c * comp_stride + z * plane_stride + kx] = buf[e];
+    }
+}
+
+template <typename R>
+hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
+    const int lgT = ilog2(pl.ty);
+    const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
+    const unsigned blocks = (unsigned)(ntx * 3 * pl.nz);
+    const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
+    hipLaunchKernelGGL(yfwd_kernel<R>, dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
+                       static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
+    const int lgT = ilog2(pl.ty);
+    const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
+    const unsigned blocks = (unsigned)(ntx * 3 * pl.nz);
+    const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
+    hipLaunchKernelGGL(yinv_kernel<R>, dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X2),
+                       static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s) {
+    const int lgT = ilog2(pl.tz);
+    const int ntx = (pl.Hx + pl.tz - 1) / pl.tz;
+    const unsigned blocks = (unsigned)(ntx * pl.Py);
+    const size_t lds = (size_t)3 * pl.Pz * pl.tz * sizeof(cx<R>);
+    hipLaunchKernelGGL(zconv_kernel<R>, dim3(blocks), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
+                       static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hy, pl.Hz, pl.Sx, lgT,
+                       ntx);
+    return hipGetLastError();
+}
+
+template hipError_t launch_yfwd<float>(const Plan&, const void*, void*, hipStream_t);
+template hipError_t launch_yfwd<double>(const Plan&, const void*, void*, hipStream_t);
+template hipError_t launch_yinv<float>(const Plan&, const void*, void*, hipStream_t);
+template hipError_t launch_yinv<double>(const Plan&, const void*, void*, hipStream_t);
+template hipError_t launch_zconv<float>(const Plan&, void*, const void*, float, hipStream_t);
+template hipError_t launch_zconv<double>(const Plan&, void*, const void*, double, hipStream_t);
+
+}  // namespace magx

@@ -1,0 +1,597 @@
+// C ABI of the magx library: argument validation, planning, buffer layout and
+// launch sequencing on the caller's stream.  Every numeric step runs in the
+// HIP kernels of tensor.hip, conv.hip and pencil.hip.
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <utility>
+#include <vector>
+
+#include "magx_internal.hpp"
+
+using namespace magx;
+
+struct magx_ctx {
+    Plan pl;
+    void* spectrum;
+    long long heff_count;
+    int device;
+    // launch timing of one kernel family (diagnostics)
+    int prof_kind;
+    size_t prof_used;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+};
+
+namespace magx {
+
+enum ProfKind { kProfXfwd = 1, kProfYfwd, kProfZconv, kProfYinv, kProfStage, kProfField, kProfBstart, kProfBstage };
+
+// Records a HIP event pair around one launch when its family is being timed.
+struct ProfScope {
+    magx_ctx* c;
+    hipStream_t s;
+    hipEvent_t stop = nullptr;
+    ProfScope(magx_ctx* ctx, int kind, hipStream_t st) : c(ctx), s(st) {
+        if (!c || c->prof_kind != kind) return;
+        if (c->prof_used == c->prof_events.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess) return;
+            if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return; }
+            c->prof_events.emplace_back(a, b);
+        }
+        auto& ev = c->prof_events[c->prof_used++];
+        (void)hipEventRecord(ev.first, s);
+        stop = ev.second;
+    }
+    ~ProfScope() {
+        if (stop) (void)hipEventRecord(stop, s);
+    }
+};
+
+}  // namespace magx
+
+namespace magx {
+
+static int next_pow2_at_least(long long v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+static int pow2_floor(long long v) {
+    int p = 1;
+    while ((long long)p * 2 <= v) p <<= 1;
+    return p;
+}
+
+int make_plan(const magx_grid* g, magx_dtype dt, Plan* pl) {
+    if (!g || !pl) return MAGX_EINVAL;
+    if (dt != MAGX_F32 && dt != MAGX_F64) return MAGX_EDTYPE;
+    if (g->nx < 1 || g->ny < 1 || g->nz < 1) return MAGX_EINVAL;
+    if (!(g->dx > 0.0) || !(g->dy > 0.0) || !(g->dz > 0.0) || !std::isfinite(g->dx) || !std::isfinite(g->dy) ||
+        !std::isfinite(g->dz))
+        return MAGX_EINVAL;
+    Plan p{};
+    p.dtype = dt;
+    p.esize = dt == MAGX_F32 ? 4 : 8;
+    p.nx = g->nx; p.ny = g->ny; p.nz = g->nz;
+    p.dx = g->dx; p.dy = g->dy; p.dz = g->dz;
+    if (g->nx > 4096 || g->ny > 4096 || g->nz > 4096) return MAGX_ESIZE;
+    p.Px = next_pow2_at_least(std::max(2, 2 * g->nx));
+    p.Py = next_pow2_at_least(std::max(2, 2 * g->ny));
+    p.Pz = next_pow2_at_least(std::max(2, 2 * g->nz));
+    // LDS budgets of the passes (64 KiB per block): x lines 3*Lh, y columns
+    // Py*ty, z columns 3*Pz*tz complex values
+    const int lds_cplx = dt == MAGX_F32 ? 8192 : 4096;
+    if (p.Py > 4096 || 3 * (p.Px / 2) > lds_cplx || 3 * p.Pz > lds_cplx) return MAGX_ESIZE;
+    p.lgPx = ilog2(p.Px); p.lgPy = ilog2(p.Py); p.lgPz = ilog2(p.Pz);
+    p.Lh = p.Px / 2; p.lgLh = p.lgPx - 1;
+    p.Hx = p.Lh + 1; p.Hy = p.Py / 2 + 1; p.Hz = p.Pz / 2 + 1;
+    p.Sx = (p.Hx + 15) / 16 * 16;
+    p.ncell = (long long)p.nx * p.ny * p.nz;
+    p.ty = std::min(16, pow2_floor(lds_cplx / p.Py));
+    p.tz = std::min(64, pow2_floor(lds_cplx / (3 * p.Pz)));
+    p.np = std::max(1, 1024 / p.Lh);
+    const int npen = p.ny * p.nz;
+    if (p.np > npen) p.np = npen;
+    p.pencil_blocks = (npen + p.np - 1) / p.np;
+    const size_t es = (size_t)p.esize;
+    const long long N = p.ncell;
+    p.field_bytes = (size_t)3 * N * es;
+    size_t off = 0;
+    p.off_x1 = off; off = align256(off + (size_t)3 * p.nz * p.ny * p.Sx * 2 * es);
+    p.off_x2 = off; off = align256(off + (size_t)3 * p.nz * p.Py * p.Sx * 2 * es);
+    for (int i = 0; i < 4; ++i) { p.off_f[i] = off; off = align256(off + p.field_bytes); }
+    p.off_part = off; off = align256(off + (size_t)p.pencil_blocks * 8 * sizeof(double));
+    p.ws_bytes = off;
+    p.tape_step_bytes = (size_t)28 * N * es;
+    p.tape_extra_bytes = (size_t)3 * N * es;
+    p.spectrum_bytes = (size_t)6 * p.Hz * p.Hy * p.Sx * es;
+    const long long a1 = 6 * N, a2 = 6LL * p.Hy * p.Hx * p.nz;
+    p.scratch_a_elems = std::max(a1, a2);
+    p.scratch_b_elems = 6LL * p.Hx * p.nz * p.ny;
+    p.scratch_bytes = (size_t)(p.scratch_a_elems + p.scratch_b_elems) * sizeof(double);
+    *pl = p;
+    return MAGX_OK;
+}
+
+static int check_params(const magx_params* p) {
+    if (!p) return MAGX_EINVAL;
+    const double v[] = {p->Ms, p->A, p->D, p->Ku, p->eK[0], p->eK[1], p->eK[2], p->Hbias[0], p->Hbias[1],
+                        p->Hbias[2], p->alpha, p->gamma, p->mu0};
+    for (double x : v)
+        if (!std::isfinite(x)) return MAGX_EINVAL;
+    if (!(p->Ms > 0.0) || !(p->mu0 > 0.0) || p->alpha < 0.0 || p->A < 0.0) return MAGX_EINVAL;
+    if (p->terms & ~31u) return MAGX_EINVAL;
+    if (p->renorm < 0 || p->renorm > 2) return MAGX_EINVAL;
+    if (p->check_finite != 0 && p->check_finite != 1) return MAGX_EINVAL;
+    if ((p->terms & MAGX_DMI) && (!(p->terms & MAGX_EXCH) || !(p->A > 0.0))) return MAGX_EINVAL;
+    return MAGX_OK;
+}
+
+template <typename R>
+static Phys<R> make_phys(const Plan& pl, const magx_params* p) {
+    Phys<R> ph{};
+    const double mu0Ms = p->mu0 * p->Ms;
+    ph.Ms = (R)p->Ms;
+    ph.cex = (R)(2.0 * p->A / mu0Ms);
+    ph.cdmi = (R)(2.0 * p->D / mu0Ms);
+    ph.kap = (p->terms & MAGX_DMI) ? (R)(-p->D / (2.0 * p->A)) : (R)0;
+    ph.cani = (R)(2.0 * p->Ku / mu0Ms);
+    for (int c = 0; c < 3; ++c) {
+        ph.eK[c] = (R)p->eK[c];
+        ph.hb[c] = (R)p->Hbias[c];
+    }
+    ph.a = (R)(p->mu0 * p->gamma / (1.0 + p->alpha * p->alpha));
+    ph.alpha = (R)p->alpha;
+    ph.idx2 = (R)(1.0 / (pl.dx * pl.dx));
+    ph.idy2 = (R)(1.0 / (pl.dy * pl.dy));
+    ph.idz2 = (R)(1.0 / (pl.dz * pl.dz));
+    ph.h2x = (R)(0.5 / pl.dx);
+    ph.h2y = (R)(0.5 / pl.dy);
+    ph.dx = (R)pl.dx;
+    ph.dy = (R)pl.dy;
+    ph.terms = p->terms;
+    ph.renorm = p->renorm;
+    return ph;
+}
+
+static std::mutex g_tw_mutex;
+static bool g_tw_ready[64];
+
+static int ensure_twiddles(hipStream_t s, int* device) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return MAGX_EHIP;
+    *device = dev;
+    if (dev < 0 || dev >= 64) return MAGX_EHIP;
+    std::lock_guard<std::mutex> lk(g_tw_mutex);
+    if (g_tw_ready[dev]) return MAGX_OK;
+    if (launch_twiddle_init(s) != hipSuccess) return MAGX_EHIP;
+    // other streams of this device may use the table right away
+    if (hipStreamSynchronize(s) != hipSuccess) return MAGX_EHIP;
+    g_tw_ready[dev] = true;
+    return MAGX_OK;
+}
+
+static inline char* bptr(void* p, size_t off) { return static_cast<char*>(p) + off; }
+
+// Convolution passes on X1 (input, overwritten with Y1) using X2.
+template <typename R>
+static int conv_passes(magx_ctx* c, void* ws, R Ms, hipStream_t s) {
+    const Plan& pl = c->pl;
+    void* X1 = bptr(ws, pl.off_x1);
+    void* X2 = bptr(ws, pl.off_x2);
+    {
+        ProfScope ps(c, kProfYfwd, s);
+        if (launch_yfwd<R>(pl, X1, X2, s) != hipSuccess) return MAGX_EHIP;
+    }
+    {
+        ProfScope ps(c, kProfZconv, s);
+        if (launch_zconv<R>(pl, X2, c->spectrum, Ms, s) != hipSuccess) return MAGX_EHIP;
+    }
+    {
+        ProfScope ps(c, kProfYinv, s);
+        if (launch_yinv<R>(pl, X2, X1, s) != hipSuccess) return MAGX_EHIP;
+    }
+    c->heff_count++;
+    return MAGX_OK;
+}
+
+template <typename R>
+static int do_heff(magx_ctx* c, const R* m, const magx_params* p, R* H, void* ws, hipStream_t s, int energy,
+                   double* e_out) {
+    const Plan& pl = c->pl;
+    Phys<R> ph = make_phys<R>(pl, p);
+    void* X1 = bptr(ws, pl.off_x1);
+    double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
+    if (p->terms & MAGX_DEMAG) {
+        {
+            ProfScope ps(c, kProfXfwd, s);
+            if (launch_xfwd<R>(pl, m, X1, s) != hipSuccess) return MAGX_EHIP;
+        }
+        int rc = conv_passes<R>(c, ws, ph.Ms, s);
+        if (rc) return rc;
+    }
+    {
+        ProfScope ps(c, kProfField, s);
+        if (launch_field<R>(pl, ph, X1, m, H, 1, energy, 0, part, s) != hipSuccess) return MAGX_EHIP;
+    }
+    if (energy) {
+        const double V = pl.dx * pl.dy * pl.dz;
+        const double pref = -0.5 * p->mu0 * p->Ms * V;
+        const double vku = (p->terms & MAGX_ANIS) ? (double)pl.ncell * V * p->Ku : 0.0;
+        if (launch_energy_finish(part, pl.pencil_blocks, pref, vku, e_out, s) != hipSuccess) return MAGX_EHIP;
+    }
+    return MAGX_OK;
+}
+
+template <typename R>
+struct TapeView {
+    R* base;
+    long long N;
+    int nsteps;
+    R* y(int n, int s) const {   // s = 1..5
+        if (s == 5) return n + 1 < nsteps ? y(n + 1, 1) : base + (long long)nsteps * 28 * N;
+        return base + (long long)n * 28 * N + (long long)(s - 1) * 3 * N;
+    }
+    R* H(int n, int s) const { return base + (long long)n * 28 * N + 12 * N + (long long)(s - 1) * 3 * N; }
+    R* nx(int n, int s) const { return base + (long long)n * 28 * N + 24 * N + (long long)(s - 2) * N; }  // s = 2..5
+};
+
+template <typename R>
+static int do_step(magx_ctx* c, R* m, const magx_params* p, double dt, int nsteps, R* tape, void* ws,
+                   hipStream_t s) {
+    const Plan& pl = c->pl;
+    Phys<R> ph = make_phys<R>(pl, p);
+    const bool demag = (p->terms & MAGX_DEMAG) != 0;
+    void* X1 = bptr(ws, pl.off_x1);
+    R* acc = reinterpret_cast<R*>(bptr(ws, pl.off_f[0]));
+    R* ybuf[2] = {reinterpret_cast<R*>(bptr(ws, pl.off_f[1])), reinterpret_cast<R*>(bptr(ws, pl.off_f[2]))};
+    TapeView<R> tv{tape, pl.ncell, nsteps};
+    if (demag) {
+        ProfScope ps(c, kProfXfwd, s);
+        if (launch_xfwd<R>(pl, m, X1, s) != hipSuccess) return MAGX_EHIP;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+        for (int st = 1; st <= 4; ++st) {
+            if (demag) {
+                int rc = conv_passes<R>(c, ws, ph.Ms, s);
+                if (rc) return rc;
+            } else {
+                c->heff_count++;
+            }
+            StageArgs<R> a{};
+            a.yin = st == 1 ? m : (tape ? tv.y(n, st) : ybuf[st % 2]);
+            a.mn = m;
+            a.acc = acc;
+            a.yout = st < 4 ? (tape ? tv.y(n, st + 1) : ybuf[(st + 1) % 2]) : m;
+            a.yout2 = (st == 4 && tape) ? tv.y(n, 5) : nullptr;
+            a.tapeH = tape ? tv.H(n, st) : nullptr;
+            a.tapeNx = tape ? tv.nx(n, st + 1) : nullptr;
+            a.tapeYin = (st == 1 && tape) ? tv.y(n, 1) : nullptr;
+            a.stage = st;
+            a.dt = (R)dt;
+            a.want_next = !(n == nsteps - 1 && st == 4);
+            ProfScope ps(c, kProfStage, s);
+            if (launch_stage<R>(pl, ph, X1, X1, a, s) != hipSuccess) return MAGX_EHIP;
+        }
+    }
+    return MAGX_OK;
+}
+
+template <typename R>
+static int do_step_backward(magx_ctx* c, const R* tape, int nsteps, const magx_params* p, double dt, R* gm,
+                            R* gHbias, void* ws, hipStream_t s, bool fresh = true, bool finish = true) {
+    const Plan& pl = c->pl;
+    Phys<R> ph = make_phys<R>(pl, p);
+    const bool demag = (p->terms & MAGX_DEMAG) != 0;
+    void* X1 = bptr(ws, pl.off_x1);
+    R* xi5 = reinterpret_cast<R*>(bptr(ws, pl.off_f[0]));
+    R* kap = reinterpret_cast<R*>(bptr(ws, pl.off_f[1]));
+    R* mub[2] = {reinterpret_cast<R*>(bptr(ws, pl.off_f[2])), reinterpret_cast<R*>(bptr(ws, pl.off_f[3]))};
+    double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
+    TapeView<R> tv{const_cast<R*>(tape), pl.ncell, nsteps};
+    // per-block double partials of dL/dH_bias; a checkpointed rollout keeps
+    // them across segments so the summation order does not depend on ckpt
+    if (fresh && launch_fill_zero(part, (long long)pl.pencil_blocks * 8, s) != hipSuccess) return MAGX_EHIP;
+    for (int n = nsteps - 1; n >= 0; --n) {
+        StartArgs<R> sa{};
+        sa.gm = gm;
+        sa.y5 = tv.y(n, 5);
+        sa.nx5 = tv.nx(n, 5);
+        sa.y4 = tv.y(n, 4);
+        sa.xi5 = xi5;
+        sa.kap = kap;
+        sa.muout = mub[0];
+        sa.dt = (R)dt;
+        {
+            ProfScope ps(c, kProfBstart, s);
+            if (launch_bstart<R>(pl, ph, X1, sa, part, s) != hipSuccess) return MAGX_EHIP;
+        }
+        for (int st = 4; st >= 1; --st) {
+            if (demag) {
+                int rc = conv_passes<R>(c, ws, ph.Ms, s);
+                if (rc) return rc;
+            }
+            BackArgs<R> ba{};
+            ba.mu = mub[st % 2];
+            ba.ys = tv.y(n, st);
+            ba.Hs = tv.H(n, st);
+            ba.kap = kap;
+            ba.xi5 = xi5;
+            ba.nxs = st >= 2 ? tv.nx(n, st) : nullptr;
+            ba.yprev = st >= 2 ? tv.y(n, st - 1) : nullptr;
+            ba.gm = gm;
+            ba.muout = mub[(st - 1) % 2];
+            ba.stage = st;
+            ba.dt = (R)dt;
+            ProfScope ps(c, kProfBstage, s);
+            if (launch_bstage<R>(pl, ph, X1, X1, ba, part, s) != hipSuccess) return MAGX_EHIP;
+        }
+    }
+    if (finish && (p->terms & MAGX_ZEEMAN)) {
+        if (launch_reduce_partials<R>(part, pl.pencil_blocks, 3, gHbias, fresh ? 1 : 0, s) != hipSuccess)
+            return MAGX_EHIP;
+    }
+    return MAGX_OK;
+}
+
+template <typename R>
+static int do_heff_backward(magx_ctx* c, const R* gH, const magx_params* p, R* gm, R* gHbias, void* ws,
+                            hipStream_t s) {
+    const Plan& pl = c->pl;
+    Phys<R> ph = make_phys<R>(pl, p);
+    void* X1 = bptr(ws, pl.off_x1);
+    double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
+    if (launch_fill_zero(part, (long long)pl.pencil_blocks * 8, s) != hipSuccess) return MAGX_EHIP;
+    if (p->terms & MAGX_DEMAG) {
+        if (launch_xfwd<R>(pl, gH, X1, s) != hipSuccess) return MAGX_EHIP;
+        int rc = conv_passes<R>(c, ws, ph.Ms, s);
+        if (rc) return rc;
+    }
+    const int sum_input = (p->terms & MAGX_ZEEMAN) ? 1 : 0;
+    if (launch_field<R>(pl, ph, X1, gH, gm, 0, 0, sum_input, part, s) != hipSuccess) return MAGX_EHIP;
+    if (launch_reduce_partials<R>(part, pl.pencil_blocks, 3, gHbias, 0, s) != hipSuccess) return MAGX_EHIP;
+    return MAGX_OK;
+}
+
+}  // namespace magx
+
+// ---------------------------------------------------------------------------------
+extern "C" {
+
+int magx_sizes(const magx_grid* g, magx_dtype dt, magx_size_info* out) {
+    if (!out) return MAGX_EINVAL;
+    Plan pl;
+    int rc = make_plan(g, dt, &pl);
+    if (rc) return rc;
+    out->spectrum_bytes = pl.spectrum_bytes;
+    out->init_scratch_bytes = pl.scratch_bytes;
+    out->workspace_bytes = pl.ws_bytes;
+    out->tape_bytes_per_step = pl.tape_step_bytes;
+    out->tape_bytes_extra = pl.tape_extra_bytes;
+    out->field_bytes = pl.field_bytes;
+    return MAGX_OK;
+}
+
+int magx_tensor_init(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, void* spectrum, void* scratch,
+                     void* stream) {
+    if (!ctx) return MAGX_EINVAL;
+    *ctx = nullptr;
+    if (!spectrum || !scratch) return MAGX_EINVAL;
+    Plan pl;
+    int rc = make_plan(g, dt, &pl);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    rc = ensure_twiddles(s, &dev);
+    if (rc) return rc;
+    if (build_tensor_spectrum(pl, spectrum, scratch, s) != hipSuccess) return MAGX_EHIP;
+    magx_ctx* c = new (std::nothrow) magx_ctx;
+    if (!c) return MAGX_EINVAL;
+    c->pl = pl;
+    c->spectrum = spectrum;
+    c->heff_count = 0;
+    c->device = dev;
+    c->prof_kind = 0;
+    c->prof_used = 0;
+    *ctx = c;
+    return MAGX_OK;
+}
+
+int magx_heff(magx_ctx* ctx, const void* m, const magx_params* p, void* H, void* ws, void* stream) {
+    if (!ctx || !m || !H || !ws) return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->pl.dtype == MAGX_F32)
+        return do_heff<float>(ctx, static_cast<const float*>(m), p, static_cast<float*>(H), ws, s, 0, nullptr);
+    return do_heff<double>(ctx, static_cast<const double*>(m), p, static_cast<double*>(H), ws, s, 0, nullptr);
+}
+
+int magx_energy(magx_ctx* ctx, const void* m, const magx_params* p, void* e_out, void* ws, void* stream) {
+    if (!ctx || !m || !e_out || !ws) return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* e = static_cast<double*>(e_out);
+    if (ctx->pl.dtype == MAGX_F32)
+        return do_heff<float>(ctx, static_cast<const float*>(m), p, nullptr, ws, s, 1, e);
+    return do_heff<double>(ctx, static_cast<const double*>(m), p, nullptr, ws, s, 1, e);
+}
+
+int magx_llg_rhs(magx_ctx* ctx, const void* m, const void* H, const magx_params* p, void* dmdt, void* stream) {
+    if (!ctx || !m || !H || !dmdt) return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e;
+    if (ctx->pl.dtype == MAGX_F32)
+        e = launch_rhs<float>(ctx->pl, make_phys<float>(ctx->pl, p), static_cast<const float*>(m),
+                              static_cast<const float*>(H), static_cast<float*>(dmdt), s);
+    else
+        e = launch_rhs<double>(ctx->pl, make_phys<double>(ctx->pl, p), static_cast<const double*>(m),
+                               static_cast<const double*>(H), static_cast<double*>(dmdt), s);
+    return e == hipSuccess ? MAGX_OK : MAGX_EHIP;
+}
+
+int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps, void* tape, void* ws,
+              void* stream) {
+    if (!ctx || !m || !ws || nsteps < 0 || !std::isfinite(dt)) return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (nsteps == 0) return MAGX_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->pl.dtype == MAGX_F32)
+        return do_step<float>(ctx, static_cast<float*>(m), p, dt, nsteps, static_cast<float*>(tape), ws, s);
+    return do_step<double>(ctx, static_cast<double*>(m), p, dt, nsteps, static_cast<double*>(tape), ws, s);
+}
+
+int magx_heff_backward(magx_ctx* ctx, const void* gH, const magx_params* p, void* gm, void* gHbias, void* ws,
+                       void* stream) {
+    if (!ctx || !gH || !gm || !gHbias || !ws) return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->pl.dtype == MAGX_F32)
+        return do_heff_backward<float>(ctx, static_cast<const float*>(gH), p, static_cast<float*>(gm),
+                                       static_cast<float*>(gHbias), ws, s);
+    return do_heff_backward<double>(ctx, static_cast<const double*>(gH), p, static_cast<double*>(gm),
+                                    static_cast<double*>(gHbias), ws, s);
+}
+
+int magx_step_backward(magx_ctx* ctx, const void* tape, int nsteps, const magx_params* p, double dt, void* gm,
+                       void* gHbias, void* ws, void* stream) {
+    if (!ctx || !tape || !gm || !gHbias || !ws || nsteps < 0 || !std::isfinite(dt)) return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (nsteps == 0) return MAGX_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->pl.dtype == MAGX_F32)
+        return do_step_backward<float>(ctx, static_cast<const float*>(tape), nsteps, p, dt,
+                                       static_cast<float*>(gm), static_cast<float*>(gHbias), ws, s);
+    return do_step_backward<double>(ctx, static_cast<const double*>(tape), nsteps, p, dt, static_cast<double*>(gm),
+                                    static_cast<double*>(gHbias), ws, s);
+}
+
+int magx_rollout_forward(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps, int ckpt,
+                         void* ckpt_store, void* ws, void* stream) {
+    if (!ctx || !m || !ckpt_store || !ws || nsteps < 0 || ckpt < 1 || !std::isfinite(dt)) return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t fb = ctx->pl.field_bytes;
+    const long long n3 = 3 * ctx->pl.ncell;
+    for (int n0 = 0, seg = 0; n0 < nsteps; n0 += ckpt, ++seg) {
+        void* slot = bptr(ckpt_store, (size_t)seg * fb);
+        hipError_t e = ctx->pl.dtype == MAGX_F32
+                           ? launch_copy<float>(static_cast<const float*>(m), static_cast<float*>(slot), n3, s)
+                           : launch_copy<double>(static_cast<const double*>(m), static_cast<double*>(slot), n3, s);
+        if (e != hipSuccess) return MAGX_EHIP;
+        rc = magx_step(ctx, m, p, dt, std::min(ckpt, nsteps - n0), nullptr, ws, stream);
+        if (rc) return rc;
+    }
+    return MAGX_OK;
+}
+
+int magx_rollout_backward(magx_ctx* ctx, const void* ckpt_store, const magx_params* p, double dt, int nsteps,
+                          int ckpt, void* gm, void* gHbias, void* tape, void* mwork, void* ws, void* stream) {
+    if (!ctx || !ckpt_store || !gm || !gHbias || !tape || !mwork || !ws || nsteps < 0 || ckpt < 1 ||
+        !std::isfinite(dt))
+        return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const Plan& pl = ctx->pl;
+    double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
+    if (launch_fill_zero(part, (long long)pl.pencil_blocks * 8, s) != hipSuccess) return MAGX_EHIP;
+    hipError_t e;
+    const size_t fb = pl.field_bytes;
+    const long long n3 = 3 * pl.ncell;
+    const int nseg = nsteps == 0 ? 0 : (nsteps + ckpt - 1) / ckpt;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int n0 = seg * ckpt;
+        const int len = std::min(ckpt, nsteps - n0);
+        const void* slot = bptr(const_cast<void*>(ckpt_store), (size_t)seg * fb);
+        e = pl.dtype == MAGX_F32
+                ? launch_copy<float>(static_cast<const float*>(slot), static_cast<float*>(mwork), n3, s)
+                : launch_copy<double>(static_cast<const double*>(slot), static_cast<double*>(mwork), n3, s);
+        if (e != hipSuccess) return MAGX_EHIP;
+        rc = magx_step(ctx, mwork, p, dt, len, tape, ws, stream);
+        if (rc) return rc;
+        rc = pl.dtype == MAGX_F32
+                 ? do_step_backward<float>(ctx, static_cast<const float*>(tape), len, p, dt, static_cast<float*>(gm),
+                                           static_cast<float*>(gHbias), ws, s, false, false)
+                 : do_step_backward<double>(ctx, static_cast<const double*>(tape), len, p, dt,
+                                            static_cast<double*>(gm), static_cast<double*>(gHbias), ws, s, false,
+                                            false);
+        if (rc) return rc;
+    }
+    // gHbias = sum over blocks of the partials (0 without a Zeeman term)
+    e = pl.dtype == MAGX_F32
+            ? launch_reduce_partials<float>(part, pl.pencil_blocks, 3, static_cast<float*>(gHbias), 0, s)
+            : launch_reduce_partials<double>(part, pl.pencil_blocks, 3, static_cast<double*>(gHbias), 0, s);
+    return e == hipSuccess ? MAGX_OK : MAGX_EHIP;
+}
+
+long long magx_heff_count(const magx_ctx* ctx) { return ctx ? ctx->heff_count : -1; }
+
+int magx_ctx_info(const magx_ctx* ctx, magx_grid* g, magx_dtype* dt) {
+    if (!ctx || !g || !dt) return MAGX_EINVAL;
+    g->nx = ctx->pl.nx; g->ny = ctx->pl.ny; g->nz = ctx->pl.nz;
+    g->dx = ctx->pl.dx; g->dy = ctx->pl.dy; g->dz = ctx->pl.dz;
+    *dt = ctx->pl.dtype;
+    return MAGX_OK;
+}
+
+const char* magx_strerror(int code) {
+    switch (code) {
+        case MAGX_OK: return "ok";
+        case MAGX_EINVAL: return "invalid argument";
+        case MAGX_ESIZE: return "grid too large for the FFT passes";
+        case MAGX_EDTYPE: return "unknown element type";
+        case MAGX_EWORKSPACE: return "buffer too small";
+        case MAGX_EHIP: return "HIP error";
+        case MAGX_ENONFINITE: return "non-finite value";
+        case MAGX_ESTATE: return "context has no demag tensor";
+        default: return "unknown error";
+    }
+}
+
+int magx_profile_start(magx_ctx* ctx, int kind) {
+    if (!ctx || kind < 0 || kind > kProfBstage) return MAGX_EINVAL;
+    ctx->prof_kind = kind;
+    ctx->prof_used = 0;
+    return MAGX_OK;
+}
+
+int magx_profile_stop(magx_ctx* ctx, long long* launches, double* total_ms) {
+    if (!ctx || !launches || !total_ms) return MAGX_EINVAL;
+    double tot = 0.0;
+    for (size_t i = 0; i < ctx->prof_used; ++i) {
+        auto& ev = ctx->prof_events[i];
+        if (hipEventSynchronize(ev.second) != hipSuccess) return MAGX_EHIP;
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, ev.first, ev.second) != hipSuccess) return MAGX_EHIP;
+        tot += ms;
+    }
+    *launches = (long long)ctx->prof_used;
+    *total_ms = tot;
+    ctx->prof_kind = 0;
+    ctx->prof_used = 0;
+    return MAGX_OK;
+}
+
+void magx_destroy(magx_ctx* ctx) {
+    if (!ctx) return;
+    for (auto& ev : ctx->prof_events) {
+        (void)hipEventDestroy(ev.first);
+        (void)hipEventDestroy(ev.second);
+    }
+    delete ctx;
+}
+
+}  // extern "C"

@@ -1,0 +1,710 @@
+// x-direction passes of the demag convolution fused with everything that is
+// local to a cell (Section II-A/II-B, Eqs. (1), (2), (5), (7), (9), (10)).
+//
+// A block owns np "pencils" (z, y) and all three components of each: 3*np
+// x lines.  The real transform of length Px = 2^k (>= 2 nx, zero padded) is
+// done as a complex FFT of length Lh = Px/2 on z[n] = x[2n] + i x[2n+1] plus
+// the usual split/merge step, so each thread slot owns a PAIR of cells
+// (2n, 2n+1) and LDS line entries are written whole.
+//
+// Kernels
+//  xfwd    r2c of a field (first forward x pass of a step)
+//  field   c2r of the demag spectrum + exchange/DMI/anisotropy/Zeeman -> H_eff,
+//          or per-block energy sums, or K applied to a cotangent
+//  stage   one RK4 stage: H_eff(y_s) -> k_s = R(y_s) -> accumulator, next
+//          stage input (renormalised) -> its r2c for the next convolution
+//  bstart  reverse of the step's final combination and renormalisation
+//  bstage  reverse of one stage: K mu_s + pointwise Jacobian-transpose terms
+//
+// Boundary condition (Eq. (10) with the outward normal n): one ghost per face,
+// m_ghost = m_b + h (-D/2A) (e_z x n) x m_b, shared by the exchange and DMI
+// stencils; on z faces and without DMI it is plain zero-flux Neumann.
+#include "magx_internal.hpp"
+
+namespace magx {
+
+template <typename R> constexpr int pemax() { return sizeof(R) == 4 ? 32 : 16; }
+constexpr int kMaxSlot = 8;   // (pair-of-cells) slots per thread: np * Lh <= 2048
+
+struct PG {
+    int nx, ny, nz, Lh, lgLh, Hx, Sx, lgPx, np, npen_total;
+    long long N;
+};
+
+static PG make_pg(const Plan& pl) {
+    PG g;
+    g.nx = pl.nx; g.ny = pl.ny; g.nz = pl.nz;
+    g.Lh = pl.Lh; g.lgLh = pl.lgLh; g.Hx = pl.Hx; g.Sx = pl.Sx; g.lgPx = pl.lgPx;
+    g.np = pl.np; g.npen_total = pl.ny * pl.nz; g.N = pl.ncell;
+    return g;
+}
+
+template <typename R>
+__device__ __forceinline__ void load3(const R* __restrict__ f, long long N, long long id, R v[3]) {
+    v[0] = f[id];
+    v[1] = f[N + id];
+    v[2] = f[2 * N + id];
+}
+
+template <typename R>
+__device__ __forceinline__ void store3(R* __restrict__ f, long long N, long long id, const R v[3]) {
+    f[id] = v[0];
+    f[N + id] = v[1];
+    f[2 * N + id] = v[2];
+}
+
+// Exchange, DMI and anisotropy fields of the linear field f at cell (x,y,z).
+template <typename R>
+__device__ __forceinline__ void local_field(const R* __restrict__ f, const PG& g, int x, int y, int z,
+                                            const Phys<R>& ph, R m[3], R hex[3], R hdmi[3], R hani[3]) {
+    const long long N = g.N;
+    const long long id = ((long long)z * g.ny + y) * g.nx + x;
+    load3(f, N, id, m);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) hex[c] = hdmi[c] = hani[c] = (R)0;
+    if (ph.terms & (MAGX_EXCH | MAGX_DMI)) {
+        R xp[3], xm[3], yp[3], ym[3], zp[3], zm[3];
+        const R kdx = ph.kap * ph.dx, kdy = ph.kap * ph.dy;
+        if (x + 1 < g.nx) load3(f, N, id + 1, xp);
+        else { xp[0] = m[0] + kdx * m[2]; xp[1] = m[1]; xp[2] = m[2] - kdx * m[0]; }
+        if (x > 0) load3(f, N, id - 1, xm);
+        else { xm[0] = m[0] - kdx * m[2]; xm[1] = m[1]; xm[2] = m[2] + kdx * m[0]; }
+        if (y + 1 < g.ny) load3(f, N, id + g.nx, yp);
+        else { yp[0] = m[0]; yp[1] = m[1] + kdy * m[2]; yp[2] = m[2] - kdy * m[1]; }
+        if (y > 0) load3(f, N, id - g.nx, ym);
+        else { ym[0] = m[0]; ym[1] = m[1] - kdy * m[2]; ym[2] = m[2] + kdy * m[1]; }
+        const long long pz = (long long)g.nx * g.ny;
+        if (z + 1 < g.nz) load3(f, N, id + pz, zp);
+        else { zp[0] = m[0]; zp[1] = m[1]; zp[2] = m[2]; }
+        if (z > 0) load3(f, N, id - pz, zm);
+        else { zm[0] = m[0]; zm[1] = m[1]; zm[2] = m[2]; }
+        if (ph.terms & MAGX_EXCH) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const R m2 = (R)2 * m[c];
+                hex[c] = ph.cex * ((xp[c] - m2 + xm[c]) * ph.idx2 + (yp[c] - m2 + ym[c]) * ph.idy2 +
+                                   (zp[c] - m2 + zm[c]) * ph.idz2);
+            }
+        }
+        if (ph.terms & MAGX_DMI) {
+            hdmi[0] = ph.cdmi * (xp[2] - xm[2]) * ph.h2x;
+            hdmi[1] = ph.cdmi * (yp[2] - ym[2]) * ph.h2y;
+            hdmi[2] = -ph.cdmi * ((xp[0] - xm[0]) * ph.h2x + (yp[1] - ym[1]) * ph.h2y);
+        }
+    }
+    if (ph.terms & MAGX_ANIS) {
+        const R pr = m[0] * ph.eK[0] + m[1] * ph.eK[1] + m[2] * ph.eK[2];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) hani[c] = ph.cani * pr * ph.eK[c];
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void cross3(const R a[3], const R b[3], R o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <typename R> __device__ __forceinline__ R dot3(const R a[3], const R b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Eq. (1) for unit m: a [m x H + alpha m x (m x H)].
+template <typename R>
+__device__ __forceinline__ void llg_rhs(const R m[3], const R H[3], R a, R alpha, R k[3]) {
+    R mxH[3], mmH[3];
+    cross3(m, H, mxH);
+    cross3(m, mxH, mmH);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) k[c] = a * (mxH[c] + alpha * mmH[c]);
+}
+
+// Cotangent of H for a cotangent kappa of R(y): a [kappa x y + alpha y x (y x kappa)].
+template <typename R>
+__device__ __forceinline__ void rhs_mu(const R y[3], const R kap[3], R a, R alpha, R mu[3]) {
+    R kxy[3], yxk[3], yyk[3];
+    cross3(kap, y, kxy);
+    cross3(y, kap, yxk);
+    cross3(y, yxk, yyk);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mu[c] = a * (kxy[c] + alpha * yyk[c]);
+}
+
+// ---- x-line transforms in LDS --------------------------------------------------
+// LDS line for (pencil p, component c) starts at (3p + c) * Lh.
+
+template <typename R>
+__device__ __forceinline__ void pen_coords(const PG& g, int pen, int& y, int& z) {
+    z = pen / g.ny;
+    y = pen - z * g.ny;
+}
+
+// Inverse x pass: Y1 rows -> real lines; afterwards the real value of cell x
+// of line l is buf[l*Lh + x/2].x (x even) or .y (x odd).
+template <typename R>
+__device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int pen0, int npen) {
+    const int Lh = g.Lh;
+    const int twsh = kTwLog - g.lgPx;
+    for (int e = threadIdx.x; e < npen * 3 * Lh; e += kNT) {
+        const int line = e >> g.lgLh, k = e & (Lh - 1);
+        const int p = line / 3, c = line - 3 * p;
+        int y, z;
+        pen_coords<R>(g, pen0 + p, y, z);
+        const cx<R>* row = Y1 + (((long long)c * g.nz + z) * g.ny + y) * g.Sx;
+        const cx<R> a = row[k];
+        const cx<R> b = cconj<R>(row[Lh - k]);
+        const cx<R> A = cadd<R>(a, b);
+        const cx<R> B = cmul<R>(csub<R>(a, b), cconj<R>(tw_fwd<R>(k << twsh)));
+        buf[e] = mk<R>(A.x - B.y, A.y + B.x);
+    }
+    lds_fft<R, true, pemax<R>()>(buf, g.lgLh, npen * 3, Lh, 1, false);
+}
+
+// Forward x pass: buf holds packed lines z[n] = x[2n] + i x[2n+1]; writes the
+// Hx-column half spectrum of every line to X1.
+template <typename R>
+__device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int pen0, int npen) {
+    const int Lh = g.Lh;
+    const int twsh = kTwLog - g.lgPx;
+    lds_fft<R, false, pemax<R>()>(buf, g.lgLh, npen * 3, Lh, 1, false);
+    const R half = (R)0.5;
+    for (int e = threadIdx.x; e < npen * 3 * g.Hx; e += kNT) {
+        const int line = e / g.Hx, k = e - line * g.Hx;
+        const int p = line / 3, c = line - 3 * p;
+        int y, z;
+        pen_coords<R>(g, pen0 + p, y, z);
+        const cx<R> Zk = buf[line * Lh + (k & (Lh - 1))];
+        const cx<R> Zm = cconj<R>(buf[line * Lh + ((Lh - k) & (Lh - 1))]);
+        const cx<R> E = cscale<R>(cadd<R>(Zk, Zm), half);
+        const cx<R> D = csub<R>(Zk, Zm);
+        const cx<R> O = mk<R>(half * D.y, -half * D.x);       // (Zk - Zm) / (2i)
+        const cx<R> X = cadd<R>(E, cmul<R>(tw_fwd<R>(k << twsh), O));
+        X1[(((long long)c * g.nz + z) * g.ny + y) * g.Sx + k] = X;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R demag_at(const cx<R>* buf, int line, int Lh, int n, int h) {
+    const cx<R> v = buf[line * Lh + n];
+    return h ? v.y : v.x;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kNT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// ---- kernels -------------------------------------------------------------------
+
+template <typename R>
+__global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R>* __restrict__ X1, PG g) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    const int pen0 = blockIdx.x * g.np;
+    const int npen = min(g.np, g.npen_total - pen0);
+    for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
+        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        int y, z;
+        pen_coords<R>(g, pen0 + p, y, z);
+        const long long row = ((long long)z * g.ny + y) * g.nx;
+        const int x0 = 2 * n, x1 = 2 * n + 1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R a = x0 < g.nx ? f[c * g.N + row + x0] : (R)0;
+            const R b = x1 < g.nx ? f[c * g.N + row + x1] : (R)0;
+            buf[(3 * p + c) * g.Lh + n] = mk<R>(a, b);
+        }
+    }
+    r2c_lines<R>(buf, X1, g, pen0, npen);
+}
+
+// mode: 0 -> write H (with bias if with_bias); 1 -> energy partials (m.H_term)
+template <typename R>
+__global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1, const R* __restrict__ f,
+                                                    R* __restrict__ H, PG g, Phys<R> ph, int has_demag,
+                                                    int with_bias, int energy, int sum_input,
+                                                    double* __restrict__ partials) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    __shared__ double red[kNT];
+    const int pen0 = blockIdx.x * g.np;
+    const int npen = min(g.np, g.npen_total - pen0);
+    if (has_demag) c2r_lines<R>(buf, Y1, g, pen0, npen);
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
+        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        int y, z;
+        pen_coords<R>(g, pen0 + p, y, z);
+        for (int h = 0; h < 2; ++h) {
+            const int x = 2 * n + h;
+            if (x >= g.nx) break;
+            R m[3], hex[3], hdmi[3], hani[3], hd[3];
+            local_field<R>(f, g, x, y, z, ph, m, hex, hdmi, hani);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) hd[c] = has_demag ? demag_at<R>(buf, 3 * p + c, g.Lh, n, h) : (R)0;
+            const long long id = ((long long)z * g.ny + y) * g.nx + x;
+            if (energy) {
+                acc[0] += (double)dot3(m, hd);
+                acc[1] += (double)dot3(m, hex);
+                acc[2] += (double)dot3(m, hdmi);
+                acc[3] += (double)dot3(m, hani);
+                if (ph.terms & MAGX_ZEEMAN) acc[4] += (double)dot3(m, ph.hb);
+            } else {
+                R out[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    out[c] = hd[c] + hex[c] + hdmi[c] + hani[c];
+                    if (with_bias && (ph.terms & MAGX_ZEEMAN)) out[c] += ph.hb[c];
+                }
+                store3(H, g.N, id, out);
+                if (sum_input) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[c] += (double)m[c];
+                }
+            }
+        }
+    }
+    if (energy) {
+        for (int v = 0; v < 5; ++v) {
+            const double s = block_sum(acc[v], red);
+            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] = s;
+        }
+    } else if (sum_input) {
+        for (int v = 0; v < 3; ++v) {
+            const double s = block_sum(acc[v], red);
+            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] += s;
+        }
+    }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, PG g,
+                                                    Phys<R> ph, StageArgs<R> a, int has_demag) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    const int pen0 = blockIdx.x * g.np;
+    const int npen = min(g.np, g.npen_total - pen0);
+    if (has_demag) c2r_lines<R>(buf, Y1, g, pen0, npen);
+    // classical RK4 tableau
+    const R bw[4] = {(R)(1.0 / 6.0), (R)(1.0 / 3.0), (R)(1.0 / 3.0), (R)(1.0 / 6.0)};
+    const R cw[4] = {(R)0, (R)0.5, (R)0.5, (R)1};
+    const int s = a.stage;
+    const bool norm = (s < 4) ? (ph.renorm == 2) : (ph.renorm >= 1);
+    R keep[kMaxSlot][2][3];
+#pragma unroll
+    for (int i = 0; i < kMaxSlot; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e >= npen * g.Lh) continue;
+        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        int y, z;
+        pen_coords<R>(g, pen0 + p, y, z);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int x = 2 * n + h;
+            keep[i][h][0] = keep[i][h][1] = keep[i][h][2] = (R)0;
+            if (x >= g.nx) continue;
+            R ys[3], hex[3], hdmi[3], hani[3], H[3], k[3];
+            local_field<R>(a.yin, g, x, y, z, ph, ys, hex, hdmi, hani);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                H[c] = hex[c] + hdmi[c] + hani[c];
+                if (has_demag) H[c] += demag_at<R>(buf, 3 * p + c, g.Lh, n, h);
+                if (ph.terms & MAGX_ZEEMAN) H[c] += ph.hb[c];
+            }
+            const long long id = ((long long)z * g.ny + y) * g.nx + x;
+            if (a.tapeH) store3(a.tapeH, g.N, id, H);
+            if (a.tapeYin) store3(a.tapeYin, g.N, id, ys);
+            llg_rhs<R>(ys, H, ph.a, ph.alpha, k);
+            R mn[3];
+            if (s == 1) { mn[0] = ys[0]; mn[1] = ys[1]; mn[2] = ys[2]; }
+            else load3(a.mn, g.N, id, mn);
+            R xn[3];
+            if (s < 4) {
+                R acc[3];
+                if (s == 1) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[c] = bw[0] * k[c];
+                } else {
+                    load3(a.acc, g.N, id, acc);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) acc[c] += bw[s - 1] * k[c];
+                }
+                store3(a.acc, g.N, id, acc);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xn[c] = mn[c] + cw[s] * a.dt * k[c];
+            } else {
+                R acc[3];
+                load3(a.acc, g.N, id, acc);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xn[c] = mn[c] + a.dt * (acc[c] + bw[3] * k[c]);
+            }
+            R nrm = (R)1;
+            if (norm) {
+                nrm = sqrt(dot3(xn, xn));
+                if (nrm > (R)0) {
+                    const R inv = (R)1 / nrm;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) xn[c] *= inv;
+                }
+            }
+            if (a.tapeNx) a.tapeNx[id] = nrm;
+            store3(a.yout, g.N, id, xn);
+            if (a.yout2) store3(a.yout2, g.N, id, xn);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) keep[i][h][c] = xn[c];
+        }
+    }
+    if (!(a.want_next && has_demag)) return;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kMaxSlot; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e >= npen * g.Lh) continue;
+        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
+    }
+    r2c_lines<R>(buf, X1, g, pen0, npen);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG g, Phys<R> ph, StartArgs<R> a,
+                                                     int has_demag, double* __restrict__ partials) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    __shared__ double red[kNT];
+    const int pen0 = blockIdx.x * g.np;
+    const int npen = min(g.np, g.npen_total - pen0);
+    const bool norm = ph.renorm >= 1;
+    const R b4 = (R)(1.0 / 6.0);
+    double hs[3] = {0, 0, 0};
+    R keep[kMaxSlot][2][3];
+#pragma unroll
+    for (int i = 0; i < kMaxSlot; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e >= npen * g.Lh) continue;
+        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        int y, z;
+        pen_coords<R>(g, pen0 + p, y, z);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int x = 2 * n + h;
+            keep[i][h][0] = keep[i][h][1] = keep[i][h][2] = (R)0;
+            if (x >= g.nx) continue;
+            const long long id = ((long long)z * g.ny + y) * g.nx + x;
+            R lam[3], xi[3];
+            load3(a.gm, g.N, id, lam);
+            if (norm) {
+                R y5[3];
+                load3(a.y5, g.N, id, y5);
+                const R nx5 = a.nx5[id];
+                const R pl = dot3(y5, lam);
+                const R inv = nx5 > (R)0 ? (R)1 / nx5 : (R)1;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xi[c] = (lam[c] - y5[c] * pl) * inv;
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xi[c] = lam[c];
+            }
+            store3(a.xi5, g.N, id, xi);
+            store3(a.gm, g.N, id, xi);
+            R kap[3], y4[3], mu[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) kap[c] = b4 * a.dt * xi[c];
+            store3(a.kap, g.N, id, kap);
+            load3(a.y4, g.N, id, y4);
+            rhs_mu<R>(y4, kap, ph.a, ph.alpha, mu);
+            store3(a.muout, g.N, id, mu);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                hs[c] += (double)mu[c];
+                keep[i][h][c] = mu[c];
+            }
+        }
+    }
+    if (ph.terms & MAGX_ZEEMAN) {
+        for (int v = 0; v < 3; ++v) {
+            const double s = block_sum(hs[v], red);
+            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] += s;
+        }
+    }
+    if (!has_demag) return;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kMaxSlot; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e >= npen * g.Lh) continue;
+        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
+    }
+    r2c_lines<R>(buf, X1, g, pen0, npen);
+}
+
+template <typename R>
+__global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1, PG g,
+                                                     Phys<R> ph, BackArgs<R> a, int has_demag,
+                                                     double* __restrict__ partials) {
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    __shared__ double red[kNT];
+    const int pen0 = blockIdx.x * g.np;
+    const int npen = min(g.np, g.npen_total - pen0);
+    if (has_demag) c2r_lines<R>(buf, Y1, g, pen0, npen);
+    const R bw[4] = {(R)(1.0 / 6.0), (R)(1.0 / 3.0), (R)(1.0 / 3.0), (R)(1.0 / 6.0)};
+    const R cw[4] = {(R)0, (R)0.5, (R)0.5, (R)1};
+    const int s = a.stage;
+    const bool norm = ph.renorm == 2;
+    double hs[3] = {0, 0, 0};
+    R keep[kMaxSlot][2][3];
+#pragma unroll
+    for (int i = 0; i < kMaxSlot; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e >= npen * g.Lh) continue;
+        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        int y, z;
+        pen_coords<R>(g, pen0 + p, y, z);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int x = 2 * n + h;
+            keep[i][h][0] = keep[i][h][1] = keep[i][h][2] = (R)0;
+            if (x >= g.nx) continue;
+            const long long id = ((long long)z * g.ny + y) * g.nx + x;
+            R mu[3], hex[3], hdmi[3], hani[3], Kmu[3];
+            local_field<R>(a.mu, g, x, y, z, ph, mu, hex, hdmi, hani);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                Kmu[c] = hex[c] + hdmi[c] + hani[c];
+                if (has_demag) Kmu[c] += demag_at<R>(buf, 3 * p + c, g.Lh, n, h);
+            }
+            R ys[3], Hs[3], kap[3];
+            load3(a.ys, g.N, id, ys);
+            load3(a.Hs, g.N, id, Hs);
+            load3(a.kap, g.N, id, kap);
+            // ybar = a [H x kappa + alpha (H (y.kappa) + kappa (y.H) - 2 y (H.kappa))] + K mu
+            R Hxk[3], yb[3];
+            cross3(Hs, kap, Hxk);
+            const R yk = dot3(ys, kap), yH = dot3(ys, Hs), Hk = dot3(Hs, kap);
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                yb[c] = ph.a * (Hxk[c] + ph.alpha * (Hs[c] * yk + kap[c] * yH - (R)2 * ys[c] * Hk)) + Kmu[c];
+            R lam[3];
+            load3(a.gm, g.N, id, lam);
+            if (s > 1) {
+                R xi[3];
+                if (norm) {
+                    const R nxs = a.nxs[id];
+                    const R py = dot3(ys, yb);
+                    const R inv = nxs > (R)0 ? (R)1 / nxs : (R)1;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) xi[c] = (yb[c] - ys[c] * py) * inv;
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) xi[c] = yb[c];
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lam[c] += xi[c];
+                store3(a.gm, g.N, id, lam);
+                R x5[3], kp[3], yp[3], mup[3];
+                load3(a.xi5, g.N, id, x5);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) kp[c] = bw[s - 2] * a.dt * x5[c] + cw[s - 1] * a.dt * xi[c];
+                store3(a.kap, g.N, id, kp);
+                load3(a.yprev, g.N, id, yp);
+                rhs_mu<R>(yp, kp, ph.a, ph.alpha, mup);
+                store3(a.muout, g.N, id, mup);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    hs[c] += (double)mup[c];
+                    keep[i][h][c] = mup[c];
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lam[c] += yb[c];
+                store3(a.gm, g.N, id, lam);
+            }
+        }
+    }
+    if (s > 1 && (ph.terms & MAGX_ZEEMAN)) {
+        for (int v = 0; v < 3; ++v) {
+            const double sm = block_sum(hs[v], red);
+            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] += sm;
+        }
+    }
+    if (s == 1 || !has_demag) return;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kMaxSlot; ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e >= npen * g.Lh) continue;
+        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
+    }
+    r2c_lines<R>(buf, X1, g, pen0, npen);
+}
+
+template <typename R>
+__global__ void rhs_kernel(const R* __restrict__ m, const R* __restrict__ H, R* __restrict__ out, long long N,
+                           R a, R alpha) {
+    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (id >= N) return;
+    R mm[3], hh[3], k[3];
+    load3(m, N, id, mm);
+    load3(H, N, id, hh);
+    llg_rhs<R>(mm, hh, a, alpha, k);
+    store3(out, N, id, k);
+}
+
+__global__ void fill_zero_kernel(double* p, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+template <typename R>
+__global__ void reduce_partials_kernel(const double* __restrict__ partials, int nblocks, int nval, R* out,
+                                       int accumulate) {
+    __shared__ double red[kNT];
+    for (int v = 0; v < nval; ++v) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kNT) acc += partials[b * 8 + v];
+        const double s = block_sum(acc, red);
+        if (threadIdx.x == 0) out[v] = accumulate ? (R)((double)out[v] + s) : (R)s;
+    }
+}
+
+// e_out: demag, exch, dmi, anis, zeeman, total (J).  pref = -(mu0 Ms V)/2.
+__global__ void energy_finish_kernel(const double* __restrict__ partials, int nblocks, double pref,
+                                     double vku_total, double* e_out) {
+    __shared__ double red[kNT];
+    double e[5];
+    for (int v = 0; v < 5; ++v) {
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblocks; b += kNT) acc += partials[b * 8 + v];
+        e[v] = block_sum(acc, red);
+    }
+    if (threadIdx.x == 0) {
+        const double ed = pref * e[0], ee = pref * e[1], em = pref * e[2];
+        const double ea = pref * e[3] + vku_total, ez = 2.0 * pref * e[4];
+        e_out[0] = ed;
+        e_out[1] = ee;
+        e_out[2] = em;
+        e_out[3] = ea;
+        e_out[4] = ez;
+        e_out[5] = ed + ee + em + ea + ez;
+    }
+}
+
+template <typename R>
+__global__ void copy_kernel(const R* __restrict__ src, R* __restrict__ dst, long long n) {
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// ---- launchers -----------------------------------------------------------------
+static inline size_t pencil_lds(const Plan& pl) { return (size_t)3 * pl.np * pl.Lh * pl.esize * 2; }
+
+template <typename R>
+hipError_t launch_xfwd(const Plan& pl, const R* f, void* X1, hipStream_t s) {
+    hipLaunchKernelGGL(xfwd_kernel<R>, dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s, f,
+                       static_cast<cx<R>*>(X1), make_pg(pl));
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_field(const Plan& pl, const Phys<R>& ph, const void* Y1, const R* f, R* H, int with_bias,
+                        int energy, int sum_input, double* partials, hipStream_t s) {
+    const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
+    hipLaunchKernelGGL(field_kernel<R>, dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+                       static_cast<const cx<R>*>(Y1), f, H, make_pg(pl), ph, has_demag, with_bias, energy,
+                       sum_input, partials);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_stage(const Plan& pl, const Phys<R>& ph, const void* Y1, void* X1, const StageArgs<R>& a,
+                        hipStream_t s) {
+    const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
+    hipLaunchKernelGGL(stage_kernel<R>, dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+                       static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_bstart(const Plan& pl, const Phys<R>& ph, void* X1, const StartArgs<R>& a, double* partials,
+                         hipStream_t s) {
+    const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
+    hipLaunchKernelGGL(bstart_kernel<R>, dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+                       static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag, partials);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_bstage(const Plan& pl, const Phys<R>& ph, const void* Y1, void* X1, const BackArgs<R>& a,
+                         double* partials, hipStream_t s) {
+    const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
+    hipLaunchKernelGGL(bstage_kernel<R>, dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+                       static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag,
+                       partials);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_rhs(const Plan& pl, const Phys<R>& ph, const R* m, const R* H, R* out, hipStream_t s) {
+    const long long N = pl.ncell;
+    hipLaunchKernelGGL(rhs_kernel<R>, dim3((unsigned)((N + kNT - 1) / kNT)), dim3(kNT), 0, s, m, H, out, N, ph.a,
+                       ph.alpha);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_zero(double* p, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + kNT - 1) / kNT)), dim3(kNT), 0, s, p, n);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_reduce_partials(const double* partials, int nblocks, int nval, R* out, int accumulate,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials_kernel<R>, dim3(1), dim3(kNT), 0, s, partials, nblocks, nval, out,
+                       accumulate);
+    return hipGetLastError();
+}
+
+hipError_t launch_energy_finish(const double* partials, int nblocks, double pref, double vku_total,
+                                double* e_out, hipStream_t s) {
+    hipLaunchKernelGGL(energy_finish_kernel, dim3(1), dim3(kNT), 0, s, partials, nblocks, pref, vku_total, e_out);
+    return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_copy(const R* src, R* dst, long long n, hipStream_t s) {
+    hipLaunchKernelGGL(copy_kernel<R>, dim3((unsigned)((n + kNT - 1) / kNT)), dim3(kNT), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+#define MAGX_INST(R)                                                                                            \
+    template hipError_t launch_xfwd<R>(const Plan&, const R*, void*, hipStream_t);                               \
+    template hipError_t launch_field<R>(const Plan&, const Phys<R>&, const void*, const R*, R*, int, int, int,   \
+                                        double*, hipStream_t);                                                  \
+    template hipError_t launch_stage<R>(const Plan&, const Phys<R>&, const void*, void*, const StageArgs<R>&,   \
+                                        hipStream_t);                                                           \
+    template hipError_t launch_bstart<R>(const Plan&, const Phys<R>&, void*, const StartArgs<R>&, double*,      \
+                                         hipStream_t);                                                          \
+    template hipError_t launch_bstage<R>(const Plan&, const Phys<R>&, const void*, void*, const BackArgs<R>&,   \
+                                         double*, hipStream_t);                                                 \
+    template hipError_t launch_rhs<R>(const Plan&, const Phys<R>&, const R*, const R*, R*, hipStream_t);         \
+    template hipError_t launch_reduce_partials<R>(const double*, int, int, R*, int, hipStream_t);               \
+    template hipError_t launch_copy<R>(const R*, R*, long long, hipStream_t);
+
+MAGX_INST(float)
+MAGX_INST(double)
+
+}  // namespace magx

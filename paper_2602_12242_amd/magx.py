@@ -1,0 +1,318 @@
+"""ctypes binding of libmagx.so (argument marshalling only).
+
+Every computation happens in the library's HIP kernels; this module turns
+torch tensors into device pointers, passes torch's current HIP stream, and
+raises on a non-zero return code.  Device buffers (tensor spectrum, scratch,
+workspace, tapes) are torch allocations sized by magx_sizes().
+
+Entry points keep the C names: magx_sizes, magx_tensor_init, magx_heff,
+magx_llg_rhs, magx_step, magx_heff_backward, magx_step_backward,
+magx_rollout_forward, magx_rollout_backward, magx_energy.  `Context` wraps
+them with owned buffers; `heff` and `Rollout` are torch.autograd Functions.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmagx.so")
+
+DEMAG, EXCH, DMI, ANIS, ZEEMAN = 1, 2, 4, 8, 16
+F32, F64 = 0, 1
+
+ERRORS = {0: "ok", -1: "invalid argument", -2: "grid too large", -3: "unknown element type",
+          -4: "buffer too small", -5: "HIP error", -6: "non-finite value", -7: "no demag tensor"}
+
+
+class MagxError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {ERRORS.get(code, 'error')} ({code})")
+        self.code = code
+
+
+class magx_grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("dx", ctypes.c_double), ("dy", ctypes.c_double), ("dz", ctypes.c_double)]
+
+
+class magx_params(ctypes.Structure):
+    _fields_ = [("Ms", ctypes.c_double), ("A", ctypes.c_double), ("D", ctypes.c_double),
+                ("Ku", ctypes.c_double), ("eK", ctypes.c_double * 3), ("Hbias", ctypes.c_double * 3),
+                ("alpha", ctypes.c_double), ("gamma", ctypes.c_double), ("mu0", ctypes.c_double),
+                ("terms", ctypes.c_uint), ("renorm", ctypes.c_int), ("check_finite", ctypes.c_int)]
+
+
+class magx_size_info(ctypes.Structure):
+    _fields_ = [("spectrum_bytes", ctypes.c_size_t), ("init_scratch_bytes", ctypes.c_size_t),
+                ("workspace_bytes", ctypes.c_size_t), ("tape_bytes_per_step", ctypes.c_size_t),
+                ("tape_bytes_extra", ctypes.c_size_t), ("field_bytes", ctypes.c_size_t)]
+
+
+EXPORTS = ("magx_sizes", "magx_tensor_init", "magx_heff", "magx_llg_rhs", "magx_step",
+           "magx_heff_backward", "magx_step_backward", "magx_rollout_forward", "magx_rollout_backward",
+           "magx_energy", "magx_heff_count", "magx_ctx_info", "magx_profile_start", "magx_profile_stop",
+           "magx_strerror", "magx_destroy")
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Loads libmagx.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with `python -m paper_2602_12242_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i, d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+    P = ctypes.POINTER
+    sig = {
+        "magx_sizes": (i, [P(magx_grid), i, P(magx_size_info)]),
+        "magx_tensor_init": (i, [P(vp), P(magx_grid), i, vp, vp, vp]),
+        "magx_heff": (i, [vp, vp, P(magx_params), vp, vp, vp]),
+        "magx_llg_rhs": (i, [vp, vp, vp, P(magx_params), vp, vp]),
+        "magx_step": (i, [vp, vp, P(magx_params), d, i, vp, vp, vp]),
+        "magx_heff_backward": (i, [vp, vp, P(magx_params), vp, vp, vp, vp]),
+        "magx_step_backward": (i, [vp, vp, i, P(magx_params), d, vp, vp, vp, vp]),
+        "magx_rollout_forward": (i, [vp, vp, P(magx_params), d, i, i, vp, vp, vp]),
+        "magx_rollout_backward": (i, [vp, vp, P(magx_params), d, i, i, vp, vp, vp, vp, vp, vp]),
+        "magx_energy": (i, [vp, vp, P(magx_params), vp, vp, vp]),
+        "magx_heff_count": (ctypes.c_longlong, [vp]),
+        "magx_ctx_info": (i, [vp, P(magx_grid), P(ctypes.c_int)]),
+        "magx_profile_start": (i, [vp, i]),
+        "magx_profile_stop": (i, [vp, P(ctypes.c_longlong), P(ctypes.c_double)]),
+        "magx_strerror": (ctypes.c_char_p, [i]),
+        "magx_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise MagxError(rc, where)
+
+
+def make_grid(n, d):
+    return magx_grid(int(n[0]), int(n[1]), int(n[2]), float(d[0]), float(d[1]), float(d[2]))
+
+
+def make_params(Ms, A=0.0, D=0.0, Ku=0.0, eK=(0.0, 0.0, 1.0), Hbias=(0.0, 0.0, 0.0), alpha=0.0,
+                gamma=-1.759e11, mu0=4e-7 * 3.141592653589793, terms=31, renorm=2, check_finite=0, **_):
+    p = magx_params()
+    p.Ms, p.A, p.D, p.Ku = float(Ms), float(A), float(D), float(Ku)
+    for c in range(3):
+        p.eK[c] = float(eK[c])
+        p.Hbias[c] = float(Hbias[c])
+    p.alpha, p.gamma, p.mu0 = float(alpha), float(gamma), float(mu0)
+    p.terms, p.renorm, p.check_finite = int(terms), int(renorm), int(check_finite)
+    return p
+
+
+def magx_sizes(n, d, dtype=F32):
+    info = magx_size_info()
+    g = make_grid(n, d)
+    _check(load().magx_sizes(ctypes.byref(g), int(dtype), ctypes.byref(info)), "magx_sizes")
+    return {k: getattr(info, k) for k, _ in magx_size_info._fields_}
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _tdtype(dtype):
+    return torch.float32 if dtype == F32 else torch.float64
+
+
+class Context:
+    """A grid, its demag tensor spectrum and a workspace on one GPU."""
+
+    def __init__(self, n, d, dtype=F32, device="cuda"):
+        self.lib = load()
+        self.n = tuple(int(v) for v in n)
+        self.d = tuple(float(v) for v in d)
+        self.dtype = dtype
+        self.tdtype = _tdtype(dtype)
+        dev = torch.device(device)
+        if dev.type == "cuda" and dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        self.device = dev
+        self.sizes = magx_sizes(self.n, self.d, dtype)
+        self.shape = (3, self.n[2], self.n[1], self.n[0])
+        with torch.cuda.device(self.device):
+            self.spectrum = torch.empty(self.sizes["spectrum_bytes"], dtype=torch.uint8, device=self.device)
+            scratch = torch.empty(self.sizes["init_scratch_bytes"], dtype=torch.uint8, device=self.device)
+            self.ws = torch.empty(self.sizes["workspace_bytes"], dtype=torch.uint8, device=self.device)
+            h = ctypes.c_void_p()
+            g = make_grid(self.n, self.d)
+            _check(self.lib.magx_tensor_init(ctypes.byref(h), ctypes.byref(g), int(dtype), _ptr(self.spectrum),
+                                             _ptr(scratch), _stream()), "magx_tensor_init")
+            torch.cuda.current_stream().synchronize()
+            del scratch
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            self.lib.magx_destroy(h)
+            self.h = None
+
+    # -- helpers ---------------------------------------------------------------------------
+    def field(self):
+        return torch.empty(self.shape, dtype=self.tdtype, device=self.device)
+
+    def _chk(self, t, name):
+        if t.dtype != self.tdtype or not t.is_contiguous() or tuple(t.shape) != self.shape or t.device != self.device:
+            raise ValueError(f"{name}: expected contiguous {self.tdtype} {self.shape} on {self.device}")
+
+    def spectrum_array(self):
+        """The stored tensor spectrum as a (6, Hz, Hy, Sx) view (for tests)."""
+        nx, ny, nz = self.n
+        Px, Py, Pz = (max(2, 1 << (2 * v - 1).bit_length()) for v in (nx, ny, nz))
+        Hx, Hy, Hz = Px // 2 + 1, Py // 2 + 1, Pz // 2 + 1
+        Sx = (Hx + 15) // 16 * 16
+        el = self.spectrum.view(self.tdtype)
+        return el[: 6 * Hz * Hy * Sx].view(6, Hz, Hy, Sx)[..., :Hx], (Px, Py, Pz)
+
+    @property
+    def heff_count(self):
+        return int(self.lib.magx_heff_count(self.h))
+
+    # -- entry points ------------------------------------------------------------------------
+    def heff(self, m, p, out=None):
+        self._chk(m, "m")
+        H = self.field() if out is None else out
+        _check(self.lib.magx_heff(self.h, _ptr(m), ctypes.byref(p), _ptr(H), _ptr(self.ws), _stream()),
+               "magx_heff")
+        return H
+
+    def llg_rhs(self, m, H, p, out=None):
+        self._chk(m, "m")
+        self._chk(H, "H")
+        k = self.field() if out is None else out
+        _check(self.lib.magx_llg_rhs(self.h, _ptr(m), _ptr(H), ctypes.byref(p), _ptr(k), _stream()),
+               "magx_llg_rhs")
+        return k
+
+    def tape(self, nsteps):
+        nbytes = nsteps * self.sizes["tape_bytes_per_step"] + self.sizes["tape_bytes_extra"]
+        return torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+
+    def step(self, m, p, dt, nsteps, tape=None):
+        """Advances m in place by nsteps RK4 steps."""
+        self._chk(m, "m")
+        _check(self.lib.magx_step(self.h, _ptr(m), ctypes.byref(p), float(dt), int(nsteps), _ptr(tape),
+                                  _ptr(self.ws), _stream()), "magx_step")
+        return m
+
+    def heff_backward(self, gH, p):
+        self._chk(gH, "gH")
+        gm = self.field()
+        gh = torch.empty(3, dtype=self.tdtype, device=self.device)
+        _check(self.lib.magx_heff_backward(self.h, _ptr(gH), ctypes.byref(p), _ptr(gm), _ptr(gh), _ptr(self.ws),
+                                           _stream()), "magx_heff_backward")
+        return gm, gh
+
+    def step_backward(self, tape, nsteps, p, dt, gm, gHbias):
+        """gm: cotangent of the final state in, of the initial state out (in place);
+        gHbias (3,) is incremented."""
+        self._chk(gm, "gm")
+        _check(self.lib.magx_step_backward(self.h, _ptr(tape), int(nsteps), ctypes.byref(p), float(dt), _ptr(gm),
+                                           _ptr(gHbias), _ptr(self.ws), _stream()), "magx_step_backward")
+        return gm, gHbias
+
+    def checkpoint_store(self, nsteps, ckpt):
+        nseg = max(1, -(-nsteps // ckpt))
+        return torch.empty((nseg,) + self.shape, dtype=self.tdtype, device=self.device)
+
+    def rollout_forward(self, m, p, dt, nsteps, ckpt, store):
+        self._chk(m, "m")
+        _check(self.lib.magx_rollout_forward(self.h, _ptr(m), ctypes.byref(p), float(dt), int(nsteps), int(ckpt),
+                                             _ptr(store), _ptr(self.ws), _stream()), "magx_rollout_forward")
+        return m
+
+    def rollout_backward(self, store, p, dt, nsteps, ckpt, gm, tape=None, mwork=None):
+        self._chk(gm, "gm")
+        tape = self.tape(ckpt) if tape is None else tape
+        mwork = self.field() if mwork is None else mwork
+        gh = torch.empty(3, dtype=self.tdtype, device=self.device)
+        _check(self.lib.magx_rollout_backward(self.h, _ptr(store), ctypes.byref(p), float(dt), int(nsteps),
+                                              int(ckpt), _ptr(gm), _ptr(gh), _ptr(tape), _ptr(mwork),
+                                              _ptr(self.ws), _stream()), "magx_rollout_backward")
+        return gm, gh
+
+    PROFILE_KINDS = {"xfwd": 1, "yfwd": 2, "zconv": 3, "yinv": 4, "stage": 5, "field": 6, "bstart": 7,
+                     "bstage": 8}
+
+    def profile_start(self, kind):
+        _check(self.lib.magx_profile_start(self.h, self.PROFILE_KINDS[kind]), "magx_profile_start")
+
+    def profile_stop(self):
+        n = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        _check(self.lib.magx_profile_stop(self.h, ctypes.byref(n), ctypes.byref(ms)), "magx_profile_stop")
+        return int(n.value), float(ms.value)
+
+    def energy(self, m, p):
+        self._chk(m, "m")
+        e = torch.empty(6, dtype=torch.float64, device=self.device)
+        _check(self.lib.magx_energy(self.h, _ptr(m), ctypes.byref(p), _ptr(e), _ptr(self.ws), _stream()),
+               "magx_energy")
+        return e
+
+
+def _with_bias(p, h):
+    q = magx_params()
+    ctypes.pointer(q)[0] = p
+    for c in range(3):
+        q.Hbias[c] = float(h[c])
+    return q
+
+
+class HeffFunction(torch.autograd.Function):
+    """H = H_eff(m; H_bias) with the hand-written reverse mode."""
+
+    @staticmethod
+    def forward(ctx, m, hbias, context, p):
+        q = _with_bias(p, hbias.detach().cpu().tolist())
+        ctx.context, ctx.p = context, q
+        return context.heff(m.contiguous(), q)
+
+    @staticmethod
+    def backward(ctx, gH):
+        gm, gh = ctx.context.heff_backward(gH.contiguous(), ctx.p)
+        return gm, gh, None, None
+
+
+def heff(m, hbias, context, p):
+    return HeffFunction.apply(m, hbias, context, p)
+
+
+class Rollout(torch.autograd.Function):
+    """m_T = nsteps RK4 steps from m0 with bias field hbias; the reverse pass
+    re-runs checkpointed segments with a tape and reverses them."""
+
+    @staticmethod
+    def forward(ctx, m0, hbias, context, p, dt, nsteps, ckpt):
+        q = _with_bias(p, hbias.detach().cpu().tolist())
+        m = m0.detach().clone().contiguous()
+        store = context.checkpoint_store(nsteps, ckpt)
+        context.rollout_forward(m, q, dt, nsteps, ckpt, store)
+        ctx.context, ctx.p, ctx.dt, ctx.nsteps, ctx.ckpt = context, q, dt, nsteps, ckpt
+        ctx.store = store
+        return m
+
+    @staticmethod
+    def backward(ctx, gmT):
+        gm = gmT.detach().clone().contiguous()
+        gm, gh = ctx.context.rollout_backward(ctx.store, ctx.p, ctx.dt, ctx.nsteps, ctx.ckpt, gm)
+        return gm, gh, None, None, None, None, None
