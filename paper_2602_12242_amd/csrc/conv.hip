@@ -28,19 +28,16 @@ __global__ void __launch_bounds__(kNT) yfwd_kernel(const cx<R>* __restrict__ X1,
     const cx<R>* src = X1 + plane * ny * (long long)Sx;
     cx<R>* dst = X2 + plane * Py * (long long)Sx;
     const cx<R> zero = mk<R>(0, 0);
-    for (int e = threadIdx.x; e < (Py << lgT); e += kNT) {
-        const int row = e >> lgT, col = e & (T - 1);
-        const int kx = kx0 + col;
-        cx<R> v = zero;
-        if (row < ny && kx < Hx) v = src[(long long)row * Sx + kx];
-        buf[e] = v;
-    }
-    lds_fft<R, false, emax<R>()>(buf, lgPy, T, 1, T, true);
-    for (int e = threadIdx.x; e < (Py << lgT); e += kNT) {
-        const int row = e >> lgT, col = e & (T - 1);
-        const int kx = kx0 + col;
-        if (kx < Hx) dst[(long long)row * Sx + kx] = buf[e];
-    }
+    // sequence b = column kx0 + b; rows >= ny are the zero padding, never read
+    auto load = [&](int b, int j) -> cx<R> {
+        const int kx = kx0 + b;
+        return (j < ny && kx < Hx) ? src[(long long)j * Sx + kx] : zero;
+    };
+    auto store = [&](int b, int j, cx<R> v) {
+        const int kx = kx0 + b;
+        if (kx < Hx) dst[(long long)j * Sx + kx] = v;
+    };
+    fft_io<R, false, emax<R>(), false, false>(buf, lgPy, T, 1, T, true, load, store);
 }
 
 template <typename R>
@@ -56,17 +53,16 @@ __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2,
     const cx<R>* src = X2 + plane * Py * (long long)Sx;
     cx<R>* dst = Y1 + plane * ny * (long long)Sx;
     const cx<R> zero = mk<R>(0, 0);
-    for (int e = threadIdx.x; e < (Py << lgT); e += kNT) {
-        const int row = e >> lgT, col = e & (T - 1);
-        const int kx = kx0 + col;
-        buf[e] = kx < Hx ? src[(long long)row * Sx + kx] : zero;
-    }
-    lds_fft<R, true, emax<R>()>(buf, lgPy, T, 1, T, true);
-    for (int e = threadIdx.x; e < (ny << lgT); e += kNT) {
-        const int row = e >> lgT, col = e & (T - 1);
-        const int kx = kx0 + col;
-        if (kx < Hx) dst[(long long)row * Sx + kx] = buf[e];
-    }
+    auto load = [&](int b, int j) -> cx<R> {
+        const int kx = kx0 + b;
+        return kx < Hx ? src[(long long)j * Sx + kx] : zero;
+    };
+    // rows inside the box only
+    auto store = [&](int b, int j, cx<R> v) {
+        const int kx = kx0 + b;
+        if (j < ny && kx < Hx) dst[(long long)j * Sx + kx] = v;
+    };
+    fft_io<R, true, emax<R>(), false, false>(buf, lgPy, T, 1, T, true, load, store);
 }
 
 // LDS layout: element (z, c, col) at (z * 3 + c) * T + col, i.e. sequence
@@ -87,15 +83,18 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     const long long comp_stride = (long long)nz * plane_stride;
     cx<R>* base = X2 + (long long)ky * Sx;
     const cx<R> zero = mk<R>(0, 0);
-    for (int e = threadIdx.x; e < Pz * T3; e += kNT) {
-        const int z = e / T3, r = e - z * T3;
-        const int c = r >> lgT, col = r & (T - 1);
-        const int kx = kx0 + col;
-        cx<R> v = zero;
-        if (z < nz && kx < Hx) v = base[c * comp_stride + z * plane_stride + kx];
-        buf[e] = v;
-    }
-    lds_fft<R, false, emax<R>()>(buf, lgPz, T3, 1, T3, true);
+    // rows z >= nz are the zero padding (never read) and are never written back
+    auto load = [&](int b, int j) -> cx<R> {
+        const int c = b >> lgT, kx = kx0 + (b & (T - 1));
+        return (j < nz && kx < Hx) ? base[c * comp_stride + j * plane_stride + kx] : zero;
+    };
+    auto store = [&](int b, int j, cx<R> v) {
+        const int c = b >> lgT, kx = kx0 + (b & (T - 1));
+        if (j < nz && kx < Hx) base[c * comp_stride + j * plane_stride + kx] = v;
+    };
+    auto none_load = [&](int, int) -> cx<R> { return zero; };
+    auto none_store = [&](int, int, cx<R>) {};
+    fft_io<R, false, emax<R>(), false, true>(buf, lgPz, T3, 1, T3, true, load, none_store);
     // pointwise 3x3 symmetric product with the real spectrum (octant + parity)
     const int kyo = ky <= Py / 2 ? ky : Py - ky;
     const R sy = ky <= Py / 2 ? (R)1 : (R)-1;
@@ -116,13 +115,8 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
         p[T] = mk<R>(s * (nxy * mx.x + nyy * my.x + nyz * mz.x), s * (nxy * mx.y + nyy * my.y + nyz * mz.y));
         p[2 * T] = mk<R>(s * (nxz * mx.x + nyz * my.x + nzz * mz.x), s * (nxz * mx.y + nyz * my.y + nzz * mz.y));
     }
-    lds_fft<R, true, emax<R>()>(buf, lgPz, T3, 1, T3, true);
-    for (int e = threadIdx.x; e < nz * T3; e += kNT) {
-        const int z = e / T3, r = e - z * T3;
-        const int c = r >> lgT, col = r & (T - 1);
-        const int kx = kx0 + col;
-        if (kx < Hx) base[c * comp_stride + z * plane_stride + kx] = buf[e];
-    }
+    __syncthreads();
+    fft_io<R, true, emax<R>(), true, false>(buf, lgPz, T3, 1, T3, true, none_load, store);
 }
 
 template <typename R>

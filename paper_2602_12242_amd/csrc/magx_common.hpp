@@ -161,6 +161,132 @@ __device__ __forceinline__ void lds_fft(cx<R>* buf, int lgL, int nseq, int bs, i
     else if (rem == 1) stockham_pass<R, 2, INV, EMAX>(buf, lgL, lgNs, nseq, bs, es, seq_fast);
 }
 
+// ---- Stockham FFT with its first pass reading, and its last pass writing,
+// through caller-supplied functors --------------------------------------------------
+// load(b, j) returns input element j of sequence b (e.g. from global memory,
+// zero for padding); store(b, j, v) consumes output element j.  Middle passes
+// run in LDS (element j of sequence b at buf[b*bs + j*es]).  With SRC_LDS /
+// DST_LDS the first / last pass uses the LDS buffer instead.  The remainder
+// radix (2 or 4) comes first, then radix-8 passes.  The radix-8 twiddles
+// w^{rk} come from three table reads (w^k, w^2k, w^4k) and their products.
+// A barrier follows every pass that writes LDS; a caller that reuses LDS after
+// a pass writing through `store` must place its own barrier.
+template <typename R, bool INV>
+__device__ __forceinline__ void twiddle_apply(cx<R>* v, int RAD, int k, int twshift) {
+    if (!k) return;
+    const cx<R> w1 = tw<R, INV>(k << twshift);
+    if (RAD == 2) { v[1] = cmul<R>(v[1], w1); return; }
+    const cx<R> w2 = tw<R, INV>((2 * k) << twshift);
+    if (RAD == 4) {
+        v[1] = cmul<R>(v[1], w1);
+        v[2] = cmul<R>(v[2], w2);
+        v[3] = cmul<R>(v[3], cmul<R>(w2, w1));
+        return;
+    }
+    const cx<R> w4 = tw<R, INV>((4 * k) << twshift);
+    const cx<R> w3 = cmul<R>(w2, w1);
+    v[1] = cmul<R>(v[1], w1);
+    v[2] = cmul<R>(v[2], w2);
+    v[3] = cmul<R>(v[3], w3);
+    v[4] = cmul<R>(v[4], w4);
+    v[5] = cmul<R>(v[5], cmul<R>(w4, w1));
+    v[6] = cmul<R>(v[6], cmul<R>(w4, w2));
+    v[7] = cmul<R>(v[7], cmul<R>(w4, w3));
+}
+
+template <typename R, int RAD, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, class Load, class Store>
+__device__ __forceinline__ void stockham_io_pass(cx<R>* buf, int lgL, int lgNs, int nseq, int bs, int es,
+                                                 bool seq_fast, Load& load, Store& store) {
+    constexpr int PER = EMAX / RAD > 0 ? EMAX / RAD : 1;
+    constexpr int LGR = RAD == 2 ? 1 : (RAD == 4 ? 2 : 3);
+    const int lgnb = lgL - LGR;
+    const int nb = 1 << lgnb;
+    const int total = nb * nseq;
+    const int Ns = 1 << lgNs;
+    const int twshift = kTwLog - LGR - lgNs;
+    cx<R> v[PER][RAD];
+    int seqv[PER], pos0[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int t = threadIdx.x + i * kNT;
+        if (t < total) {
+            int b, j;
+            if (seq_fast) { b = t % nseq; j = t / nseq; }
+            else { b = t >> lgnb; j = t & (nb - 1); }
+            seqv[i] = b;
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) {
+                if constexpr (SRC_LDS) v[i][r] = buf[b * bs + (j + (r << lgnb)) * es];
+                else v[i][r] = load(b, j + (r << lgnb));
+            }
+            const int k = j & (Ns - 1);
+            pos0[i] = ((j >> lgNs) * RAD) * Ns + k;
+            twiddle_apply<R, INV>(v[i], RAD, k, twshift);
+            dft<R, RAD, INV>(v[i]);
+        }
+    }
+    if constexpr (SRC_LDS && DST_LDS) __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int t = threadIdx.x + i * kNT;
+        if (t < total) {
+#pragma unroll
+            for (int r = 0; r < RAD; ++r) {
+                const int pos = pos0[i] + r * Ns;
+                if constexpr (DST_LDS) buf[seqv[i] * bs + pos * es] = v[i][r];
+                else store(seqv[i], pos, v[i][r]);
+            }
+        }
+    }
+    if constexpr (DST_LDS) __syncthreads();
+}
+
+template <typename R, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, class Load, class Store>
+__device__ __forceinline__ void fft_io(cx<R>* buf, int lgL, int nseq, int bs, int es, bool seq_fast, Load load,
+                                       Store store) {
+    if (lgL == 0) {   // length 1: the transform is the identity
+        for (int b = threadIdx.x; b < nseq; b += kNT) {
+            cx<R> x;
+            if constexpr (SRC_LDS) x = buf[b * bs];
+            else x = load(b, 0);
+            if constexpr (SRC_LDS && DST_LDS) { (void)0; }
+            if constexpr (DST_LDS) buf[b * bs] = x;
+            else store(b, 0, x);
+        }
+        if constexpr (DST_LDS) __syncthreads();
+        return;
+    }
+    const int rem = lgL % 3;
+    int lgNs = 0, left = lgL;
+    bool first = true;
+    if (rem) {
+        const bool last = (left == rem);
+        if (rem == 1) {
+            if (last) stockham_io_pass<R, 2, INV, EMAX, SRC_LDS, DST_LDS>(buf, lgL, 0, nseq, bs, es, seq_fast, load, store);
+            else stockham_io_pass<R, 2, INV, EMAX, SRC_LDS, true>(buf, lgL, 0, nseq, bs, es, seq_fast, load, store);
+        } else {
+            if (last) stockham_io_pass<R, 4, INV, EMAX, SRC_LDS, DST_LDS>(buf, lgL, 0, nseq, bs, es, seq_fast, load, store);
+            else stockham_io_pass<R, 4, INV, EMAX, SRC_LDS, true>(buf, lgL, 0, nseq, bs, es, seq_fast, load, store);
+        }
+        lgNs += rem;
+        left -= rem;
+        first = false;
+    }
+    while (left > 0) {
+        const bool last = (left == 3);
+        if (first) {
+            if (last) stockham_io_pass<R, 8, INV, EMAX, SRC_LDS, DST_LDS>(buf, lgL, lgNs, nseq, bs, es, seq_fast, load, store);
+            else stockham_io_pass<R, 8, INV, EMAX, SRC_LDS, true>(buf, lgL, lgNs, nseq, bs, es, seq_fast, load, store);
+            first = false;
+        } else {
+            if (last) stockham_io_pass<R, 8, INV, EMAX, true, DST_LDS>(buf, lgL, lgNs, nseq, bs, es, seq_fast, load, store);
+            else stockham_io_pass<R, 8, INV, EMAX, true, true>(buf, lgL, lgNs, nseq, bs, es, seq_fast, load, store);
+        }
+        lgNs += 3;
+        left -= 3;
+    }
+}
+
 __host__ __device__ inline int ilog2(int v) {
     int r = 0;
     while ((1 << r) < v) ++r;

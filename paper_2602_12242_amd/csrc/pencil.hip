@@ -23,8 +23,11 @@
 
 namespace magx {
 
-template <typename R> constexpr int pemax() { return sizeof(R) == 4 ? 32 : 16; }
-constexpr int kMaxSlot = 8;   // (pair-of-cells) slots per thread: np * Lh <= 2048
+// Two register budgets: BIG = false holds 16 FFT elements and 4 cell-pair
+// slots per thread (np * Lh <= 1024, every grid with nx <= 1024); BIG = true
+// holds 32 and 8 (nx up to 2048, float only).
+template <bool BIG> constexpr int pemax() { return BIG ? 32 : 16; }
+template <bool BIG> constexpr int maxslot() { return BIG ? 8 : 4; }
 
 struct PG {
     int nx, ny, nz, Lh, lgLh, Hx, Sx, lgPx, np, npen_total;
@@ -142,12 +145,13 @@ __device__ __forceinline__ void pen_coords(const PG& g, int pen, int& y, int& z)
 
 // Inverse x pass: Y1 rows -> real lines; afterwards the real value of cell x
 // of line l is buf[l*Lh + x/2].x (x even) or .y (x odd).
-template <typename R>
+template <typename R, bool BIG>
 __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int pen0, int npen) {
     const int Lh = g.Lh;
     const int twsh = kTwLog - g.lgPx;
-    for (int e = threadIdx.x; e < npen * 3 * Lh; e += kNT) {
-        const int line = e >> g.lgLh, k = e & (Lh - 1);
+    // split step of the half-length inverse, computed while the first FFT
+    // pass reads Y1: Z[k] = (X[k] + X*[Lh-k]) + i (X[k] - X*[Lh-k]) w^-k
+    auto load = [&](int line, int k) -> cx<R> {
         const int p = line / 3, c = line - 3 * p;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
@@ -156,18 +160,19 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int pen0, in
         const cx<R> b = cconj<R>(row[Lh - k]);
         const cx<R> A = cadd<R>(a, b);
         const cx<R> B = cmul<R>(csub<R>(a, b), cconj<R>(tw_fwd<R>(k << twsh)));
-        buf[e] = mk<R>(A.x - B.y, A.y + B.x);
-    }
-    lds_fft<R, true, pemax<R>()>(buf, g.lgLh, npen * 3, Lh, 1, false);
+        return mk<R>(A.x - B.y, A.y + B.x);
+    };
+    auto none_store = [&](int, int, cx<R>) {};
+    fft_io<R, true, pemax<BIG>(), false, true>(buf, g.lgLh, npen * 3, Lh, 1, false, load, none_store);
 }
 
 // Forward x pass: buf holds packed lines z[n] = x[2n] + i x[2n+1]; writes the
 // Hx-column half spectrum of every line to X1.
-template <typename R>
+template <typename R, bool BIG>
 __device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int pen0, int npen) {
     const int Lh = g.Lh;
     const int twsh = kTwLog - g.lgPx;
-    lds_fft<R, false, pemax<R>()>(buf, g.lgLh, npen * 3, Lh, 1, false);
+    lds_fft<R, false, pemax<BIG>()>(buf, g.lgLh, npen * 3, Lh, 1, false);
     const R half = (R)0.5;
     for (int e = threadIdx.x; e < npen * 3 * g.Hx; e += kNT) {
         const int line = e / g.Hx, k = e - line * g.Hx;
@@ -204,7 +209,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 // ---- kernels -------------------------------------------------------------------
 
-template <typename R>
+template <typename R, bool BIG>
 __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R>* __restrict__ X1, PG g) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
@@ -223,11 +228,11 @@ __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R
             buf[(3 * p + c) * g.Lh + n] = mk<R>(a, b);
         }
     }
-    r2c_lines<R>(buf, X1, g, pen0, npen);
+    r2c_lines<R, BIG>(buf, X1, g, pen0, npen);
 }
 
 // mode: 0 -> write H (with bias if with_bias); 1 -> energy partials (m.H_term)
-template <typename R>
+template <typename R, bool BIG>
 __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1, const R* __restrict__ f,
                                                     R* __restrict__ H, PG g, Phys<R> ph, int has_demag,
                                                     int with_bias, int energy, int sum_input,
@@ -237,7 +242,7 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
     __shared__ double red[kNT];
     const int pen0 = blockIdx.x * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
-    if (has_demag) c2r_lines<R>(buf, Y1, g, pen0, npen);
+    if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
     double acc[5] = {0, 0, 0, 0, 0};
     for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
@@ -285,22 +290,22 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
     }
 }
 
-template <typename R>
+template <typename R, bool BIG>
 __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, PG g,
                                                     Phys<R> ph, StageArgs<R> a, int has_demag) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int pen0 = blockIdx.x * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
-    if (has_demag) c2r_lines<R>(buf, Y1, g, pen0, npen);
+    if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
     // classical RK4 tableau
     const R bw[4] = {(R)(1.0 / 6.0), (R)(1.0 / 3.0), (R)(1.0 / 3.0), (R)(1.0 / 6.0)};
     const R cw[4] = {(R)0, (R)0.5, (R)0.5, (R)1};
     const int s = a.stage;
     const bool norm = (s < 4) ? (ph.renorm == 2) : (ph.renorm >= 1);
-    R keep[kMaxSlot][2][3];
+    R keep[maxslot<BIG>()][2][3];
 #pragma unroll
-    for (int i = 0; i < kMaxSlot; ++i) {
+    for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
@@ -365,17 +370,17 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
     if (!(a.want_next && has_demag)) return;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kMaxSlot; ++i) {
+    for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
     }
-    r2c_lines<R>(buf, X1, g, pen0, npen);
+    r2c_lines<R, BIG>(buf, X1, g, pen0, npen);
 }
 
-template <typename R>
+template <typename R, bool BIG>
 __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG g, Phys<R> ph, StartArgs<R> a,
                                                      int has_demag, double* __restrict__ partials) {
     extern __shared__ unsigned char smem_raw[];
@@ -386,9 +391,9 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
     const bool norm = ph.renorm >= 1;
     const R b4 = (R)(1.0 / 6.0);
     double hs[3] = {0, 0, 0};
-    R keep[kMaxSlot][2][3];
+    R keep[maxslot<BIG>()][2][3];
 #pragma unroll
-    for (int i = 0; i < kMaxSlot; ++i) {
+    for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
@@ -439,17 +444,17 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
     if (!has_demag) return;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kMaxSlot; ++i) {
+    for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
     }
-    r2c_lines<R>(buf, X1, g, pen0, npen);
+    r2c_lines<R, BIG>(buf, X1, g, pen0, npen);
 }
 
-template <typename R>
+template <typename R, bool BIG>
 __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1, PG g,
                                                      Phys<R> ph, BackArgs<R> a, int has_demag,
                                                      double* __restrict__ partials) {
@@ -458,15 +463,15 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
     __shared__ double red[kNT];
     const int pen0 = blockIdx.x * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
-    if (has_demag) c2r_lines<R>(buf, Y1, g, pen0, npen);
+    if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
     const R bw[4] = {(R)(1.0 / 6.0), (R)(1.0 / 3.0), (R)(1.0 / 3.0), (R)(1.0 / 6.0)};
     const R cw[4] = {(R)0, (R)0.5, (R)0.5, (R)1};
     const int s = a.stage;
     const bool norm = ph.renorm == 2;
     double hs[3] = {0, 0, 0};
-    R keep[kMaxSlot][2][3];
+    R keep[maxslot<BIG>()][2][3];
 #pragma unroll
-    for (int i = 0; i < kMaxSlot; ++i) {
+    for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
@@ -542,14 +547,14 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
     if (s == 1 || !has_demag) return;
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kMaxSlot; ++i) {
+    for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
     }
-    r2c_lines<R>(buf, X1, g, pen0, npen);
+    r2c_lines<R, BIG>(buf, X1, g, pen0, npen);
 }
 
 template <typename R>
@@ -611,10 +616,13 @@ __global__ void copy_kernel(const R* __restrict__ src, R* __restrict__ dst, long
 
 // ---- launchers -----------------------------------------------------------------
 static inline size_t pencil_lds(const Plan& pl) { return (size_t)3 * pl.np * pl.Lh * pl.esize * 2; }
+static inline bool pencil_big(const Plan& pl) { return pl.np * pl.Lh > 1024; }
 
 template <typename R>
 hipError_t launch_xfwd(const Plan& pl, const R* f, void* X1, hipStream_t s) {
-    hipLaunchKernelGGL(xfwd_kernel<R>, dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s, f,
+    if (pencil_big(pl)) hipLaunchKernelGGL((xfwd_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s, f,
+                       static_cast<cx<R>*>(X1), make_pg(pl));
+    else hipLaunchKernelGGL((xfwd_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s, f,
                        static_cast<cx<R>*>(X1), make_pg(pl));
     return hipGetLastError();
 }
@@ -623,7 +631,10 @@ template <typename R>
 hipError_t launch_field(const Plan& pl, const Phys<R>& ph, const void* Y1, const R* f, R* H, int with_bias,
                         int energy, int sum_input, double* partials, hipStream_t s) {
     const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
-    hipLaunchKernelGGL(field_kernel<R>, dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+    if (pencil_big(pl)) hipLaunchKernelGGL((field_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+                       static_cast<const cx<R>*>(Y1), f, H, make_pg(pl), ph, has_demag, with_bias, energy,
+                       sum_input, partials);
+    else hipLaunchKernelGGL((field_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
                        static_cast<const cx<R>*>(Y1), f, H, make_pg(pl), ph, has_demag, with_bias, energy,
                        sum_input, partials);
     return hipGetLastError();
@@ -633,7 +644,9 @@ template <typename R>
 hipError_t launch_stage(const Plan& pl, const Phys<R>& ph, const void* Y1, void* X1, const StageArgs<R>& a,
                         hipStream_t s) {
     const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
-    hipLaunchKernelGGL(stage_kernel<R>, dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+    if (pencil_big(pl)) hipLaunchKernelGGL((stage_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+                       static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag);
+    else hipLaunchKernelGGL((stage_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
                        static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag);
     return hipGetLastError();
 }
@@ -642,7 +655,9 @@ template <typename R>
 hipError_t launch_bstart(const Plan& pl, const Phys<R>& ph, void* X1, const StartArgs<R>& a, double* partials,
                          hipStream_t s) {
     const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
-    hipLaunchKernelGGL(bstart_kernel<R>, dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+    if (pencil_big(pl)) hipLaunchKernelGGL((bstart_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+                       static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag, partials);
+    else hipLaunchKernelGGL((bstart_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
                        static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag, partials);
     return hipGetLastError();
 }
@@ -651,7 +666,10 @@ template <typename R>
 hipError_t launch_bstage(const Plan& pl, const Phys<R>& ph, const void* Y1, void* X1, const BackArgs<R>& a,
                          double* partials, hipStream_t s) {
     const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
-    hipLaunchKernelGGL(bstage_kernel<R>, dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+    if (pencil_big(pl)) hipLaunchKernelGGL((bstage_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
+                       static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag,
+                       partials);
+    else hipLaunchKernelGGL((bstage_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
                        static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag,
                        partials);
     return hipGetLastError();
