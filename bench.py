@@ -28,7 +28,7 @@ sys.path.insert(0, ROOT)
 METRIC = "H_eff Mcells/s + RK4 steps/s, FP32 vs FP64 at stated err, 512×512×32; fwd+bwd"
 PEAK_HBM_GBS = 8000.0
 DOMINANT = "zconv"          # largest share of GPU time in the timed step (rocprofv3 summary)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "zconv_demag512_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "zconv_demag512_traffic.txt")
 
 
 def kernel_bytes(kind, n, es):
@@ -114,7 +114,78 @@ def cpu_baseline(w, budget_cells=(128, 128, 32)):
                       f"({dt:.1f} s), scaled by cell count {sub}/{w.ncell}"}
 
 
+def _pmc_rows(path, counter):
+    """(kernel name, value) per dispatch from a rocprofv3 result: a rocpd
+    SQLite database (*_results.db) or a counter_collection.csv."""
+    rows = []
+    if path.endswith(".db"):
+        import sqlite3
+        con = sqlite3.connect(path)
+        for name, cn, cv in con.execute("select name, counter_name, counter_value from pmc_events"):
+            if cn == counter:
+                rows.append((name, float(cv)))
+        return rows
+    import csv
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            if r.get("Counter_Name") == counter:
+                rows.append((r.get("Kernel_Name", ""), float(r["Counter_Value"])))
+    return rows
+
+
+def trace_summary(db, out_path, command):
+    """Writes a kernel-time summary (rocprofv3 --kernel-trace --stats result)."""
+    import sqlite3
+    con = sqlite3.connect(db)
+    rows = list(con.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
+                            "order by total_duration desc"))
+    lines = ["# rocprofv3 kernel trace: demag 512x512x32 FP32, checkpointed forward+adjoint RK4 steps", "",
+             "command: `" + command + "`", "",
+             "| kernel | calls | total ms | mean us | share % |", "|---|---|---|---|---|"]
+    for name, calls, tot, avg, pct in rows:
+        short = name.split("(")[0].replace("void ", "")
+        lines.append(f"| {short} | {calls} | {tot / 1e3:.3f} | {avg:.1f} | {pct:.1f} |")
+    with open(out_path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def pmc_summarize(fetch_csv, write_csv, command):
+    """HBM bytes per launch of the dominant kernel from FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch), each scaled by what the same counter reads for the
+    library's plain copy kernel moving a known 12N bytes each way."""
+    from workloads import WORKLOADS
+    N = WORKLOADS["demag"].ncell
+    known = 12.0 * N
+    out = {"kernel": DOMINANT, "workload": "demag 512x512x32 FP32", "source_hash": source_hash(),
+           "command": command}
+    total = 0.0
+    for label, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _pmc_rows(path, counter)
+        copy = [v * 1024.0 for k, v in rows if "copy_kernel" in k]
+        dom = [v * 1024.0 for k, v in rows if DOMINANT + "_kernel" in k]
+        if not copy or not dom:
+            raise SystemExit(f"{path}: no {counter} rows for copy_kernel / {DOMINANT}_kernel")
+        factor = known / (sum(copy) / len(copy))
+        per = factor * sum(dom) / len(dom)
+        out[f"{label}_raw_bytes_per_launch"] = sum(dom) / len(dom)
+        out[f"{label}_calibration_factor"] = factor
+        out[f"{label}_bytes_per_launch"] = per
+        total += per
+    out["bytes_per_launch"] = total
+    out["algorithmic_bytes_per_launch"] = kernel_bytes(DOMINANT, WORKLOADS["demag"].n, 4)
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--pmc-summarize":
+        pmc_summarize(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "--trace-summarize":
+        trace_summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)

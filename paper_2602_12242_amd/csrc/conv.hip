@@ -22,8 +22,9 @@ __global__ void __launch_bounds__(kNT) yfwd_kernel(const cx<R>* __restrict__ X1,
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
     const int Py = 1 << lgPy;
-    const int tx = blockIdx.x % ntx;
-    const long long plane = blockIdx.x / ntx;    // c * nz + z
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int tx = lb % ntx;
+    const long long plane = lb / ntx;    // c * nz + z
     const int kx0 = tx * T;
     const cx<R>* src = X1 + plane * ny * (long long)Sx;
     cx<R>* dst = X2 + plane * Py * (long long)Sx;
@@ -47,8 +48,9 @@ __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2,
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
     const int Py = 1 << lgPy;
-    const int tx = blockIdx.x % ntx;
-    const long long plane = blockIdx.x / ntx;
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int tx = lb % ntx;
+    const long long plane = lb / ntx;
     const int kx0 = tx * T;
     const cx<R>* src = X2 + plane * Py * (long long)Sx;
     cx<R>* dst = Y1 + plane * ny * (long long)Sx;
@@ -76,8 +78,12 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     const int T = 1 << lgT;
     const int T3 = 3 * T;
     const int Pz = 1 << lgPz;
-    const int tx = blockIdx.x % ntx;
-    const int ky = blockIdx.x / ntx;
+    // logical order 0, 1, Py-1, 2, Py-2, ..., Py/2: the mirrored rows ky and
+    // Py-ky read the same tensor octant rows one after the other on one XCD
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int tx = lb % ntx;
+    const int u = lb / ntx;
+    const int ky = (u & 1) ? (u + 1) >> 1 : (u == 0 ? 0 : Py - (u >> 1));
     const int kx0 = tx * T;
     const long long plane_stride = (long long)Py * Sx;     // one z row of X2
     const long long comp_stride = (long long)nz * plane_stride;

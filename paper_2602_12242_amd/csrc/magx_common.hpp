@@ -287,6 +287,16 @@ __device__ __forceinline__ void fft_io(cx<R>* buf, int lgL, int nseq, int bs, in
     }
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8), each with its own L2.  This bijection of [0, nblocks) gives every XCD
+// a contiguous range of logical blocks, so neighbouring tiles (which share
+// cache lines, stencil rows or tensor rows) meet in the same L2.
+__device__ __forceinline__ int xcd_logical_block(int b, int nblocks) {
+    const int q = nblocks >> 3, r = nblocks & 7;
+    const int x = b & 7, i = b >> 3;
+    return x * q + min(x, r) + i;
+}
+
 __host__ __device__ inline int ilog2(int v) {
     int r = 0;
     while ((1 << r) < v) ++r;

@@ -213,7 +213,7 @@ template <typename R, bool BIG>
 __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R>* __restrict__ X1, PG g) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
-    const int pen0 = blockIdx.x * g.np;
+    const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
     for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
-    const int pen0 = blockIdx.x * g.np;
+    const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
     if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
     double acc[5] = {0, 0, 0, 0, 0};
@@ -295,7 +295,7 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
                                                     Phys<R> ph, StageArgs<R> a, int has_demag) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
-    const int pen0 = blockIdx.x * g.np;
+    const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
     if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
     // classical RK4 tableau
@@ -386,7 +386,7 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
-    const int pen0 = blockIdx.x * g.np;
+    const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
     const bool norm = ph.renorm >= 1;
     const R b4 = (R)(1.0 / 6.0);
@@ -461,7 +461,7 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
-    const int pen0 = blockIdx.x * g.np;
+    const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
     if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
     const R bw[4] = {(R)(1.0 / 6.0), (R)(1.0 / 3.0), (R)(1.0 / 3.0), (R)(1.0 / 6.0)};
