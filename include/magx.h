@@ -46,7 +46,7 @@ extern "C" {
 #define MAGX_EINVAL     -1   /* null pointer, non-positive size or spacing, bad flag, DMI without exchange */
 #define MAGX_ESIZE      -2   /* n > 4096 on an axis, or an extended-grid length P = next power of two
                                 >= 2n exceeds the FFT passes' limits: Py <= 4096; Px <= 4096 (float)
-                                or 2048 (double); Pz <= 2048 (float) or 1024 (double) */
+                                or 2048 (double); Pz <= 1024 (float) or 512 (double) */
 #define MAGX_EDTYPE     -3   /* unknown element type */
 #define MAGX_EWORKSPACE -4   /* reserved: buffer sizes are the caller's contract (see magx_sizes) */
 #define MAGX_EHIP       -5   /* a HIP call failed */

@@ -13,9 +13,9 @@
 
 namespace magx {
 
-template <typename R> constexpr int emax() { return sizeof(R) == 4 ? 32 : 16; }
+// EM: FFT elements held per thread (T * L <= kNT * EM); 16 or 32.
 
-template <typename R>
+template <typename R, int EM>
 __global__ void __launch_bounds__(kNT) yfwd_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
                                                    int lgPy, int Hx, int Sx, int lgT, int ntx) {
     extern __shared__ unsigned char smem_raw[];
@@ -38,10 +38,10 @@ __global__ void __launch_bounds__(kNT) yfwd_kernel(const cx<R>* __restrict__ X1,
         const int kx = kx0 + b;
         if (kx < Hx) dst[(long long)j * Sx + kx] = v;
     };
-    fft_io<R, false, emax<R>(), false, false>(buf, lgPy, T, 1, T, true, load, store);
+    fft_io<R, false, EM, false, false>(buf, lgPy, T, 1, T, true, load, store);
 }
 
-template <typename R>
+template <typename R, int EM>
 __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
                                                    int lgPy, int Hx, int Sx, int lgT, int ntx) {
     extern __shared__ unsigned char smem_raw[];
@@ -64,12 +64,13 @@ __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2,
         const int kx = kx0 + b;
         if (j < ny && kx < Hx) dst[(long long)j * Sx + kx] = v;
     };
-    fft_io<R, true, emax<R>(), false, false>(buf, lgPy, T, 1, T, true, load, store);
+    fft_io<R, true, EM, false, false>(buf, lgPy, T, 1, T, true, load, store);
 }
 
 // LDS layout: element (z, c, col) at (z * 3 + c) * T + col, i.e. sequence
-// b = c*T + col with unit sequence stride and element stride 3T.
-template <typename R>
+// b = c*T + col with unit sequence stride and element stride 3T; behind it the
+// block's tensor tile tl[(comp * (Pz/2+1) + kzo) * T + col].
+template <typename R, int EM>
 __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
                                                     int nz, int lgPz, int Py, int Hx, int Hy, int Hz, int Sx,
                                                     int lgT, int ntx) {
@@ -78,6 +79,8 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     const int T = 1 << lgT;
     const int T3 = 3 * T;
     const int Pz = 1 << lgPz;
+    const int H2 = Pz >> 1;
+    R* tl = reinterpret_cast<R*>(buf + Pz * T3);
     // logical order 0, 1, Py-1, 2, Py-2, ..., Py/2: the mirrored rows ky and
     // Py-ky read the same tensor octant rows one after the other on one XCD
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -85,6 +88,29 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     const int u = lb / ntx;
     const int ky = (u & 1) ? (u + 1) >> 1 : (u == 0 ? 0 : Py - (u >> 1));
     const int kx0 = tx * T;
+    const int kyo = ky <= Py / 2 ? ky : Py - ky;
+    const R sy = ky <= Py / 2 ? (R)1 : (R)-1;
+    // tensor tile -> LDS first; its loads are in flight while the FFT loads X2
+    {
+        const int ntl = 6 * (H2 + 1) * T;
+        const long long cstride = (long long)Hz * Hy * Sx;
+        for (int e0 = threadIdx.x; e0 < ntl; e0 += kNT * 4) {
+            R v[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = e0 + q * kNT;
+                const int col = e & (T - 1), rest = e >> lgT;
+                const int c6 = rest / (H2 + 1), kzo = rest - c6 * (H2 + 1);
+                const int kx = kx0 + col;
+                v[q] = (e < ntl && kx < Hx) ? spec[c6 * cstride + ((long long)kzo * Hy + kyo) * Sx + kx] : (R)0;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = e0 + q * kNT;
+                if (e < ntl) tl[e] = v[q];
+            }
+        }
+    }
     const long long plane_stride = (long long)Py * Sx;     // one z row of X2
     const long long comp_stride = (long long)nz * plane_stride;
     cx<R>* base = X2 + (long long)ky * Sx;
@@ -100,30 +126,35 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     };
     auto none_load = [&](int, int) -> cx<R> { return zero; };
     auto none_store = [&](int, int, cx<R>) {};
-    fft_io<R, false, emax<R>(), false, true>(buf, lgPz, T3, 1, T3, true, load, none_store);
-    // pointwise 3x3 symmetric product with the real spectrum (octant + parity)
-    const int kyo = ky <= Py / 2 ? ky : Py - ky;
-    const R sy = ky <= Py / 2 ? (R)1 : (R)-1;
-    const long long cstride = (long long)Hz * Hy * Sx;
-    for (int e = threadIdx.x; e < Pz * T; e += kNT) {
-        const int kz = e >> lgT, col = e & (T - 1);
-        const int kx = kx0 + col;
-        if (kx >= Hx) continue;
-        const int kzo = kz <= Pz / 2 ? kz : Pz - kz;
-        const R sz = kz <= Pz / 2 ? (R)1 : (R)-1;
-        const R* sp = spec + ((long long)kzo * Hy + kyo) * Sx + kx;
-        const R nxx = sp[0], nyy = sp[cstride], nzz = sp[2 * cstride];
-        const R nxy = sy * sp[3 * cstride], nxz = sz * sp[4 * cstride], nyz = sy * sz * sp[5 * cstride];
-        cx<R>* p = buf + kz * T3 + col;
-        const cx<R> mx = p[0], my = p[T], mz = p[2 * T];
-        const R s = -Ms;
-        p[0] = mk<R>(s * (nxx * mx.x + nxy * my.x + nxz * mz.x), s * (nxx * mx.y + nxy * my.y + nxz * mz.y));
-        p[T] = mk<R>(s * (nxy * mx.x + nyy * my.x + nyz * mz.x), s * (nxy * mx.y + nyy * my.y + nyz * mz.y));
-        p[2 * T] = mk<R>(s * (nxz * mx.x + nyz * my.x + nzz * mz.x), s * (nxz * mx.y + nyz * my.y + nzz * mz.y));
+    fft_io<R, false, EM, false, true>(buf, lgPz, T3, 1, T3, true, load, none_store);
+    // 3x3 symmetric product with the real spectrum: H_a = -Ms sum_b N_ab M_b.
+    // Item (kzo, col) serves kz = kzo and its mirror Pz - kzo, where the
+    // components odd in z (xz, yz) change sign.
+    const int tslab = (H2 + 1) * T;
+    const R s = -Ms;
+    for (int e = threadIdx.x; e < tslab; e += kNT) {
+        const int kzo = e >> lgT, col = e & (T - 1);
+        const R* t = tl + e;
+        const R nxx = t[0], nyy = t[tslab], nzz = t[2 * tslab];
+        const R nxy = sy * t[3 * tslab], nxz = t[4 * tslab], nyz = sy * t[5 * tslab];
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            if (m == 1 && (kzo == 0 || kzo == H2)) break;
+            const int kz = m ? Pz - kzo : kzo;
+            const R sz = m ? (R)-1 : (R)1;
+            const R xz = sz * nxz, yz = sz * nyz;
+            cx<R>* p = buf + kz * T3 + col;
+            const cx<R> mx = p[0], my = p[T], mz = p[2 * T];
+            p[0] = mk<R>(s * (nxx * mx.x + nxy * my.x + xz * mz.x), s * (nxx * mx.y + nxy * my.y + xz * mz.y));
+            p[T] = mk<R>(s * (nxy * mx.x + nyy * my.x + yz * mz.x), s * (nxy * mx.y + nyy * my.y + yz * mz.y));
+            p[2 * T] = mk<R>(s * (xz * mx.x + yz * my.x + nzz * mz.x), s * (xz * mx.y + yz * my.y + nzz * mz.y));
+        }
     }
     __syncthreads();
-    fft_io<R, true, emax<R>(), true, false>(buf, lgPz, T3, 1, T3, true, none_load, store);
+    fft_io<R, true, EM, true, false>(buf, lgPz, T3, 1, T3, true, none_load, store);
 }
+
+static inline bool em_big(long long elements) { return elements > (long long)kNT * 16; }
 
 template <typename R>
 hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
@@ -131,8 +162,12 @@ hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) 
     const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
     const unsigned blocks = (unsigned)(ntx * 3 * pl.nz);
     const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
-    hipLaunchKernelGGL(yfwd_kernel<R>, dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
-                       static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
+    if (em_big((long long)pl.Py * pl.ty))
+        hipLaunchKernelGGL((yfwd_kernel<R, 32>), dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
+                           static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
+    else
+        hipLaunchKernelGGL((yfwd_kernel<R, 16>), dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
+                           static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
     return hipGetLastError();
 }
 
@@ -142,8 +177,12 @@ hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) 
     const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
     const unsigned blocks = (unsigned)(ntx * 3 * pl.nz);
     const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
-    hipLaunchKernelGGL(yinv_kernel<R>, dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X2),
-                       static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
+    if (em_big((long long)pl.Py * pl.ty))
+        hipLaunchKernelGGL((yinv_kernel<R, 32>), dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X2),
+                           static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
+    else
+        hipLaunchKernelGGL((yinv_kernel<R, 16>), dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X2),
+                           static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
     return hipGetLastError();
 }
 
@@ -152,10 +191,15 @@ hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStr
     const int lgT = ilog2(pl.tz);
     const int ntx = (pl.Hx + pl.tz - 1) / pl.tz;
     const unsigned blocks = (unsigned)(ntx * pl.Py);
-    const size_t lds = (size_t)3 * pl.Pz * pl.tz * sizeof(cx<R>);
-    hipLaunchKernelGGL(zconv_kernel<R>, dim3(blocks), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
-                       static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hy, pl.Hz, pl.Sx, lgT,
-                       ntx);
+    const size_t lds = (size_t)3 * pl.Pz * pl.tz * sizeof(cx<R>) + (size_t)6 * (pl.Pz / 2 + 1) * pl.tz * sizeof(R);
+    if (em_big(3LL * pl.Pz * pl.tz))
+        hipLaunchKernelGGL((zconv_kernel<R, 32>), dim3(blocks), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
+                           static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hy, pl.Hz, pl.Sx, lgT,
+                           ntx);
+    else
+        hipLaunchKernelGGL((zconv_kernel<R, 16>), dim3(blocks), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
+                           static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hy, pl.Hz, pl.Sx, lgT,
+                           ntx);
     return hipGetLastError();
 }
 

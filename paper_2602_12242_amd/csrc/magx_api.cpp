@@ -2,6 +2,7 @@
 // launch sequencing on the caller's stream.  Every numeric step runs in the
 // HIP kernels of tensor.hip, conv.hip and pencil.hip.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -93,7 +94,26 @@ int make_plan(const magx_grid* g, magx_dtype dt, Plan* pl) {
     p.Sx = (p.Hx + 15) / 16 * 16;
     p.ncell = (long long)p.nx * p.ny * p.nz;
     p.ty = std::min(16, pow2_floor(lds_cplx / p.Py));
-    p.tz = std::min(64, pow2_floor(lds_cplx / (3 * p.Pz)));
+    // tuning override of the y tile width (power of two within the LDS budget)
+    if (const char* e = std::getenv("MAGX_TILE_Y")) {
+        const int t = std::atoi(e);
+        if (t >= 1 && (t & (t - 1)) == 0 && (long long)t * p.Py <= lds_cplx) p.ty = t;
+    }
+    // z tile: data 3*Pz*tz complex + tensor tile 6*(Pz/2+1)*tz reals within
+    // 64 KiB, and at most 16 FFT elements per thread when possible
+    {
+        const long long per_col = (long long)p.esize * (6LL * p.Pz + 6LL * (p.Pz / 2 + 1));
+        int tz = std::min(64, pow2_floor(65536 / per_col));
+        while (tz > 1 && 3LL * p.Pz * tz > (long long)kNT * 16) tz >>= 1;
+        if (tz < 1 || 3LL * p.Pz * tz > (long long)kNT * 32 || per_col * tz > 65536) return MAGX_ESIZE;
+        // tuning override of the z tile width (power of two within both budgets)
+        if (const char* e = std::getenv("MAGX_TILE_Z")) {
+            const int t = std::atoi(e);
+            if (t >= 1 && (t & (t - 1)) == 0 && 3LL * p.Pz * t <= (long long)kNT * 32 && per_col * t <= 65536)
+                tz = t;
+        }
+        p.tz = tz;
+    }
     p.np = std::max(1, 1024 / p.Lh);
     const int npen = p.ny * p.nz;
     if (p.np > npen) p.np = npen;

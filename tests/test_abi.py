@@ -72,6 +72,8 @@ def test_sizes_of_workloads():
     ((4, 4, 4), (1e-9,) * 3, 7, -3),
     ((5000, 4, 4), (1e-9,) * 3, 0, -2),
     ((4, 4, 2048), (1e-9,) * 3, 1, -2),
+    ((4, 4, 1024), (1e-9,) * 3, 0, -2),
+    ((4, 4, 512), (1e-9,) * 3, 1, -2),
 ])
 def test_sizes_rejects(n, d, dt, code):
     magx, lib = _lib()
