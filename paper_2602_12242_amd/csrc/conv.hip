@@ -26,19 +26,18 @@ __global__ void __launch_bounds__(kNT) yfwd_kernel(const cx<R>* __restrict__ X1,
     const int tx = lb % ntx;
     const long long plane = lb / ntx;    // c * nz + z
     const int kx0 = tx * T;
-    const cx<R>* src = X1 + plane * ny * (long long)Sx;
-    cx<R>* dst = X2 + plane * Py * (long long)Sx;
-    const cx<R> zero = mk<R>(0, 0);
+    const cx<R>* src = X1 + plane * ny * (long long)Sx + kx0;
+    cx<R>* dst = X2 + plane * Py * (long long)Sx + kx0;
+    const int ncol = min(T, Hx - kx0);
     // sequence b = column kx0 + b; rows >= ny are the zero padding, never read
     auto load = [&](int b, int j) -> cx<R> {
-        const int kx = kx0 + b;
-        return (j < ny && kx < Hx) ? src[(long long)j * Sx + kx] : zero;
+        if (j < ny && b < ncol) return src[mul24(j, Sx) + b];
+        return mk<R>(0, 0);
     };
     auto store = [&](int b, int j, cx<R> v) {
-        const int kx = kx0 + b;
-        if (kx < Hx) dst[(long long)j * Sx + kx] = v;
+        if (b < ncol) dst[mul24(j, Sx) + b] = v;
     };
-    fft_io<R, false, EM, false, false>(buf, lgPy, T, 1, T, true, load, store);
+    fft_io<R, false, EM, false, false, kCols, 1>(buf, lgPy, lgT, T, load, store);
 }
 
 template <typename R, int EM>
@@ -52,19 +51,18 @@ __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2,
     const int tx = lb % ntx;
     const long long plane = lb / ntx;
     const int kx0 = tx * T;
-    const cx<R>* src = X2 + plane * Py * (long long)Sx;
-    cx<R>* dst = Y1 + plane * ny * (long long)Sx;
-    const cx<R> zero = mk<R>(0, 0);
+    const cx<R>* src = X2 + plane * Py * (long long)Sx + kx0;
+    cx<R>* dst = Y1 + plane * ny * (long long)Sx + kx0;
+    const int ncol = min(T, Hx - kx0);
     auto load = [&](int b, int j) -> cx<R> {
-        const int kx = kx0 + b;
-        return kx < Hx ? src[(long long)j * Sx + kx] : zero;
+        if (b < ncol) return src[mul24(j, Sx) + b];
+        return mk<R>(0, 0);
     };
     // rows inside the box only
     auto store = [&](int b, int j, cx<R> v) {
-        const int kx = kx0 + b;
-        if (j < ny && kx < Hx) dst[(long long)j * Sx + kx] = v;
+        if (j < ny && b < ncol) dst[mul24(j, Sx) + b] = v;
     };
-    fft_io<R, true, EM, false, false>(buf, lgPy, T, 1, T, true, load, store);
+    fft_io<R, true, EM, false, false, kCols, 1>(buf, lgPy, lgT, T, load, store);
 }
 
 // LDS layout: element (z, c, col) at (z * 3 + c) * T + col, i.e. sequence
@@ -80,7 +78,7 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     const int T3 = 3 * T;
     const int Pz = 1 << lgPz;
     const int H2 = Pz >> 1;
-    R* tl = reinterpret_cast<R*>(buf + Pz * T3);
+    R* tl = reinterpret_cast<R*>(smem_raw + (size_t)Pz * T3 * sizeof(cx<R>));
     // logical order 0, 1, Py-1, 2, Py-2, ..., Py/2: the mirrored rows ky and
     // Py-ky read the same tensor octant rows one after the other on one XCD
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -93,7 +91,7 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     // tensor tile -> LDS first; its loads are in flight while the FFT loads X2
     {
         const int ntl = 6 * (H2 + 1) * T;
-        const long long cstride = (long long)Hz * Hy * Sx;
+        const int cstride = Hz * Hy * Sx;
         for (int e0 = threadIdx.x; e0 < ntl; e0 += kNT * 4) {
             R v[4];
 #pragma unroll
@@ -102,7 +100,7 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
                 const int col = e & (T - 1), rest = e >> lgT;
                 const int c6 = rest / (H2 + 1), kzo = rest - c6 * (H2 + 1);
                 const int kx = kx0 + col;
-                v[q] = (e < ntl && kx < Hx) ? spec[c6 * cstride + ((long long)kzo * Hy + kyo) * Sx + kx] : (R)0;
+                v[q] = (e < ntl && kx < Hx) ? spec[c6 * cstride + mul24(mul24(kzo, Hy) + kyo, Sx) + kx] : (R)0;
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -111,22 +109,23 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
             }
         }
     }
-    const long long plane_stride = (long long)Py * Sx;     // one z row of X2
-    const long long comp_stride = (long long)nz * plane_stride;
-    cx<R>* base = X2 + (long long)ky * Sx;
-    const cx<R> zero = mk<R>(0, 0);
+    const int plane_stride = Py * Sx;     // one z row of X2 (< 2^23, checked in the plan)
+    const int comp_stride = nz * plane_stride;
+    cx<R>* base = X2 + (long long)ky * Sx + kx0;
+    const int ncol = min(T, Hx - kx0);
     // rows z >= nz are the zero padding (never read) and are never written back
     auto load = [&](int b, int j) -> cx<R> {
-        const int c = b >> lgT, kx = kx0 + (b & (T - 1));
-        return (j < nz && kx < Hx) ? base[c * comp_stride + j * plane_stride + kx] : zero;
+        const int c = b >> lgT, col = b & (T - 1);
+        if (j < nz && col < ncol) return base[c * comp_stride + mul24(j, plane_stride) + col];
+        return mk<R>(0, 0);
     };
     auto store = [&](int b, int j, cx<R> v) {
-        const int c = b >> lgT, kx = kx0 + (b & (T - 1));
-        if (j < nz && kx < Hx) base[c * comp_stride + j * plane_stride + kx] = v;
+        const int c = b >> lgT, col = b & (T - 1);
+        if (j < nz && col < ncol) base[c * comp_stride + mul24(j, plane_stride) + col] = v;
     };
-    auto none_load = [&](int, int) -> cx<R> { return zero; };
+    auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
     auto none_store = [&](int, int, cx<R>) {};
-    fft_io<R, false, EM, false, true>(buf, lgPz, T3, 1, T3, true, load, none_store);
+    fft_io<R, false, EM, false, true, kCols, 3>(buf, lgPz, lgT, T3, load, none_store);
     // 3x3 symmetric product with the real spectrum: H_a = -Ms sum_b N_ab M_b.
     // Item (kzo, col) serves kz = kzo and its mirror Pz - kzo, where the
     // components odd in z (xz, yz) change sign.
@@ -151,7 +150,7 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
         }
     }
     __syncthreads();
-    fft_io<R, true, EM, true, false>(buf, lgPz, T3, 1, T3, true, none_load, store);
+    fft_io<R, true, EM, true, false, kCols, 3>(buf, lgPz, lgT, T3, none_load, store);
 }
 
 static inline bool em_big(long long elements) { return elements > (long long)kNT * 16; }

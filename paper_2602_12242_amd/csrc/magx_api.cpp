@@ -92,6 +92,10 @@ int make_plan(const magx_grid* g, magx_dtype dt, Plan* pl) {
     p.Lh = p.Px / 2; p.lgLh = p.lgPx - 1;
     p.Hx = p.Lh + 1; p.Hy = p.Py / 2 + 1; p.Hz = p.Pz / 2 + 1;
     p.Sx = (p.Hx + 15) / 16 * 16;
+    // 32-bit element offsets inside the spectral arrays, 24-bit row strides
+    if (3LL * p.nz * p.Py * p.Sx >= (1LL << 31) || (long long)p.Py * p.Sx >= (1LL << 23) ||
+        6LL * p.Hz * p.Hy * p.Sx >= (1LL << 31))
+        return MAGX_ESIZE;
     p.ncell = (long long)p.nx * p.ny * p.nz;
     p.ty = std::min(16, pow2_floor(lds_cplx / p.Py));
     // tuning override of the y tile width (power of two within the LDS budget)

@@ -92,85 +92,27 @@ template <typename R, int RAD, bool INV> __device__ __forceinline__ void dft(cx<
     else dft8<R, INV>(v);
 }
 
-// ---- LDS Stockham FFT ------------------------------------------------------------
-// nseq independent sequences of length L = 2^lgL (1 <= L <= 4096) live in LDS;
-// element j of sequence b is at buf[b*bs + j*es].  If seq_fast, consecutive
-// threads take consecutive sequences (column tiles, es > 1); otherwise
-// consecutive positions within a sequence (contiguous lines, es == 1).
-// Each thread holds at most EMAX elements, i.e. nseq*L <= kNT*EMAX.  All
-// threads of the block must call; the routine begins and ends with a barrier.
-// Unnormalised: the inverse is the conjugate-twiddle transform.
-template <typename R, int RAD, bool INV, int EMAX>
-__device__ __forceinline__ void stockham_pass(cx<R>* buf, int lgL, int lgNs, int nseq, int bs,
-                                              int es, bool seq_fast) {
-    constexpr int PER = EMAX / RAD > 0 ? EMAX / RAD : 1;
-    constexpr int LGR = RAD == 2 ? 1 : (RAD == 4 ? 2 : 3);
-    const int lgnb = lgL - LGR;          // log2 butterflies per sequence
-    const int nb = 1 << lgnb;
-    const int total = nb * nseq;
-    const int Ns = 1 << lgNs;
-    const int twshift = kTwLog - LGR - lgNs;   // w_{RAD*Ns}^{rk} = table[(r*k) << twshift]
-    cx<R> v[PER][RAD];
-    int base[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int t = threadIdx.x + i * kNT;
-        if (t < total) {
-            int b, j;
-            if (seq_fast) { b = t % nseq; j = t / nseq; }
-            else { b = t >> lgnb; j = t & (nb - 1); }
-            base[i] = b * bs;
-            const cx<R>* src = buf + b * bs + j * es;
-#pragma unroll
-            for (int r = 0; r < RAD; ++r) v[i][r] = src[(r << lgnb) * es];
-            // twiddle and butterfly in registers
-            const int k = j & (Ns - 1);
-#pragma unroll
-            for (int r = 1; r < RAD; ++r) {
-                if (k) v[i][r] = cmul<R>(v[i][r], tw<R, INV>((r * k) << twshift));
-            }
-            dft<R, RAD, INV>(v[i]);
-            // destination index of output r: ((j >> lgNs) * RAD + r) * Ns + k
-            base[i] += (((j >> lgNs) * RAD) * Ns + k) * es;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int t = threadIdx.x + i * kNT;
-        if (t < total) {
-            cx<R>* dst = buf + base[i];
-#pragma unroll
-            for (int r = 0; r < RAD; ++r) dst[(r * Ns) * es] = v[i][r];
-        }
-    }
-    __syncthreads();
-}
+// ---- Stockham FFTs in LDS ----------------------------------------------------------
+// nseq independent sequences of length L = 2^lgL (1 <= L <= 4096).  Two LDS
+// layouts:
+//  * columns (LAYOUT = kCols): nseq = NC << lgT sequences, element j of
+//    sequence b at b + j*nseq; consecutive threads take consecutive b
+//    (coalesced column tiles; NC = 1 or 3 is a compile-time constant so the
+//    thread -> (b, j) split needs no runtime division);
+//  * lines (LAYOUT = kLines): element j of sequence b at (b << lgL) + j;
+//    consecutive threads take consecutive j.
+// Each thread holds at most EMAX elements (nseq * L <= kNT * EMAX).
+// load(b, j) / store(b, j, v) are used instead of LDS by the first / last
+// pass when SRC_LDS / DST_LDS is false.  The remainder radix (2 or 4) comes
+// first, then radix-8 passes.  Radix-8 twiddles w^{rk} come from three table
+// reads (w^k, w^2k, w^4k) and their products.  A barrier follows every pass
+// that writes LDS (and precedes a pass reading and writing LDS in place).
+// Unnormalised; the inverse uses conjugate twiddles.
+constexpr int kCols = 0;
+constexpr int kLines = 1;
 
-template <typename R, bool INV, int EMAX>
-__device__ __forceinline__ void lds_fft(cx<R>* buf, int lgL, int nseq, int bs, int es, bool seq_fast) {
-    __syncthreads();
-    int lgNs = 0;
-    int rem = lgL;
-    while (rem >= 3) {
-        stockham_pass<R, 8, INV, EMAX>(buf, lgL, lgNs, nseq, bs, es, seq_fast);
-        lgNs += 3;
-        rem -= 3;
-    }
-    if (rem == 2) stockham_pass<R, 4, INV, EMAX>(buf, lgL, lgNs, nseq, bs, es, seq_fast);
-    else if (rem == 1) stockham_pass<R, 2, INV, EMAX>(buf, lgL, lgNs, nseq, bs, es, seq_fast);
-}
+__device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
 
-// ---- Stockham FFT with its first pass reading, and its last pass writing,
-// through caller-supplied functors --------------------------------------------------
-// load(b, j) returns input element j of sequence b (e.g. from global memory,
-// zero for padding); store(b, j, v) consumes output element j.  Middle passes
-// run in LDS (element j of sequence b at buf[b*bs + j*es]).  With SRC_LDS /
-// DST_LDS the first / last pass uses the LDS buffer instead.  The remainder
-// radix (2 or 4) comes first, then radix-8 passes.  The radix-8 twiddles
-// w^{rk} come from three table reads (w^k, w^2k, w^4k) and their products.
-// A barrier follows every pass that writes LDS; a caller that reuses LDS after
-// a pass writing through `store` must place its own barrier.
 template <typename R, bool INV>
 __device__ __forceinline__ void twiddle_apply(cx<R>* v, int RAD, int k, int twshift) {
     if (!k) return;
@@ -194,9 +136,24 @@ __device__ __forceinline__ void twiddle_apply(cx<R>* v, int RAD, int k, int twsh
     v[7] = cmul<R>(v[7], cmul<R>(w4, w3));
 }
 
-template <typename R, int RAD, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, class Load, class Store>
-__device__ __forceinline__ void stockham_io_pass(cx<R>* buf, int lgL, int lgNs, int nseq, int bs, int es,
-                                                 bool seq_fast, Load& load, Store& store) {
+template <int LAYOUT, int NC>
+__device__ __forceinline__ void seq_split(int t, int lgT, int lgnb, int nseq, int& b, int& j) {
+    if constexpr (LAYOUT == kLines) {
+        b = t >> lgnb;
+        j = t & ((1 << lgnb) - 1);
+    } else if constexpr (NC == 1) {
+        b = t & (nseq - 1);
+        j = t >> lgT;
+    } else {
+        j = (t >> lgT) / NC;
+        b = t - mul24(j, nseq);
+    }
+}
+
+template <typename R, int RAD, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, int LAYOUT, int NC, class Load,
+          class Store>
+__device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lgL, int lgNs, int lgT, int nseq,
+                                                 Load& load, Store& store) {
     constexpr int PER = EMAX / RAD > 0 ? EMAX / RAD : 1;
     constexpr int LGR = RAD == 2 ? 1 : (RAD == 4 ? 2 : 3);
     const int lgnb = lgL - LGR;
@@ -204,23 +161,29 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* buf, int lgL, int lgNs, 
     const int total = nb * nseq;
     const int Ns = 1 << lgNs;
     const int twshift = kTwLog - LGR - lgNs;
+    // uniform strides between the RAD inputs / outputs of one butterfly
+    const int in_stride = LAYOUT == kLines ? nb : (nb * nseq);
+    const int out_stride = LAYOUT == kLines ? Ns : (Ns * nseq);
     cx<R> v[PER][RAD];
-    int seqv[PER], pos0[PER];
+    int seqv[PER], pos0[PER], obase[PER];
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
         const int t = threadIdx.x + i * kNT;
         if (t < total) {
             int b, j;
-            if (seq_fast) { b = t % nseq; j = t / nseq; }
-            else { b = t >> lgnb; j = t & (nb - 1); }
+            seq_split<LAYOUT, NC>(t, lgT, lgnb, nseq, b, j);
             seqv[i] = b;
+            if constexpr (SRC_LDS) {
+                const int ib = LAYOUT == kLines ? (b << lgL) + j : b + mul24(j, nseq);
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) {
-                if constexpr (SRC_LDS) v[i][r] = buf[b * bs + (j + (r << lgnb)) * es];
-                else v[i][r] = load(b, j + (r << lgnb));
+                for (int r = 0; r < RAD; ++r) v[i][r] = buf[ib + r * in_stride];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RAD; ++r) v[i][r] = load(b, j + (r << lgnb));
             }
             const int k = j & (Ns - 1);
-            pos0[i] = ((j >> lgNs) * RAD) * Ns + k;
+            pos0[i] = ((j >> lgNs) << (lgNs + LGR)) + k;
+            obase[i] = LAYOUT == kLines ? (b << lgL) + pos0[i] : b + mul24(pos0[i], nseq);
             twiddle_apply<R, INV>(v[i], RAD, k, twshift);
             dft<R, RAD, INV>(v[i]);
         }
@@ -232,25 +195,22 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* buf, int lgL, int lgNs, 
         if (t < total) {
 #pragma unroll
             for (int r = 0; r < RAD; ++r) {
-                const int pos = pos0[i] + r * Ns;
-                if constexpr (DST_LDS) buf[seqv[i] * bs + pos * es] = v[i][r];
-                else store(seqv[i], pos, v[i][r]);
+                if constexpr (DST_LDS) buf[obase[i] + r * out_stride] = v[i][r];
+                else store(seqv[i], pos0[i] + r * Ns, v[i][r]);
             }
         }
     }
     if constexpr (DST_LDS) __syncthreads();
 }
 
-template <typename R, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, class Load, class Store>
-__device__ __forceinline__ void fft_io(cx<R>* buf, int lgL, int nseq, int bs, int es, bool seq_fast, Load load,
-                                       Store store) {
+template <typename R, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, int LAYOUT, int NC, class Load, class Store>
+__device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT, int nseq, Load load, Store store) {
     if (lgL == 0) {   // length 1: the transform is the identity
         for (int b = threadIdx.x; b < nseq; b += kNT) {
             cx<R> x;
-            if constexpr (SRC_LDS) x = buf[b * bs];
+            if constexpr (SRC_LDS) x = buf[b];
             else x = load(b, 0);
-            if constexpr (SRC_LDS && DST_LDS) { (void)0; }
-            if constexpr (DST_LDS) buf[b * bs] = x;
+            if constexpr (DST_LDS) buf[b] = x;
             else store(b, 0, x);
         }
         if constexpr (DST_LDS) __syncthreads();
@@ -259,14 +219,16 @@ __device__ __forceinline__ void fft_io(cx<R>* buf, int lgL, int nseq, int bs, in
     const int rem = lgL % 3;
     int lgNs = 0, left = lgL;
     bool first = true;
+#define MAGX_PASS(RADIX, S, D) \
+    stockham_io_pass<R, RADIX, INV, EMAX, S, D, LAYOUT, NC>(buf, lgL, lgNs, lgT, nseq, load, store)
     if (rem) {
         const bool last = (left == rem);
         if (rem == 1) {
-            if (last) stockham_io_pass<R, 2, INV, EMAX, SRC_LDS, DST_LDS>(buf, lgL, 0, nseq, bs, es, seq_fast, load, store);
-            else stockham_io_pass<R, 2, INV, EMAX, SRC_LDS, true>(buf, lgL, 0, nseq, bs, es, seq_fast, load, store);
+            if (last) MAGX_PASS(2, SRC_LDS, DST_LDS);
+            else MAGX_PASS(2, SRC_LDS, true);
         } else {
-            if (last) stockham_io_pass<R, 4, INV, EMAX, SRC_LDS, DST_LDS>(buf, lgL, 0, nseq, bs, es, seq_fast, load, store);
-            else stockham_io_pass<R, 4, INV, EMAX, SRC_LDS, true>(buf, lgL, 0, nseq, bs, es, seq_fast, load, store);
+            if (last) MAGX_PASS(4, SRC_LDS, DST_LDS);
+            else MAGX_PASS(4, SRC_LDS, true);
         }
         lgNs += rem;
         left -= rem;
@@ -275,16 +237,17 @@ __device__ __forceinline__ void fft_io(cx<R>* buf, int lgL, int nseq, int bs, in
     while (left > 0) {
         const bool last = (left == 3);
         if (first) {
-            if (last) stockham_io_pass<R, 8, INV, EMAX, SRC_LDS, DST_LDS>(buf, lgL, lgNs, nseq, bs, es, seq_fast, load, store);
-            else stockham_io_pass<R, 8, INV, EMAX, SRC_LDS, true>(buf, lgL, lgNs, nseq, bs, es, seq_fast, load, store);
+            if (last) MAGX_PASS(8, SRC_LDS, DST_LDS);
+            else MAGX_PASS(8, SRC_LDS, true);
             first = false;
         } else {
-            if (last) stockham_io_pass<R, 8, INV, EMAX, true, DST_LDS>(buf, lgL, lgNs, nseq, bs, es, seq_fast, load, store);
-            else stockham_io_pass<R, 8, INV, EMAX, true, true>(buf, lgL, lgNs, nseq, bs, es, seq_fast, load, store);
+            if (last) MAGX_PASS(8, true, DST_LDS);
+            else MAGX_PASS(8, true, true);
         }
         lgNs += 3;
         left -= 3;
     }
+#undef MAGX_PASS
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD

@@ -155,7 +155,7 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int pen0, in
         const int p = line / 3, c = line - 3 * p;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
-        const cx<R>* row = Y1 + (((long long)c * g.nz + z) * g.ny + y) * g.Sx;
+        const cx<R>* row = Y1 + (((c * g.nz + z) * g.ny + y) * g.Sx);
         const cx<R> a = row[k];
         const cx<R> b = cconj<R>(row[Lh - k]);
         const cx<R> A = cadd<R>(a, b);
@@ -163,7 +163,7 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int pen0, in
         return mk<R>(A.x - B.y, A.y + B.x);
     };
     auto none_store = [&](int, int, cx<R>) {};
-    fft_io<R, true, pemax<BIG>(), false, true>(buf, g.lgLh, npen * 3, Lh, 1, false, load, none_store);
+    fft_io<R, true, pemax<BIG>(), false, true, kLines, 1>(buf, g.lgLh, 0, npen * 3, load, none_store);
 }
 
 // Forward x pass: buf holds packed lines z[n] = x[2n] + i x[2n+1]; writes the
@@ -172,7 +172,10 @@ template <typename R, bool BIG>
 __device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int pen0, int npen) {
     const int Lh = g.Lh;
     const int twsh = kTwLog - g.lgPx;
-    lds_fft<R, false, pemax<BIG>()>(buf, g.lgLh, npen * 3, Lh, 1, false);
+    auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
+    auto none_store = [&](int, int, cx<R>) {};
+    __syncthreads();
+    fft_io<R, false, pemax<BIG>(), true, true, kLines, 1>(buf, g.lgLh, 0, npen * 3, none_load, none_store);
     const R half = (R)0.5;
     for (int e = threadIdx.x; e < npen * 3 * g.Hx; e += kNT) {
         const int line = e / g.Hx, k = e - line * g.Hx;
@@ -185,7 +188,7 @@ __device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int pen0, int npen
         const cx<R> D = csub<R>(Zk, Zm);
         const cx<R> O = mk<R>(half * D.y, -half * D.x);       // (Zk - Zm) / (2i)
         const cx<R> X = cadd<R>(E, cmul<R>(tw_fwd<R>(k << twsh), O));
-        X1[(((long long)c * g.nz + z) * g.ny + y) * g.Sx + k] = X;
+        X1[((c * g.nz + z) * g.ny + y) * g.Sx + k] = X;
     }
 }
 
