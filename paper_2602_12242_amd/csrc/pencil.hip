@@ -56,49 +56,131 @@ __device__ __forceinline__ void store3(R* __restrict__ f, long long N, long long
     f[2 * N + id] = v[2];
 }
 
-// Exchange, DMI and anisotropy fields of the linear field f at cell (x,y,z).
+// ---- cell pairs (2n, 2n+1) along x ------------------------------------------------
+// With nx even every pair is complete and 8-byte (float) / 16-byte (double)
+// aligned, so a pair is one vector access per component; with nx odd the last
+// pair of a row has a single cell and scalar accesses are used.
 template <typename R>
-__device__ __forceinline__ void local_field(const R* __restrict__ f, const PG& g, int x, int y, int z,
-                                            const Phys<R>& ph, R m[3], R hex[3], R hdmi[3], R hani[3]) {
-    const long long N = g.N;
-    const long long id = ((long long)z * g.ny + y) * g.nx + x;
-    load3(f, N, id, m);
+__device__ __forceinline__ void load_pair(const R* __restrict__ f, long long N, long long id, bool vec, bool two,
+                                          R a[3], R b[3]) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) hex[c] = hdmi[c] = hani[c] = (R)0;
+    for (int c = 0; c < 3; ++c) {
+        const R* p = f + c * N + id;
+        if (vec) {
+            const cx<R> v = *reinterpret_cast<const cx<R>*>(p);
+            a[c] = v.x;
+            b[c] = v.y;
+        } else {
+            a[c] = p[0];
+            b[c] = two ? p[1] : (R)0;
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void store_pair(R* __restrict__ f, long long N, long long id, bool vec, bool two,
+                                           const R a[3], const R b[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        R* p = f + c * N + id;
+        if (vec) {
+            *reinterpret_cast<cx<R>*>(p) = mk<R>(a[c], b[c]);
+        } else {
+            p[0] = a[c];
+            if (two) p[1] = b[c];
+        }
+    }
+}
+
+// Exchange + DMI + anisotropy of the linear field f for the pair of cells
+// (x0 = 2n, x0 + 1) of row (y, z); h*[0] belongs to cell x0, h*[1] to x0 + 1.
+// The ghost rule is the same as in local_field.
+template <typename R>
+__device__ __forceinline__ void local_field_pair(const R* __restrict__ f, const PG& g, int x0, int y, int z,
+                                                 bool vec, bool two, const Phys<R>& ph, R m[2][3], R h[2][3],
+                                                 R hex_dot[2], R hdmi_dot[2], R hani_dot[2], bool want_parts) {
+    const long long N = g.N;
+    const long long id = ((long long)z * g.ny + y) * g.nx + x0;
+    load_pair(f, N, id, vec, two, m[0], m[1]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) h[q][c] = (R)0;
+        hex_dot[q] = hdmi_dot[q] = hani_dot[q] = (R)0;
+    }
     if (ph.terms & (MAGX_EXCH | MAGX_DMI)) {
-        R xp[3], xm[3], yp[3], ym[3], zp[3], zm[3];
         const R kdx = ph.kap * ph.dx, kdy = ph.kap * ph.dy;
-        if (x + 1 < g.nx) load3(f, N, id + 1, xp);
-        else { xp[0] = m[0] + kdx * m[2]; xp[1] = m[1]; xp[2] = m[2] - kdx * m[0]; }
-        if (x > 0) load3(f, N, id - 1, xm);
-        else { xm[0] = m[0] - kdx * m[2]; xm[1] = m[1]; xm[2] = m[2] + kdx * m[0]; }
-        if (y + 1 < g.ny) load3(f, N, id + g.nx, yp);
-        else { yp[0] = m[0]; yp[1] = m[1] + kdy * m[2]; yp[2] = m[2] - kdy * m[1]; }
-        if (y > 0) load3(f, N, id - g.nx, ym);
-        else { ym[0] = m[0]; ym[1] = m[1] - kdy * m[2]; ym[2] = m[2] + kdy * m[1]; }
+        R xl[3], xr[3], yp[2][3], ym[2][3], zp[2][3], zm[2][3];
+        // outer x neighbours of the pair: cell x0 - 1 and cell x0 + 2 (or x0 + 1 if alone)
+        R last[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) last[c] = two ? m[1][c] : m[0][c];
+        if (x0 > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xl[c] = f[c * N + id - 1];
+        } else {
+            xl[0] = m[0][0] - kdx * m[0][2]; xl[1] = m[0][1]; xl[2] = m[0][2] + kdx * m[0][0];
+        }
+        const int xr_x = x0 + (two ? 2 : 1);
+        if (xr_x < g.nx) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xr[c] = f[c * N + id + (two ? 2 : 1)];
+        } else {
+            xr[0] = last[0] + kdx * last[2]; xr[1] = last[1]; xr[2] = last[2] - kdx * last[0];
+        }
+        if (y + 1 < g.ny) load_pair(f, N, id + g.nx, vec, two, yp[0], yp[1]);
+        if (y > 0) load_pair(f, N, id - g.nx, vec, two, ym[0], ym[1]);
         const long long pz = (long long)g.nx * g.ny;
-        if (z + 1 < g.nz) load3(f, N, id + pz, zp);
-        else { zp[0] = m[0]; zp[1] = m[1]; zp[2] = m[2]; }
-        if (z > 0) load3(f, N, id - pz, zm);
-        else { zm[0] = m[0]; zm[1] = m[1]; zm[2] = m[2]; }
-        if (ph.terms & MAGX_EXCH) {
+        if (z + 1 < g.nz) load_pair(f, N, id + pz, vec, two, zp[0], zp[1]);
+        if (z > 0) load_pair(f, N, id - pz, vec, two, zm[0], zm[1]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const R* mc = m[q];
+            R xp[3], xm[3], ypq[3], ymq[3], zpq[3], zmq[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const R m2 = (R)2 * m[c];
-                hex[c] = ph.cex * ((xp[c] - m2 + xm[c]) * ph.idx2 + (yp[c] - m2 + ym[c]) * ph.idy2 +
-                                   (zp[c] - m2 + zm[c]) * ph.idz2);
+                xm[c] = q == 0 ? xl[c] : m[0][c];
+                xp[c] = q == 0 ? (two ? m[1][c] : xr[c]) : xr[c];
             }
-        }
-        if (ph.terms & MAGX_DMI) {
-            hdmi[0] = ph.cdmi * (xp[2] - xm[2]) * ph.h2x;
-            hdmi[1] = ph.cdmi * (yp[2] - ym[2]) * ph.h2y;
-            hdmi[2] = -ph.cdmi * ((xp[0] - xm[0]) * ph.h2x + (yp[1] - ym[1]) * ph.h2y);
+            if (y + 1 < g.ny) { ypq[0] = yp[q][0]; ypq[1] = yp[q][1]; ypq[2] = yp[q][2]; }
+            else { ypq[0] = mc[0]; ypq[1] = mc[1] + kdy * mc[2]; ypq[2] = mc[2] - kdy * mc[1]; }
+            if (y > 0) { ymq[0] = ym[q][0]; ymq[1] = ym[q][1]; ymq[2] = ym[q][2]; }
+            else { ymq[0] = mc[0]; ymq[1] = mc[1] - kdy * mc[2]; ymq[2] = mc[2] + kdy * mc[1]; }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                zpq[c] = (z + 1 < g.nz) ? zp[q][c] : mc[c];
+                zmq[c] = (z > 0) ? zm[q][c] : mc[c];
+            }
+            R hx[3] = {(R)0, (R)0, (R)0}, hd[3] = {(R)0, (R)0, (R)0};
+            if (ph.terms & MAGX_EXCH) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const R m2 = (R)2 * mc[c];
+                    hx[c] = ph.cex * ((xp[c] - m2 + xm[c]) * ph.idx2 + (ypq[c] - m2 + ymq[c]) * ph.idy2 +
+                                      (zpq[c] - m2 + zmq[c]) * ph.idz2);
+                }
+            }
+            if (ph.terms & MAGX_DMI) {
+                hd[0] = ph.cdmi * (xp[2] - xm[2]) * ph.h2x;
+                hd[1] = ph.cdmi * (ypq[2] - ymq[2]) * ph.h2y;
+                hd[2] = -ph.cdmi * ((xp[0] - xm[0]) * ph.h2x + (ypq[1] - ymq[1]) * ph.h2y);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h[q][c] = hx[c] + hd[c];
+            if (want_parts) {
+                hex_dot[q] = mc[0] * hx[0] + mc[1] * hx[1] + mc[2] * hx[2];
+                hdmi_dot[q] = mc[0] * hd[0] + mc[1] * hd[1] + mc[2] * hd[2];
+            }
         }
     }
     if (ph.terms & MAGX_ANIS) {
-        const R pr = m[0] * ph.eK[0] + m[1] * ph.eK[1] + m[2] * ph.eK[2];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) hani[c] = ph.cani * pr * ph.eK[c];
+        for (int q = 0; q < 2; ++q) {
+            const R pr = m[q][0] * ph.eK[0] + m[q][1] * ph.eK[1] + m[q][2] * ph.eK[2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h[q][c] += ph.cani * pr * ph.eK[c];
+            if (want_parts) hani_dot[q] = ph.cani * pr * pr;
+        }
     }
 }
 
@@ -245,50 +327,56 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
     __shared__ double red[kNT];
     const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
+    const bool vec = (g.nx & 1) == 0;
     if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
     double acc[5] = {0, 0, 0, 0, 0};
     for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        const int x0 = 2 * n;
+        if (x0 >= g.nx) continue;
+        const bool two = x0 + 1 < g.nx;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
-        for (int h = 0; h < 2; ++h) {
-            const int x = 2 * n + h;
-            if (x >= g.nx) break;
-            R m[3], hex[3], hdmi[3], hani[3], hd[3];
-            local_field<R>(f, g, x, y, z, ph, m, hex, hdmi, hani);
+        R m[2][3], hl[2][3], ex[2], dm[2], an[2], out[2][3];
+        local_field_pair<R>(f, g, x0, y, z, vec, two, ph, m, hl, ex, dm, an, energy != 0);
+        const long long id = ((long long)z * g.ny + y) * g.nx + x0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) hd[c] = has_demag ? demag_at<R>(buf, 3 * p + c, g.Lh, n, h) : (R)0;
-            const long long id = ((long long)z * g.ny + y) * g.nx + x;
+        for (int q = 0; q < 2; ++q) {
+            R hd[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) hd[c] = has_demag ? demag_at<R>(buf, 3 * p + c, g.Lh, n, q) : (R)0;
+            const bool live = q == 0 || two;
             if (energy) {
-                acc[0] += (double)dot3(m, hd);
-                acc[1] += (double)dot3(m, hex);
-                acc[2] += (double)dot3(m, hdmi);
-                acc[3] += (double)dot3(m, hani);
-                if (ph.terms & MAGX_ZEEMAN) acc[4] += (double)dot3(m, ph.hb);
+                if (live) {
+                    acc[0] += (double)dot3(m[q], hd);
+                    acc[1] += (double)ex[q];
+                    acc[2] += (double)dm[q];
+                    acc[3] += (double)an[q];
+                    if (ph.terms & MAGX_ZEEMAN) acc[4] += (double)dot3(m[q], ph.hb);
+                }
             } else {
-                R out[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    out[c] = hd[c] + hex[c] + hdmi[c] + hani[c];
-                    if (with_bias && (ph.terms & MAGX_ZEEMAN)) out[c] += ph.hb[c];
+                    out[q][c] = hd[c] + hl[q][c];
+                    if (with_bias && (ph.terms & MAGX_ZEEMAN)) out[q][c] += ph.hb[c];
                 }
-                store3(H, g.N, id, out);
-                if (sum_input) {
+                if (sum_input && live) {
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) acc[c] += (double)m[c];
+                    for (int c = 0; c < 3; ++c) acc[c] += (double)m[q][c];
                 }
             }
         }
+        if (!energy) store_pair(H, g.N, id, vec, two, out[0], out[1]);
     }
     if (energy) {
         for (int v = 0; v < 5; ++v) {
-            const double s = block_sum(acc[v], red);
-            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] = s;
+            const double sm = block_sum(acc[v], red);
+            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] = sm;
         }
     } else if (sum_input) {
         for (int v = 0; v < 3; ++v) {
-            const double s = block_sum(acc[v], red);
-            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] += s;
+            const double sm = block_sum(acc[v], red);
+            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] += sm;
         }
     }
 }
@@ -300,6 +388,7 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
+    const bool vec = (g.nx & 1) == 0;
     if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
     // classical RK4 tableau
     const R bw[4] = {(R)(1.0 / 6.0), (R)(1.0 / 3.0), (R)(1.0 / 3.0), (R)(1.0 / 6.0)};
@@ -310,64 +399,71 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
 #pragma unroll
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) keep[i][q][0] = keep[i][q][1] = keep[i][q][2] = (R)0;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        const int x0 = 2 * n;
+        if (x0 >= g.nx) continue;
+        const bool two = x0 + 1 < g.nx;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
+        const long long id = ((long long)z * g.ny + y) * g.nx + x0;
+        R ys[2][3], H[2][3], ex[2], dm[2], an[2];
+        local_field_pair<R>(a.yin, g, x0, y, z, vec, two, ph, ys, H, ex, dm, an, false);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int x = 2 * n + h;
-            keep[i][h][0] = keep[i][h][1] = keep[i][h][2] = (R)0;
-            if (x >= g.nx) continue;
-            R ys[3], hex[3], hdmi[3], hani[3], H[3], k[3];
-            local_field<R>(a.yin, g, x, y, z, ph, ys, hex, hdmi, hani);
+        for (int q = 0; q < 2; ++q)
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                H[c] = hex[c] + hdmi[c] + hani[c];
-                if (has_demag) H[c] += demag_at<R>(buf, 3 * p + c, g.Lh, n, h);
-                if (ph.terms & MAGX_ZEEMAN) H[c] += ph.hb[c];
+                if (has_demag) H[q][c] += demag_at<R>(buf, 3 * p + c, g.Lh, n, q);
+                if (ph.terms & MAGX_ZEEMAN) H[q][c] += ph.hb[c];
             }
-            const long long id = ((long long)z * g.ny + y) * g.nx + x;
-            if (a.tapeH) store3(a.tapeH, g.N, id, H);
-            if (a.tapeYin) store3(a.tapeYin, g.N, id, ys);
-            llg_rhs<R>(ys, H, ph.a, ph.alpha, k);
-            R mn[3];
-            if (s == 1) { mn[0] = ys[0]; mn[1] = ys[1]; mn[2] = ys[2]; }
-            else load3(a.mn, g.N, id, mn);
-            R xn[3];
-            if (s < 4) {
-                R acc[3];
-                if (s == 1) {
+        if (a.tapeH) store_pair(a.tapeH, g.N, id, vec, two, H[0], H[1]);
+        if (a.tapeYin) store_pair(a.tapeYin, g.N, id, vec, two, ys[0], ys[1]);
+        R k[2][3], mn[2][3], acc[2][3], xn[2][3], nrm[2];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) acc[c] = bw[0] * k[c];
+        for (int q = 0; q < 2; ++q) llg_rhs<R>(ys[q], H[q], ph.a, ph.alpha, k[q]);
+        if (s == 1) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) mn[q][c] = ys[q][c];
+        } else {
+            load_pair(a.mn, g.N, id, vec, two, mn[0], mn[1]);
+        }
+        if (s > 1) load_pair(a.acc, g.N, id, vec, two, acc[0], acc[1]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (s < 4) {
+                    acc[q][c] = (s == 1 ? (R)0 : acc[q][c]) + bw[s - 1] * k[q][c];
+                    xn[q][c] = mn[q][c] + cw[s] * a.dt * k[q][c];
                 } else {
-                    load3(a.acc, g.N, id, acc);
-#pragma unroll
-                    for (int c = 0; c < 3; ++c) acc[c] += bw[s - 1] * k[c];
+                    xn[q][c] = mn[q][c] + a.dt * (acc[q][c] + bw[3] * k[q][c]);
                 }
-                store3(a.acc, g.N, id, acc);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) xn[c] = mn[c] + cw[s] * a.dt * k[c];
-            } else {
-                R acc[3];
-                load3(a.acc, g.N, id, acc);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) xn[c] = mn[c] + a.dt * (acc[c] + bw[3] * k[c]);
             }
-            R nrm = (R)1;
+            nrm[q] = (R)1;
             if (norm) {
-                nrm = sqrt(dot3(xn, xn));
-                if (nrm > (R)0) {
-                    const R inv = (R)1 / nrm;
+                nrm[q] = sqrt(dot3(xn[q], xn[q]));
+                if (nrm[q] > (R)0) {
+                    const R inv = (R)1 / nrm[q];
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) xn[c] *= inv;
+                    for (int c = 0; c < 3; ++c) xn[q][c] *= inv;
                 }
             }
-            if (a.tapeNx) a.tapeNx[id] = nrm;
-            store3(a.yout, g.N, id, xn);
-            if (a.yout2) store3(a.yout2, g.N, id, xn);
+        }
+        if (s < 4) store_pair(a.acc, g.N, id, vec, two, acc[0], acc[1]);
+        if (a.tapeNx) {
+            if (vec) *reinterpret_cast<cx<R>*>(a.tapeNx + id) = mk<R>(nrm[0], nrm[1]);
+            else { a.tapeNx[id] = nrm[0]; if (two) a.tapeNx[id + 1] = nrm[1]; }
+        }
+        store_pair(a.yout, g.N, id, vec, two, xn[0], xn[1]);
+        if (a.yout2) store_pair(a.yout2, g.N, id, vec, two, xn[0], xn[1]);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) keep[i][h][c] = xn[c];
+        for (int c = 0; c < 3; ++c) {
+            keep[i][0][c] = xn[0][c];
+            keep[i][1][c] = two ? xn[1][c] : (R)0;
         }
     }
     if (!(a.want_next && has_demag)) return;
@@ -391,6 +487,7 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
     __shared__ double red[kNT];
     const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
+    const bool vec = (g.nx & 1) == 0;
     const bool norm = ph.renorm >= 1;
     const R b4 = (R)(1.0 / 6.0);
     double hs[3] = {0, 0, 0};
@@ -398,50 +495,59 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
 #pragma unroll
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) keep[i][q][0] = keep[i][q][1] = keep[i][q][2] = (R)0;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        const int x0 = 2 * n;
+        if (x0 >= g.nx) continue;
+        const bool two = x0 + 1 < g.nx;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
+        const long long id = ((long long)z * g.ny + y) * g.nx + x0;
+        R lam[2][3], xi[2][3], y5[2][3], y4[2][3], kap[2][3], mu[2][3];
+        load_pair(a.gm, g.N, id, vec, two, lam[0], lam[1]);
+        load_pair(a.y4, g.N, id, vec, two, y4[0], y4[1]);
+        if (norm) {
+            load_pair(a.y5, g.N, id, vec, two, y5[0], y5[1]);
+            R nx5[2];
+            nx5[0] = a.nx5[id];
+            nx5[1] = two ? a.nx5[id + 1] : (R)1;
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int x = 2 * n + h;
-            keep[i][h][0] = keep[i][h][1] = keep[i][h][2] = (R)0;
-            if (x >= g.nx) continue;
-            const long long id = ((long long)z * g.ny + y) * g.nx + x;
-            R lam[3], xi[3];
-            load3(a.gm, g.N, id, lam);
-            if (norm) {
-                R y5[3];
-                load3(a.y5, g.N, id, y5);
-                const R nx5 = a.nx5[id];
-                const R pl = dot3(y5, lam);
-                const R inv = nx5 > (R)0 ? (R)1 / nx5 : (R)1;
+            for (int q = 0; q < 2; ++q) {
+                const R pl = dot3(y5[q], lam[q]);
+                const R inv = nx5[q] > (R)0 ? (R)1 / nx5[q] : (R)1;
 #pragma unroll
-                for (int c = 0; c < 3; ++c) xi[c] = (lam[c] - y5[c] * pl) * inv;
-            } else {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) xi[c] = lam[c];
+                for (int c = 0; c < 3; ++c) xi[q][c] = (lam[q][c] - y5[q][c] * pl) * inv;
             }
-            store3(a.xi5, g.N, id, xi);
-            store3(a.gm, g.N, id, xi);
-            R kap[3], y4[3], mu[3];
+        } else {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) kap[c] = b4 * a.dt * xi[c];
-            store3(a.kap, g.N, id, kap);
-            load3(a.y4, g.N, id, y4);
-            rhs_mu<R>(y4, kap, ph.a, ph.alpha, mu);
-            store3(a.muout, g.N, id, mu);
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                hs[c] += (double)mu[c];
-                keep[i][h][c] = mu[c];
-            }
+                for (int c = 0; c < 3; ++c) xi[q][c] = lam[q][c];
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) kap[q][c] = b4 * a.dt * xi[q][c];
+            rhs_mu<R>(y4[q], kap[q], ph.a, ph.alpha, mu[q]);
+        }
+        store_pair(a.xi5, g.N, id, vec, two, xi[0], xi[1]);
+        store_pair(a.gm, g.N, id, vec, two, xi[0], xi[1]);
+        store_pair(a.kap, g.N, id, vec, two, kap[0], kap[1]);
+        store_pair(a.muout, g.N, id, vec, two, mu[0], mu[1]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const R m1 = two ? mu[1][c] : (R)0;
+            hs[c] += (double)mu[0][c] + (double)m1;
+            keep[i][0][c] = mu[0][c];
+            keep[i][1][c] = m1;
         }
     }
     if (ph.terms & MAGX_ZEEMAN) {
         for (int v = 0; v < 3; ++v) {
-            const double s = block_sum(hs[v], red);
-            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] += s;
+            const double sm = block_sum(hs[v], red);
+            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] += sm;
         }
     }
     if (!has_demag) return;
@@ -466,6 +572,7 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
     __shared__ double red[kNT];
     const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
+    const bool vec = (g.nx & 1) == 0;
     if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
     const R bw[4] = {(R)(1.0 / 6.0), (R)(1.0 / 3.0), (R)(1.0 / 3.0), (R)(1.0 / 6.0)};
     const R cw[4] = {(R)0, (R)0.5, (R)0.5, (R)1};
@@ -476,69 +583,86 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
 #pragma unroll
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) keep[i][q][0] = keep[i][q][1] = keep[i][q][2] = (R)0;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        const int x0 = 2 * n;
+        if (x0 >= g.nx) continue;
+        const bool two = x0 + 1 < g.nx;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
+        const long long id = ((long long)z * g.ny + y) * g.nx + x0;
+        R mu[2][3], Kmu[2][3], ex[2], dm[2], an[2];
+        local_field_pair<R>(a.mu, g, x0, y, z, vec, two, ph, mu, Kmu, ex, dm, an, false);
+        if (has_demag) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int x = 2 * n + h;
-            keep[i][h][0] = keep[i][h][1] = keep[i][h][2] = (R)0;
-            if (x >= g.nx) continue;
-            const long long id = ((long long)z * g.ny + y) * g.nx + x;
-            R mu[3], hex[3], hdmi[3], hani[3], Kmu[3];
-            local_field<R>(a.mu, g, x, y, z, ph, mu, hex, hdmi, hani);
+            for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                Kmu[c] = hex[c] + hdmi[c] + hani[c];
-                if (has_demag) Kmu[c] += demag_at<R>(buf, 3 * p + c, g.Lh, n, h);
-            }
-            R ys[3], Hs[3], kap[3];
-            load3(a.ys, g.N, id, ys);
-            load3(a.Hs, g.N, id, Hs);
-            load3(a.kap, g.N, id, kap);
-            // ybar = a [H x kappa + alpha (H (y.kappa) + kappa (y.H) - 2 y (H.kappa))] + K mu
-            R Hxk[3], yb[3];
-            cross3(Hs, kap, Hxk);
-            const R yk = dot3(ys, kap), yH = dot3(ys, Hs), Hk = dot3(Hs, kap);
+                for (int c = 0; c < 3; ++c) Kmu[q][c] += demag_at<R>(buf, 3 * p + c, g.Lh, n, q);
+        }
+        R ys[2][3], Hs[2][3], kap[2][3], lam[2][3], yb[2][3];
+        load_pair(a.ys, g.N, id, vec, two, ys[0], ys[1]);
+        load_pair(a.Hs, g.N, id, vec, two, Hs[0], Hs[1]);
+        load_pair(a.kap, g.N, id, vec, two, kap[0], kap[1]);
+        load_pair(a.gm, g.N, id, vec, two, lam[0], lam[1]);
+        // ybar = a [H x kappa + alpha (H (y.kappa) + kappa (y.H) - 2 y (H.kappa))] + K mu
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            R Hxk[3];
+            cross3(Hs[q], kap[q], Hxk);
+            const R yk = dot3(ys[q], kap[q]), yH = dot3(ys[q], Hs[q]), Hk = dot3(Hs[q], kap[q]);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
-                yb[c] = ph.a * (Hxk[c] + ph.alpha * (Hs[c] * yk + kap[c] * yH - (R)2 * ys[c] * Hk)) + Kmu[c];
-            R lam[3];
-            load3(a.gm, g.N, id, lam);
-            if (s > 1) {
-                R xi[3];
-                if (norm) {
-                    const R nxs = a.nxs[id];
-                    const R py = dot3(ys, yb);
-                    const R inv = nxs > (R)0 ? (R)1 / nxs : (R)1;
+                yb[q][c] = ph.a * (Hxk[c] + ph.alpha * (Hs[q][c] * yk + kap[q][c] * yH - (R)2 * ys[q][c] * Hk)) +
+                           Kmu[q][c];
+        }
+        if (s > 1) {
+            R xi[2][3], x5[2][3], kp[2][3], yp[2][3], mup[2][3];
+            if (norm) {
+                R nxs[2];
+                nxs[0] = a.nxs[id];
+                nxs[1] = two ? a.nxs[id + 1] : (R)1;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) xi[c] = (yb[c] - ys[c] * py) * inv;
-                } else {
+                for (int q = 0; q < 2; ++q) {
+                    const R py = dot3(ys[q], yb[q]);
+                    const R inv = nxs[q] > (R)0 ? (R)1 / nxs[q] : (R)1;
 #pragma unroll
-                    for (int c = 0; c < 3; ++c) xi[c] = yb[c];
-                }
-#pragma unroll
-                for (int c = 0; c < 3; ++c) lam[c] += xi[c];
-                store3(a.gm, g.N, id, lam);
-                R x5[3], kp[3], yp[3], mup[3];
-                load3(a.xi5, g.N, id, x5);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) kp[c] = bw[s - 2] * a.dt * x5[c] + cw[s - 1] * a.dt * xi[c];
-                store3(a.kap, g.N, id, kp);
-                load3(a.yprev, g.N, id, yp);
-                rhs_mu<R>(yp, kp, ph.a, ph.alpha, mup);
-                store3(a.muout, g.N, id, mup);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    hs[c] += (double)mup[c];
-                    keep[i][h][c] = mup[c];
+                    for (int c = 0; c < 3; ++c) xi[q][c] = (yb[q][c] - ys[q][c] * py) * inv;
                 }
             } else {
 #pragma unroll
-                for (int c = 0; c < 3; ++c) lam[c] += yb[c];
-                store3(a.gm, g.N, id, lam);
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) xi[q][c] = yb[q][c];
             }
+            load_pair(a.xi5, g.N, id, vec, two, x5[0], x5[1]);
+            load_pair(a.yprev, g.N, id, vec, two, yp[0], yp[1]);
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    lam[q][c] += xi[q][c];
+                    kp[q][c] = bw[s - 2] * a.dt * x5[q][c] + cw[s - 1] * a.dt * xi[q][c];
+                }
+                rhs_mu<R>(yp[q], kp[q], ph.a, ph.alpha, mup[q]);
+            }
+            store_pair(a.gm, g.N, id, vec, two, lam[0], lam[1]);
+            store_pair(a.kap, g.N, id, vec, two, kp[0], kp[1]);
+            store_pair(a.muout, g.N, id, vec, two, mup[0], mup[1]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const R m1 = two ? mup[1][c] : (R)0;
+                hs[c] += (double)mup[0][c] + (double)m1;
+                keep[i][0][c] = mup[0][c];
+                keep[i][1][c] = m1;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) lam[q][c] += yb[q][c];
+            store_pair(a.gm, g.N, id, vec, two, lam[0], lam[1]);
         }
     }
     if (s > 1 && (ph.terms & MAGX_ZEEMAN)) {
