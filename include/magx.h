@@ -19,6 +19,13 @@
  *  - Vector fields (m, H, dm/dt, gradients) are contiguous arrays of the
  *    context's element type (float for MAGX_F32, double for MAGX_F64) laid out
  *    (3, nz, ny, nx): component-major, then z, then y, with x fastest.
+ *  - A context made by magx_tensor_init_batched with nbatch = B advances B
+ *    independent systems of the same grid that share one tensor spectrum
+ *    (an ensemble of initial states or bias fields).  Every vector field is
+ *    then (B, 3, nz, ny, nx), every per-system output (energies, gHbias)
+ *    holds B consecutive records, and every size magx_sizes_batched reports
+ *    covers the whole batch.  Member b's results equal those of a B = 1
+ *    context run on member b alone, bit for bit.
  *  - All pointers named "device" point to memory on the context's GPU, owned
  *    by the caller.  The library never allocates or frees device memory; the
  *    sizes it needs are reported by magx_sizes().
@@ -104,6 +111,10 @@ typedef struct magx_ctx magx_ctx;
 
 /* Sizes of every buffer for grid g and element type dt.  Host only. */
 int magx_sizes(const magx_grid* g, magx_dtype dt, magx_size_info* out);
+/* The same for a batch of nbatch >= 1 systems (spectrum and init scratch do
+ * not grow with nbatch; fields, workspace and tape do).  MAGX_ESIZE if the
+ * batch's spectral intermediates exceed 2^31 elements. */
+int magx_sizes_batched(const magx_grid* g, magx_dtype dt, int nbatch, magx_size_info* out);
 
 /* Creates a context and builds the demag tensor spectrum (Section II-B: the
  * real-space tensor on the extended grid of twice the problem size, then its
@@ -117,6 +128,17 @@ int magx_sizes(const magx_grid* g, magx_dtype dt, magx_size_info* out);
  * On success *ctx is set; on failure *ctx is NULL. */
 int magx_tensor_init(magx_ctx** ctx, const magx_grid* g, magx_dtype dt,
                      void* spectrum, void* scratch, void* stream);
+/* As magx_tensor_init, for a batch of nbatch >= 1 systems of grid g. */
+int magx_tensor_init_batched(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, int nbatch,
+                             void* spectrum, void* scratch, void* stream);
+
+/* Per-system bias fields: hbias (device, nbatch x 3 elements of the context
+ * type, A/m, owned by the caller and kept valid while in use) replaces
+ * p->Hbias for member b by hbias[3b..3b+2] in every later call; NULL goes
+ * back to p->Hbias for all members.  Host only; enqueues nothing. */
+int magx_set_member_bias(magx_ctx* ctx, const void* hbias);
+/* Number of systems of a context (host), -1 for NULL. */
+int magx_ctx_batch(const magx_ctx* ctx);
 
 /* Effective field, Eq. (2), of the unit field m (device, read) into H (device,
  * written), in A/m.  `ws`: device workspace of workspace_bytes. */

@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2,
 template <typename R, int EM>
 __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
                                                     int nz, int lgPz, int Py, int Hx, int Hy, int Hz, int Sx,
-                                                    int lgT, int ntx) {
+                                                    int lgT, int ntx, int blocks_per_member) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
@@ -81,7 +81,9 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     R* tl = reinterpret_cast<R*>(smem_raw + (size_t)Pz * T3 * sizeof(cx<R>));
     // logical order 0, 1, Py-1, 2, Py-2, ..., Py/2: the mirrored rows ky and
     // Py-ky read the same tensor octant rows one after the other on one XCD
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int lbg = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int mb = lbg / blocks_per_member;            // member of a batch of systems
+    const int lb = lbg - mb * blocks_per_member;
     const int tx = lb % ntx;
     const int u = lb / ntx;
     const int ky = (u & 1) ? (u + 1) >> 1 : (u == 0 ? 0 : Py - (u >> 1));
@@ -111,7 +113,7 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     }
     const int plane_stride = Py * Sx;     // one z row of X2 (< 2^23, checked in the plan)
     const int comp_stride = nz * plane_stride;
-    cx<R>* base = X2 + (long long)ky * Sx + kx0;
+    cx<R>* base = X2 + (long long)mb * 3 * comp_stride + (long long)ky * Sx + kx0;
     const int ncol = min(T, Hx - kx0);
     // rows z >= nz are the zero padding (never read) and are never written back
     auto load = [&](int b, int j) -> cx<R> {
@@ -159,7 +161,7 @@ template <typename R>
 hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
     const int lgT = ilog2(pl.ty);
     const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
-    const unsigned blocks = (unsigned)(ntx * 3 * pl.nz);
+    const unsigned blocks = (unsigned)(ntx * 3 * pl.nz * pl.nbatch);
     const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
     if (em_big((long long)pl.Py * pl.ty))
         hipLaunchKernelGGL((yfwd_kernel<R, 32>), dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
@@ -174,7 +176,7 @@ template <typename R>
 hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
     const int lgT = ilog2(pl.ty);
     const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
-    const unsigned blocks = (unsigned)(ntx * 3 * pl.nz);
+    const unsigned blocks = (unsigned)(ntx * 3 * pl.nz * pl.nbatch);
     const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
     if (em_big((long long)pl.Py * pl.ty))
         hipLaunchKernelGGL((yinv_kernel<R, 32>), dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X2),
@@ -189,16 +191,17 @@ template <typename R>
 hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s) {
     const int lgT = ilog2(pl.tz);
     const int ntx = (pl.Hx + pl.tz - 1) / pl.tz;
-    const unsigned blocks = (unsigned)(ntx * pl.Py);
+    const int bpm = ntx * pl.Py;
+    const unsigned blocks = (unsigned)(bpm * pl.nbatch);
     const size_t lds = (size_t)3 * pl.Pz * pl.tz * sizeof(cx<R>) + (size_t)6 * (pl.Pz / 2 + 1) * pl.tz * sizeof(R);
     if (em_big(3LL * pl.Pz * pl.tz))
         hipLaunchKernelGGL((zconv_kernel<R, 32>), dim3(blocks), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
                            static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hy, pl.Hz, pl.Sx, lgT,
-                           ntx);
+                           ntx, bpm);
     else
         hipLaunchKernelGGL((zconv_kernel<R, 16>), dim3(blocks), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
                            static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hy, pl.Hz, pl.Sx, lgT,
-                           ntx);
+                           ntx, bpm);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ using namespace magx;
 struct magx_ctx {
     Plan pl;
     void* spectrum;
+    const void* hbias_members;   // optional per-member bias fields (device, nbatch x 3)
     long long heff_count;
     int device;
     // launch timing of one kernel family (diagnostics)
@@ -68,8 +69,8 @@ static int pow2_floor(long long v) {
     return p;
 }
 
-int make_plan(const magx_grid* g, magx_dtype dt, Plan* pl) {
-    if (!g || !pl) return MAGX_EINVAL;
+int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
+    if (!g || !pl || nbatch < 1) return MAGX_EINVAL;
     if (dt != MAGX_F32 && dt != MAGX_F64) return MAGX_EDTYPE;
     if (g->nx < 1 || g->ny < 1 || g->nz < 1) return MAGX_EINVAL;
     if (!(g->dx > 0.0) || !(g->dy > 0.0) || !(g->dz > 0.0) || !std::isfinite(g->dx) || !std::isfinite(g->dy) ||
@@ -92,11 +93,13 @@ int make_plan(const magx_grid* g, magx_dtype dt, Plan* pl) {
     p.Lh = p.Px / 2; p.lgLh = p.lgPx - 1;
     p.Hx = p.Lh + 1; p.Hy = p.Py / 2 + 1; p.Hz = p.Pz / 2 + 1;
     p.Sx = (p.Hx + 15) / 16 * 16;
-    // 32-bit element offsets inside the spectral arrays, 24-bit row strides
-    if (3LL * p.nz * p.Py * p.Sx >= (1LL << 31) || (long long)p.Py * p.Sx >= (1LL << 23) ||
+    // 32-bit element offsets inside the spectral arrays (whole batch), 24-bit row strides
+    p.nbatch = nbatch;
+    if (3LL * nbatch * p.nz * p.Py * p.Sx >= (1LL << 31) || (long long)p.Py * p.Sx >= (1LL << 23) ||
         6LL * p.Hz * p.Hy * p.Sx >= (1LL << 31))
         return MAGX_ESIZE;
     p.ncell = (long long)p.nx * p.ny * p.nz;
+    if (3LL * nbatch * p.ncell >= (1LL << 31)) return MAGX_ESIZE;
     p.ty = std::min(16, pow2_floor(lds_cplx / p.Py));
     // tuning override of the y tile width (power of two within the LDS budget)
     if (const char* e = std::getenv("MAGX_TILE_Y")) {
@@ -121,20 +124,22 @@ int make_plan(const magx_grid* g, magx_dtype dt, Plan* pl) {
     p.np = std::max(1, 1024 / p.Lh);
     const int npen = p.ny * p.nz;
     if (p.np > npen) p.np = npen;
-    p.pencil_blocks = (npen + p.np - 1) / p.np;
+    // pencil blocks never straddle two members (the last one of a member may be ragged)
+    p.blocks_per_member = (npen + p.np - 1) / p.np;
+    p.pencil_blocks = nbatch * p.blocks_per_member;
     const size_t es = (size_t)p.esize;
-    const long long N = p.ncell;
+    const long long N = p.ncell * nbatch;
     p.field_bytes = (size_t)3 * N * es;
     size_t off = 0;
-    p.off_x1 = off; off = align256(off + (size_t)3 * p.nz * p.ny * p.Sx * 2 * es);
-    p.off_x2 = off; off = align256(off + (size_t)3 * p.nz * p.Py * p.Sx * 2 * es);
+    p.off_x1 = off; off = align256(off + (size_t)3 * nbatch * p.nz * p.ny * p.Sx * 2 * es);
+    p.off_x2 = off; off = align256(off + (size_t)3 * nbatch * p.nz * p.Py * p.Sx * 2 * es);
     for (int i = 0; i < 4; ++i) { p.off_f[i] = off; off = align256(off + p.field_bytes); }
     p.off_part = off; off = align256(off + (size_t)p.pencil_blocks * 8 * sizeof(double));
     p.ws_bytes = off;
     p.tape_step_bytes = (size_t)28 * N * es;
     p.tape_extra_bytes = (size_t)3 * N * es;
     p.spectrum_bytes = (size_t)6 * p.Hz * p.Hy * p.Sx * es;
-    const long long a1 = 6 * N, a2 = 6LL * p.Hy * p.Hx * p.nz;
+    const long long a1 = 6 * p.ncell, a2 = 6LL * p.Hy * p.Hx * p.nz;
     p.scratch_a_elems = std::max(a1, a2);
     p.scratch_b_elems = 6LL * p.Hx * p.nz * p.ny;
     p.scratch_bytes = (size_t)(p.scratch_a_elems + p.scratch_b_elems) * sizeof(double);
@@ -157,8 +162,9 @@ static int check_params(const magx_params* p) {
 }
 
 template <typename R>
-static Phys<R> make_phys(const Plan& pl, const magx_params* p) {
+static Phys<R> make_phys(const Plan& pl, const magx_params* p, const void* hbias_members = nullptr) {
     Phys<R> ph{};
+    ph.hbm = static_cast<const R*>(hbias_members);
     const double mu0Ms = p->mu0 * p->Ms;
     ph.Ms = (R)p->Ms;
     ph.cex = (R)(2.0 * p->A / mu0Ms);
@@ -228,7 +234,7 @@ template <typename R>
 static int do_heff(magx_ctx* c, const R* m, const magx_params* p, R* H, void* ws, hipStream_t s, int energy,
                    double* e_out) {
     const Plan& pl = c->pl;
-    Phys<R> ph = make_phys<R>(pl, p);
+    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
     void* X1 = bptr(ws, pl.off_x1);
     double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
     if (p->terms & MAGX_DEMAG) {
@@ -247,7 +253,8 @@ static int do_heff(magx_ctx* c, const R* m, const magx_params* p, R* H, void* ws
         const double V = pl.dx * pl.dy * pl.dz;
         const double pref = -0.5 * p->mu0 * p->Ms * V;
         const double vku = (p->terms & MAGX_ANIS) ? (double)pl.ncell * V * p->Ku : 0.0;
-        if (launch_energy_finish(part, pl.pencil_blocks, pref, vku, e_out, s) != hipSuccess) return MAGX_EHIP;
+        if (launch_energy_finish(part, pl.nbatch, pl.blocks_per_member, pref, vku, e_out, s) != hipSuccess)
+            return MAGX_EHIP;
     }
     return MAGX_OK;
 }
@@ -269,12 +276,12 @@ template <typename R>
 static int do_step(magx_ctx* c, R* m, const magx_params* p, double dt, int nsteps, R* tape, void* ws,
                    hipStream_t s) {
     const Plan& pl = c->pl;
-    Phys<R> ph = make_phys<R>(pl, p);
+    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
     const bool demag = (p->terms & MAGX_DEMAG) != 0;
     void* X1 = bptr(ws, pl.off_x1);
     R* acc = reinterpret_cast<R*>(bptr(ws, pl.off_f[0]));
     R* ybuf[2] = {reinterpret_cast<R*>(bptr(ws, pl.off_f[1])), reinterpret_cast<R*>(bptr(ws, pl.off_f[2]))};
-    TapeView<R> tv{tape, pl.ncell, nsteps};
+    TapeView<R> tv{tape, pl.ncell * pl.nbatch, nsteps};
     if (demag) {
         ProfScope ps(c, kProfXfwd, s);
         if (launch_xfwd<R>(pl, m, X1, s) != hipSuccess) return MAGX_EHIP;
@@ -310,14 +317,14 @@ template <typename R>
 static int do_step_backward(magx_ctx* c, const R* tape, int nsteps, const magx_params* p, double dt, R* gm,
                             R* gHbias, void* ws, hipStream_t s, bool fresh = true, bool finish = true) {
     const Plan& pl = c->pl;
-    Phys<R> ph = make_phys<R>(pl, p);
+    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
     const bool demag = (p->terms & MAGX_DEMAG) != 0;
     void* X1 = bptr(ws, pl.off_x1);
     R* xi5 = reinterpret_cast<R*>(bptr(ws, pl.off_f[0]));
     R* kap = reinterpret_cast<R*>(bptr(ws, pl.off_f[1]));
     R* mub[2] = {reinterpret_cast<R*>(bptr(ws, pl.off_f[2])), reinterpret_cast<R*>(bptr(ws, pl.off_f[3]))};
     double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
-    TapeView<R> tv{const_cast<R*>(tape), pl.ncell, nsteps};
+    TapeView<R> tv{const_cast<R*>(tape), pl.ncell * pl.nbatch, nsteps};
     // per-block double partials of dL/dH_bias; a checkpointed rollout keeps
     // them across segments so the summation order does not depend on ckpt
     if (fresh && launch_fill_zero(part, (long long)pl.pencil_blocks * 8, s) != hipSuccess) return MAGX_EHIP;
@@ -357,7 +364,8 @@ static int do_step_backward(magx_ctx* c, const R* tape, int nsteps, const magx_p
         }
     }
     if (finish && (p->terms & MAGX_ZEEMAN)) {
-        if (launch_reduce_partials<R>(part, pl.pencil_blocks, 3, gHbias, fresh ? 1 : 0, s) != hipSuccess)
+        if (launch_reduce_partials<R>(part, pl.nbatch, pl.blocks_per_member, 3, gHbias, fresh ? 1 : 0, s) !=
+            hipSuccess)
             return MAGX_EHIP;
     }
     return MAGX_OK;
@@ -367,7 +375,7 @@ template <typename R>
 static int do_heff_backward(magx_ctx* c, const R* gH, const magx_params* p, R* gm, R* gHbias, void* ws,
                             hipStream_t s) {
     const Plan& pl = c->pl;
-    Phys<R> ph = make_phys<R>(pl, p);
+    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
     void* X1 = bptr(ws, pl.off_x1);
     double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
     if (launch_fill_zero(part, (long long)pl.pencil_blocks * 8, s) != hipSuccess) return MAGX_EHIP;
@@ -378,7 +386,8 @@ static int do_heff_backward(magx_ctx* c, const R* gH, const magx_params* p, R* g
     }
     const int sum_input = (p->terms & MAGX_ZEEMAN) ? 1 : 0;
     if (launch_field<R>(pl, ph, X1, gH, gm, 0, 0, sum_input, part, s) != hipSuccess) return MAGX_EHIP;
-    if (launch_reduce_partials<R>(part, pl.pencil_blocks, 3, gHbias, 0, s) != hipSuccess) return MAGX_EHIP;
+    if (launch_reduce_partials<R>(part, pl.nbatch, pl.blocks_per_member, 3, gHbias, 0, s) != hipSuccess)
+        return MAGX_EHIP;
     return MAGX_OK;
 }
 
@@ -387,10 +396,10 @@ static int do_heff_backward(magx_ctx* c, const R* gH, const magx_params* p, R* g
 // ---------------------------------------------------------------------------------
 extern "C" {
 
-int magx_sizes(const magx_grid* g, magx_dtype dt, magx_size_info* out) {
+int magx_sizes_batched(const magx_grid* g, magx_dtype dt, int nbatch, magx_size_info* out) {
     if (!out) return MAGX_EINVAL;
     Plan pl;
-    int rc = make_plan(g, dt, &pl);
+    int rc = make_plan(g, dt, nbatch, &pl);
     if (rc) return rc;
     out->spectrum_bytes = pl.spectrum_bytes;
     out->init_scratch_bytes = pl.scratch_bytes;
@@ -401,13 +410,17 @@ int magx_sizes(const magx_grid* g, magx_dtype dt, magx_size_info* out) {
     return MAGX_OK;
 }
 
-int magx_tensor_init(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, void* spectrum, void* scratch,
-                     void* stream) {
+int magx_sizes(const magx_grid* g, magx_dtype dt, magx_size_info* out) {
+    return magx_sizes_batched(g, dt, 1, out);
+}
+
+int magx_tensor_init_batched(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, int nbatch, void* spectrum,
+                             void* scratch, void* stream) {
     if (!ctx) return MAGX_EINVAL;
     *ctx = nullptr;
     if (!spectrum || !scratch) return MAGX_EINVAL;
     Plan pl;
-    int rc = make_plan(g, dt, &pl);
+    int rc = make_plan(g, dt, nbatch, &pl);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int dev = 0;
@@ -418,6 +431,7 @@ int magx_tensor_init(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, void* sp
     if (!c) return MAGX_EINVAL;
     c->pl = pl;
     c->spectrum = spectrum;
+    c->hbias_members = nullptr;
     c->heff_count = 0;
     c->device = dev;
     c->prof_kind = 0;
@@ -425,6 +439,19 @@ int magx_tensor_init(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, void* sp
     *ctx = c;
     return MAGX_OK;
 }
+
+int magx_tensor_init(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, void* spectrum, void* scratch,
+                     void* stream) {
+    return magx_tensor_init_batched(ctx, g, dt, 1, spectrum, scratch, stream);
+}
+
+int magx_set_member_bias(magx_ctx* ctx, const void* hbias) {
+    if (!ctx) return MAGX_EINVAL;
+    ctx->hbias_members = hbias;
+    return MAGX_OK;
+}
+
+int magx_ctx_batch(const magx_ctx* ctx) { return ctx ? ctx->pl.nbatch : -1; }
 
 int magx_heff(magx_ctx* ctx, const void* m, const magx_params* p, void* H, void* ws, void* stream) {
     if (!ctx || !m || !H || !ws) return MAGX_EINVAL;
@@ -508,7 +535,7 @@ int magx_rollout_forward(magx_ctx* ctx, void* m, const magx_params* p, double dt
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t fb = ctx->pl.field_bytes;
-    const long long n3 = 3 * ctx->pl.ncell;
+    const long long n3 = 3 * ctx->pl.ncell * ctx->pl.nbatch;
     for (int n0 = 0, seg = 0; n0 < nsteps; n0 += ckpt, ++seg) {
         void* slot = bptr(ckpt_store, (size_t)seg * fb);
         hipError_t e = ctx->pl.dtype == MAGX_F32
@@ -534,7 +561,7 @@ int magx_rollout_backward(magx_ctx* ctx, const void* ckpt_store, const magx_para
     if (launch_fill_zero(part, (long long)pl.pencil_blocks * 8, s) != hipSuccess) return MAGX_EHIP;
     hipError_t e;
     const size_t fb = pl.field_bytes;
-    const long long n3 = 3 * pl.ncell;
+    const long long n3 = 3 * pl.ncell * pl.nbatch;
     const int nseg = nsteps == 0 ? 0 : (nsteps + ckpt - 1) / ckpt;
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int n0 = seg * ckpt;
@@ -554,10 +581,11 @@ int magx_rollout_backward(magx_ctx* ctx, const void* ckpt_store, const magx_para
                                             false);
         if (rc) return rc;
     }
-    // gHbias = sum over blocks of the partials (0 without a Zeeman term)
+    // gHbias = sum over each member's blocks of the partials (0 without a Zeeman term)
+    const int nb = pl.nbatch, bpm = pl.blocks_per_member;
     e = pl.dtype == MAGX_F32
-            ? launch_reduce_partials<float>(part, pl.pencil_blocks, 3, static_cast<float*>(gHbias), 0, s)
-            : launch_reduce_partials<double>(part, pl.pencil_blocks, 3, static_cast<double*>(gHbias), 0, s);
+            ? launch_reduce_partials<float>(part, nb, bpm, 3, static_cast<float*>(gHbias), 0, s)
+            : launch_reduce_partials<double>(part, nb, bpm, 3, static_cast<double*>(gHbias), 0, s);
     return e == hipSuccess ? MAGX_OK : MAGX_EHIP;
 }
 

@@ -25,7 +25,9 @@ struct Plan {
     int Px, Py, Pz, lgPx, lgPy, lgPz;
     int Lh, lgLh;               // Px/2: length of the half-size complex FFT of the x pass
     int Hx, Hy, Hz, Sx;
-    long long ncell;
+    long long ncell;            // cells of one member
+    int nbatch;                 // independent systems sharing the tensor spectrum
+    int blocks_per_member;      // pencil blocks of one member (np divides ny*nz)
     // tensor build scratch (doubles): slab A = max(octant, y-pass output), then slab B
     long long scratch_a_elems, scratch_b_elems;
     // column tiles of the y and z passes, pencils per block of the x passes
@@ -38,7 +40,7 @@ struct Plan {
     size_t spectrum_bytes, scratch_bytes;
 };
 
-int make_plan(const magx_grid* g, magx_dtype dt, Plan* pl);
+int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl);
 
 // Physical constants prepared for the kernels (element type R).
 template <typename R>
@@ -50,6 +52,7 @@ struct Phys {
     R cani;          // 2Ku/(mu0 Ms) (Eq. (5))
     R eK[3];
     R hb[3];         // bias field (Zeeman)
+    const R* hbm;    // optional per-member bias fields (nbatch x 3, device); overrides hb
     R a;             // mu0 gamma/(1+alpha^2) (Eq. (1))
     R alpha;
     R idx2, idy2, idz2;   // 1/d^2
@@ -132,12 +135,13 @@ hipError_t launch_bstart(const Plan& pl, const Phys<R>& ph, void* X1, const Star
 template <typename R>
 hipError_t launch_rhs(const Plan& pl, const Phys<R>& ph, const R* m, const R* H, R* out, hipStream_t s);
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
-// out[c] (+)= sum over blocks of partials[b*8 + c], c < nval, fixed order.
+// Per member b: out[b*nval + c] (+)= sum over its blocks of partials[lb*8 + c]
+// (logical block index lb, members own contiguous ranges), fixed order.
 template <typename R>
-hipError_t launch_reduce_partials(const double* partials, int nblocks, int nval, R* out, int accumulate,
-                                  hipStream_t s);
-hipError_t launch_energy_finish(const double* partials, int nblocks, double pref, double vku_total,
-                                double* e_out, hipStream_t s);
+hipError_t launch_reduce_partials(const double* partials, int nbatch, int blocks_per_member, int nval, R* out,
+                                  int accumulate, hipStream_t s);
+hipError_t launch_energy_finish(const double* partials, int nbatch, int blocks_per_member, double pref,
+                                double vku_member, double* e_out, hipStream_t s);
 template <typename R>
 hipError_t launch_copy(const R* src, R* dst, long long n, hipStream_t s);
 

@@ -30,15 +30,16 @@ template <bool BIG> constexpr int pemax() { return BIG ? 32 : 16; }
 template <bool BIG> constexpr int maxslot() { return BIG ? 8 : 4; }
 
 struct PG {
-    int nx, ny, nz, Lh, lgLh, Hx, Sx, lgPx, np, npen_total;
-    long long N;
+    int nx, ny, nz, Lh, lgLh, Hx, Sx, lgPx, np, npen_total;   // npen_total: pencils of one member
+    int bpm;                                                 // blocks per member
+    long long N;                                             // cells of one member
 };
 
 static PG make_pg(const Plan& pl) {
     PG g;
     g.nx = pl.nx; g.ny = pl.ny; g.nz = pl.nz;
     g.Lh = pl.Lh; g.lgLh = pl.lgLh; g.Hx = pl.Hx; g.Sx = pl.Sx; g.lgPx = pl.lgPx;
-    g.np = pl.np; g.npen_total = pl.ny * pl.nz; g.N = pl.ncell;
+    g.np = pl.np; g.npen_total = pl.ny * pl.nz; g.bpm = pl.blocks_per_member; g.N = pl.ncell;
     return g;
 }
 
@@ -228,7 +229,7 @@ __device__ __forceinline__ void pen_coords(const PG& g, int pen, int& y, int& z)
 // Inverse x pass: Y1 rows -> real lines; afterwards the real value of cell x
 // of line l is buf[l*Lh + x/2].x (x even) or .y (x odd).
 template <typename R, bool BIG>
-__device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int pen0, int npen) {
+__device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int mb, int pen0, int npen) {
     const int Lh = g.Lh;
     const int twsh = kTwLog - g.lgPx;
     // split step of the half-length inverse, computed while the first FFT
@@ -237,7 +238,7 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int pen0, in
         const int p = line / 3, c = line - 3 * p;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
-        const cx<R>* row = Y1 + (((c * g.nz + z) * g.ny + y) * g.Sx);
+        const cx<R>* row = Y1 + ((((mb * 3 + c) * g.nz + z) * g.ny + y) * g.Sx);
         const cx<R> a = row[k];
         const cx<R> b = cconj<R>(row[Lh - k]);
         const cx<R> A = cadd<R>(a, b);
@@ -251,7 +252,7 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int pen0, in
 // Forward x pass: buf holds packed lines z[n] = x[2n] + i x[2n+1]; writes the
 // Hx-column half spectrum of every line to X1.
 template <typename R, bool BIG>
-__device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int pen0, int npen) {
+__device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int mb, int pen0, int npen) {
     const int Lh = g.Lh;
     const int twsh = kTwLog - g.lgPx;
     auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
@@ -270,7 +271,7 @@ __device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int pen0, int npen
         const cx<R> D = csub<R>(Zk, Zm);
         const cx<R> O = mk<R>(half * D.y, -half * D.x);       // (Zk - Zm) / (2i)
         const cx<R> X = cadd<R>(E, cmul<R>(tw_fwd<R>(k << twsh), O));
-        X1[((c * g.nz + z) * g.ny + y) * g.Sx + k] = X;
+        X1[(((mb * 3 + c) * g.nz + z) * g.ny + y) * g.Sx + k] = X;
     }
 }
 
@@ -298,8 +299,13 @@ template <typename R, bool BIG>
 __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R>* __restrict__ X1, PG g) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
-    const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
+    // logical block -> member mb and its first pencil; members own contiguous block ranges
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int mb = lb / g.bpm;
+    const int pen0 = (lb - mb * g.bpm) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
+    const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
+    f += mo;
     for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
         int y, z;
@@ -313,7 +319,7 @@ __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R
             buf[(3 * p + c) * g.Lh + n] = mk<R>(a, b);
         }
     }
-    r2c_lines<R, BIG>(buf, X1, g, pen0, npen);
+    r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 
 // mode: 0 -> write H (with bias if with_bias); 1 -> energy partials (m.H_term)
@@ -325,10 +331,19 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
-    const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
+    // logical block -> member mb and its first pencil; members own contiguous block ranges
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int mb = lb / g.bpm;
+    const int pen0 = (lb - mb * g.bpm) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
+    const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
+    f += mo;
+    if (H) H += mo;
+    R hbv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) hbv[c] = ph.hbm ? ph.hbm[mb * 3 + c] : ph.hb[c];
     const bool vec = (g.nx & 1) == 0;
-    if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
+    if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, mb, pen0, npen);
     double acc[5] = {0, 0, 0, 0, 0};
     for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
@@ -352,13 +367,13 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
                     acc[1] += (double)ex[q];
                     acc[2] += (double)dm[q];
                     acc[3] += (double)an[q];
-                    if (ph.terms & MAGX_ZEEMAN) acc[4] += (double)dot3(m[q], ph.hb);
+                    if (ph.terms & MAGX_ZEEMAN) acc[4] += (double)dot3(m[q], hbv);
                 }
             } else {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     out[q][c] = hd[c] + hl[q][c];
-                    if (with_bias && (ph.terms & MAGX_ZEEMAN)) out[q][c] += ph.hb[c];
+                    if (with_bias && (ph.terms & MAGX_ZEEMAN)) out[q][c] += hbv[c];
                 }
                 if (sum_input && live) {
 #pragma unroll
@@ -371,12 +386,12 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
     if (energy) {
         for (int v = 0; v < 5; ++v) {
             const double sm = block_sum(acc[v], red);
-            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] = sm;
+            if (threadIdx.x == 0) partials[lb * 8 + v] = sm;
         }
     } else if (sum_input) {
         for (int v = 0; v < 3; ++v) {
             const double sm = block_sum(acc[v], red);
-            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] += sm;
+            if (threadIdx.x == 0) partials[lb * 8 + v] += sm;
         }
     }
 }
@@ -386,10 +401,26 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
                                                     Phys<R> ph, StageArgs<R> a, int has_demag) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
-    const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
+    // logical block -> member mb and its first pencil; members own contiguous block ranges
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int mb = lb / g.bpm;
+    const int pen0 = (lb - mb * g.bpm) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
+    const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
+    const long long mo1 = (long long)mb * g.N;      // member offset of scalar fields
+    a.yin += mo;
+    a.mn += mo;
+    a.acc += mo;
+    a.yout += mo;
+    if (a.yout2) a.yout2 += mo;
+    if (a.tapeH) a.tapeH += mo;
+    if (a.tapeYin) a.tapeYin += mo;
+    if (a.tapeNx) a.tapeNx += mo1;
+    R hbv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) hbv[c] = ph.hbm ? ph.hbm[mb * 3 + c] : ph.hb[c];
     const bool vec = (g.nx & 1) == 0;
-    if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
+    if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, mb, pen0, npen);
     // classical RK4 tableau
     const R bw[4] = {(R)(1.0 / 6.0), (R)(1.0 / 3.0), (R)(1.0 / 3.0), (R)(1.0 / 6.0)};
     const R cw[4] = {(R)0, (R)0.5, (R)0.5, (R)1};
@@ -416,7 +447,7 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 if (has_demag) H[q][c] += demag_at<R>(buf, 3 * p + c, g.Lh, n, q);
-                if (ph.terms & MAGX_ZEEMAN) H[q][c] += ph.hb[c];
+                if (ph.terms & MAGX_ZEEMAN) H[q][c] += hbv[c];
             }
         if (a.tapeH) store_pair(a.tapeH, g.N, id, vec, two, H[0], H[1]);
         if (a.tapeYin) store_pair(a.tapeYin, g.N, id, vec, two, ys[0], ys[1]);
@@ -476,7 +507,7 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
 #pragma unroll
         for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
     }
-    r2c_lines<R, BIG>(buf, X1, g, pen0, npen);
+    r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 
 template <typename R, bool BIG>
@@ -485,8 +516,20 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
-    const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
+    // logical block -> member mb and its first pencil; members own contiguous block ranges
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int mb = lb / g.bpm;
+    const int pen0 = (lb - mb * g.bpm) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
+    const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
+    const long long mo1 = (long long)mb * g.N;      // member offset of scalar fields
+    a.gm += mo;
+    a.y5 += mo;
+    a.y4 += mo;
+    a.xi5 += mo;
+    a.kap += mo;
+    a.muout += mo;
+    a.nx5 += mo1;
     const bool vec = (g.nx & 1) == 0;
     const bool norm = ph.renorm >= 1;
     const R b4 = (R)(1.0 / 6.0);
@@ -547,7 +590,7 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
     if (ph.terms & MAGX_ZEEMAN) {
         for (int v = 0; v < 3; ++v) {
             const double sm = block_sum(hs[v], red);
-            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] += sm;
+            if (threadIdx.x == 0) partials[lb * 8 + v] += sm;
         }
     }
     if (!has_demag) return;
@@ -560,7 +603,7 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
 #pragma unroll
         for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
     }
-    r2c_lines<R, BIG>(buf, X1, g, pen0, npen);
+    r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 
 template <typename R, bool BIG>
@@ -570,10 +613,24 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
-    const int pen0 = xcd_logical_block(blockIdx.x, gridDim.x) * g.np;
+    // logical block -> member mb and its first pencil; members own contiguous block ranges
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int mb = lb / g.bpm;
+    const int pen0 = (lb - mb * g.bpm) * g.np;
     const int npen = min(g.np, g.npen_total - pen0);
+    const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
+    const long long mo1 = (long long)mb * g.N;      // member offset of scalar fields
+    a.mu += mo;
+    a.ys += mo;
+    a.Hs += mo;
+    a.kap += mo;
+    a.xi5 += mo;
+    a.gm += mo;
+    a.muout += mo;
+    if (a.yprev) a.yprev += mo;
+    if (a.nxs) a.nxs += mo1;
     const bool vec = (g.nx & 1) == 0;
-    if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, pen0, npen);
+    if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, mb, pen0, npen);
     const R bw[4] = {(R)(1.0 / 6.0), (R)(1.0 / 3.0), (R)(1.0 / 3.0), (R)(1.0 / 6.0)};
     const R cw[4] = {(R)0, (R)0.5, (R)0.5, (R)1};
     const int s = a.stage;
@@ -668,7 +725,7 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
     if (s > 1 && (ph.terms & MAGX_ZEEMAN)) {
         for (int v = 0; v < 3; ++v) {
             const double sm = block_sum(hs[v], red);
-            if (threadIdx.x == 0) partials[blockIdx.x * 8 + v] += sm;
+            if (threadIdx.x == 0) partials[lb * 8 + v] += sm;
         }
     }
     if (s == 1 || !has_demag) return;
@@ -681,14 +738,17 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
 #pragma unroll
         for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
     }
-    r2c_lines<R, BIG>(buf, X1, g, pen0, npen);
+    r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 
 template <typename R>
 __global__ void rhs_kernel(const R* __restrict__ m, const R* __restrict__ H, R* __restrict__ out, long long N,
-                           R a, R alpha) {
-    const long long id = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (id >= N) return;
+                           long long total, R a, R alpha) {
+    // total = nbatch * N cells; member mb's fields start at mb * 3N
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= total) return;
+    const long long mb = t / N;
+    const long long id = t + 2 * mb * N;
     R mm[3], hh[3], k[3];
     load3(m, N, id, mm);
     load3(H, N, id, hh);
@@ -702,36 +762,43 @@ __global__ void fill_zero_kernel(double* p, long long n) {
 }
 
 template <typename R>
-__global__ void reduce_partials_kernel(const double* __restrict__ partials, int nblocks, int nval, R* out,
+__global__ void reduce_partials_kernel(const double* __restrict__ partials, int bpm, int nval, R* out,
                                        int accumulate) {
     __shared__ double red[kNT];
+    const int mb = blockIdx.x;
+    const double* pp = partials + (long long)mb * bpm * 8;
     for (int v = 0; v < nval; ++v) {
         double acc = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kNT) acc += partials[b * 8 + v];
+        for (int b = threadIdx.x; b < bpm; b += kNT) acc += pp[b * 8 + v];
         const double s = block_sum(acc, red);
-        if (threadIdx.x == 0) out[v] = accumulate ? (R)((double)out[v] + s) : (R)s;
+        R* o = out + mb * nval + v;
+        if (threadIdx.x == 0) *o = accumulate ? (R)((double)*o + s) : (R)s;
     }
 }
 
-// e_out: demag, exch, dmi, anis, zeeman, total (J).  pref = -(mu0 Ms V)/2.
-__global__ void energy_finish_kernel(const double* __restrict__ partials, int nblocks, double pref,
-                                     double vku_total, double* e_out) {
+// e_out[6 mb + ...]: demag, exch, dmi, anis, zeeman, total (J) of member mb.
+// pref = -(mu0 Ms V)/2, vku_member = ncell V Ku (anisotropy constant term).
+__global__ void energy_finish_kernel(const double* __restrict__ partials, int bpm, double pref,
+                                     double vku_member, double* e_out) {
     __shared__ double red[kNT];
+    const int mb = blockIdx.x;
+    const double* pp = partials + (long long)mb * bpm * 8;
     double e[5];
     for (int v = 0; v < 5; ++v) {
         double acc = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kNT) acc += partials[b * 8 + v];
+        for (int b = threadIdx.x; b < bpm; b += kNT) acc += pp[b * 8 + v];
         e[v] = block_sum(acc, red);
     }
     if (threadIdx.x == 0) {
         const double ed = pref * e[0], ee = pref * e[1], em = pref * e[2];
-        const double ea = pref * e[3] + vku_total, ez = 2.0 * pref * e[4];
-        e_out[0] = ed;
-        e_out[1] = ee;
-        e_out[2] = em;
-        e_out[3] = ea;
-        e_out[4] = ez;
-        e_out[5] = ed + ee + em + ea + ez;
+        const double ea = pref * e[3] + vku_member, ez = 2.0 * pref * e[4];
+        double* o = e_out + 6 * mb;
+        o[0] = ed;
+        o[1] = ee;
+        o[2] = em;
+        o[3] = ea;
+        o[4] = ez;
+        o[5] = ed + ee + em + ea + ez;
     }
 }
 
@@ -804,9 +871,9 @@ hipError_t launch_bstage(const Plan& pl, const Phys<R>& ph, const void* Y1, void
 
 template <typename R>
 hipError_t launch_rhs(const Plan& pl, const Phys<R>& ph, const R* m, const R* H, R* out, hipStream_t s) {
-    const long long N = pl.ncell;
-    hipLaunchKernelGGL(rhs_kernel<R>, dim3((unsigned)((N + kNT - 1) / kNT)), dim3(kNT), 0, s, m, H, out, N, ph.a,
-                       ph.alpha);
+    const long long N = pl.ncell, total = pl.ncell * pl.nbatch;
+    hipLaunchKernelGGL(rhs_kernel<R>, dim3((unsigned)((total + kNT - 1) / kNT)), dim3(kNT), 0, s, m, H, out, N,
+                       total, ph.a, ph.alpha);
     return hipGetLastError();
 }
 
@@ -816,16 +883,17 @@ hipError_t launch_fill_zero(double* p, long long n, hipStream_t s) {
 }
 
 template <typename R>
-hipError_t launch_reduce_partials(const double* partials, int nblocks, int nval, R* out, int accumulate,
-                                  hipStream_t s) {
-    hipLaunchKernelGGL(reduce_partials_kernel<R>, dim3(1), dim3(kNT), 0, s, partials, nblocks, nval, out,
-                       accumulate);
+hipError_t launch_reduce_partials(const double* partials, int nbatch, int blocks_per_member, int nval, R* out,
+                                  int accumulate, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_partials_kernel<R>, dim3(nbatch), dim3(kNT), 0, s, partials, blocks_per_member, nval,
+                       out, accumulate);
     return hipGetLastError();
 }
 
-hipError_t launch_energy_finish(const double* partials, int nblocks, double pref, double vku_total,
-                                double* e_out, hipStream_t s) {
-    hipLaunchKernelGGL(energy_finish_kernel, dim3(1), dim3(kNT), 0, s, partials, nblocks, pref, vku_total, e_out);
+hipError_t launch_energy_finish(const double* partials, int nbatch, int blocks_per_member, double pref,
+                                double vku_member, double* e_out, hipStream_t s) {
+    hipLaunchKernelGGL(energy_finish_kernel, dim3(nbatch), dim3(kNT), 0, s, partials, blocks_per_member, pref,
+                       vku_member, e_out);
     return hipGetLastError();
 }
 
@@ -846,7 +914,7 @@ hipError_t launch_copy(const R* src, R* dst, long long n, hipStream_t s) {
     template hipError_t launch_bstage<R>(const Plan&, const Phys<R>&, const void*, void*, const BackArgs<R>&,   \
                                          double*, hipStream_t);                                                 \
     template hipError_t launch_rhs<R>(const Plan&, const Phys<R>&, const R*, const R*, R*, hipStream_t);         \
-    template hipError_t launch_reduce_partials<R>(const double*, int, int, R*, int, hipStream_t);               \
+    template hipError_t launch_reduce_partials<R>(const double*, int, int, int, R*, int, hipStream_t);          \
     template hipError_t launch_copy<R>(const R*, R*, long long, hipStream_t);
 
 MAGX_INST(float)

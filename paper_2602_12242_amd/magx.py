@@ -7,8 +7,10 @@ workspace, tapes) are torch allocations sized by magx_sizes().
 
 Entry points keep the C names: magx_sizes, magx_tensor_init, magx_heff,
 magx_llg_rhs, magx_step, magx_heff_backward, magx_step_backward,
-magx_rollout_forward, magx_rollout_backward, magx_energy.  `Context` wraps
-them with owned buffers; `heff` and `Rollout` are torch.autograd Functions.
+magx_rollout_forward, magx_rollout_backward, magx_energy, plus the batched
+magx_sizes_batched, magx_tensor_init_batched and magx_set_member_bias.
+`Context` wraps them with owned buffers; `heff` and `Rollout` are
+torch.autograd Functions.
 """
 import ctypes
 import os
@@ -49,7 +51,8 @@ class magx_size_info(ctypes.Structure):
                 ("tape_bytes_extra", ctypes.c_size_t), ("field_bytes", ctypes.c_size_t)]
 
 
-EXPORTS = ("magx_sizes", "magx_tensor_init", "magx_heff", "magx_llg_rhs", "magx_step",
+EXPORTS = ("magx_sizes", "magx_sizes_batched", "magx_tensor_init", "magx_tensor_init_batched",
+           "magx_set_member_bias", "magx_ctx_batch", "magx_heff", "magx_llg_rhs", "magx_step",
            "magx_heff_backward", "magx_step_backward", "magx_rollout_forward", "magx_rollout_backward",
            "magx_energy", "magx_heff_count", "magx_ctx_info", "magx_profile_start", "magx_profile_stop",
            "magx_strerror", "magx_destroy")
@@ -69,7 +72,11 @@ def load(path=LIB_PATH):
     P = ctypes.POINTER
     sig = {
         "magx_sizes": (i, [P(magx_grid), i, P(magx_size_info)]),
+        "magx_sizes_batched": (i, [P(magx_grid), i, i, P(magx_size_info)]),
         "magx_tensor_init": (i, [P(vp), P(magx_grid), i, vp, vp, vp]),
+        "magx_tensor_init_batched": (i, [P(vp), P(magx_grid), i, i, vp, vp, vp]),
+        "magx_set_member_bias": (i, [vp, vp]),
+        "magx_ctx_batch": (i, [vp]),
         "magx_heff": (i, [vp, vp, P(magx_params), vp, vp, vp]),
         "magx_llg_rhs": (i, [vp, vp, vp, P(magx_params), vp, vp]),
         "magx_step": (i, [vp, vp, P(magx_params), d, i, vp, vp, vp]),
@@ -114,10 +121,11 @@ def make_params(Ms, A=0.0, D=0.0, Ku=0.0, eK=(0.0, 0.0, 1.0), Hbias=(0.0, 0.0, 0
     return p
 
 
-def magx_sizes(n, d, dtype=F32):
+def magx_sizes(n, d, dtype=F32, nbatch=1):
     info = magx_size_info()
     g = make_grid(n, d)
-    _check(load().magx_sizes(ctypes.byref(g), int(dtype), ctypes.byref(info)), "magx_sizes")
+    _check(load().magx_sizes_batched(ctypes.byref(g), int(dtype), int(nbatch), ctypes.byref(info)),
+           "magx_sizes_batched")
     return {k: getattr(info, k) for k, _ in magx_size_info._fields_}
 
 
@@ -134,9 +142,13 @@ def _tdtype(dtype):
 
 
 class Context:
-    """A grid, its demag tensor spectrum and a workspace on one GPU."""
+    """A grid, its demag tensor spectrum and a workspace on one GPU.
 
-    def __init__(self, n, d, dtype=F32, device="cuda"):
+    With nbatch=None the context holds one system and fields are (3, nz, ny, nx);
+    with an integer nbatch = B it advances B systems sharing the spectrum and
+    fields are (B, 3, nz, ny, nx), gHbias (B, 3) and energies (B, 6)."""
+
+    def __init__(self, n, d, dtype=F32, device="cuda", nbatch=None):
         self.lib = load()
         self.n = tuple(int(v) for v in n)
         self.d = tuple(float(v) for v in d)
@@ -146,16 +158,23 @@ class Context:
         if dev.type == "cuda" and dev.index is None:
             dev = torch.device("cuda", torch.cuda.current_device())
         self.device = dev
-        self.sizes = magx_sizes(self.n, self.d, dtype)
+        self.nbatch = 1 if nbatch is None else int(nbatch)
+        self.sizes = magx_sizes(self.n, self.d, dtype, self.nbatch)
         self.shape = (3, self.n[2], self.n[1], self.n[0])
+        self.lead = ()
+        if nbatch is not None:
+            self.lead = (self.nbatch,)
+            self.shape = self.lead + self.shape
+        self.member_bias = None
         with torch.cuda.device(self.device):
             self.spectrum = torch.empty(self.sizes["spectrum_bytes"], dtype=torch.uint8, device=self.device)
             scratch = torch.empty(self.sizes["init_scratch_bytes"], dtype=torch.uint8, device=self.device)
             self.ws = torch.empty(self.sizes["workspace_bytes"], dtype=torch.uint8, device=self.device)
             h = ctypes.c_void_p()
             g = make_grid(self.n, self.d)
-            _check(self.lib.magx_tensor_init(ctypes.byref(h), ctypes.byref(g), int(dtype), _ptr(self.spectrum),
-                                             _ptr(scratch), _stream()), "magx_tensor_init")
+            _check(self.lib.magx_tensor_init_batched(ctypes.byref(h), ctypes.byref(g), int(dtype), self.nbatch,
+                                                     _ptr(self.spectrum), _ptr(scratch), _stream()),
+                   "magx_tensor_init_batched")
             torch.cuda.current_stream().synchronize()
             del scratch
         self.h = h
@@ -182,6 +201,16 @@ class Context:
         Sx = (Hx + 15) // 16 * 16
         el = self.spectrum.view(self.tdtype)
         return el[: 6 * Hz * Hy * Sx].view(6, Hz, Hy, Sx)[..., :Hx], (Px, Py, Pz)
+
+    def set_member_bias(self, hbias):
+        """Per-member bias fields, a (nbatch, 3) tensor of the context type on its
+        device (kept referenced here), or None for the parameter bias."""
+        if hbias is not None:
+            if (hbias.dtype != self.tdtype or not hbias.is_contiguous() or tuple(hbias.shape) != (self.nbatch, 3)
+                    or hbias.device != self.device):
+                raise ValueError(f"hbias: expected contiguous {self.tdtype} ({self.nbatch}, 3) on {self.device}")
+        _check(self.lib.magx_set_member_bias(self.h, _ptr(hbias)), "magx_set_member_bias")
+        self.member_bias = hbias
 
     @property
     def heff_count(self):
@@ -217,14 +246,14 @@ class Context:
     def heff_backward(self, gH, p):
         self._chk(gH, "gH")
         gm = self.field()
-        gh = torch.empty(3, dtype=self.tdtype, device=self.device)
+        gh = torch.empty(self.lead + (3,), dtype=self.tdtype, device=self.device)
         _check(self.lib.magx_heff_backward(self.h, _ptr(gH), ctypes.byref(p), _ptr(gm), _ptr(gh), _ptr(self.ws),
                                            _stream()), "magx_heff_backward")
         return gm, gh
 
     def step_backward(self, tape, nsteps, p, dt, gm, gHbias):
         """gm: cotangent of the final state in, of the initial state out (in place);
-        gHbias (3,) is incremented."""
+        gHbias (3,) or (nbatch, 3) is incremented."""
         self._chk(gm, "gm")
         _check(self.lib.magx_step_backward(self.h, _ptr(tape), int(nsteps), ctypes.byref(p), float(dt), _ptr(gm),
                                            _ptr(gHbias), _ptr(self.ws), _stream()), "magx_step_backward")
@@ -244,7 +273,7 @@ class Context:
         self._chk(gm, "gm")
         tape = self.tape(ckpt) if tape is None else tape
         mwork = self.field() if mwork is None else mwork
-        gh = torch.empty(3, dtype=self.tdtype, device=self.device)
+        gh = torch.empty(self.lead + (3,), dtype=self.tdtype, device=self.device)
         _check(self.lib.magx_rollout_backward(self.h, _ptr(store), ctypes.byref(p), float(dt), int(nsteps),
                                               int(ckpt), _ptr(gm), _ptr(gh), _ptr(tape), _ptr(mwork),
                                               _ptr(self.ws), _stream()), "magx_rollout_backward")
@@ -264,7 +293,7 @@ class Context:
 
     def energy(self, m, p):
         self._chk(m, "m")
-        e = torch.empty(6, dtype=torch.float64, device=self.device)
+        e = torch.empty(self.lead + (6,), dtype=torch.float64, device=self.device)
         _check(self.lib.magx_energy(self.h, _ptr(m), ctypes.byref(p), _ptr(e), _ptr(self.ws), _stream()),
                "magx_energy")
         return e

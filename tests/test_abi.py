@@ -66,6 +66,35 @@ def test_sizes_of_workloads():
     assert s["workspace_bytes"] < 40e9
 
 
+def test_batched_sizes_scale_with_the_batch():
+    magx, lib = _lib()
+    n, d = (256, 256, 16), (2e-9,) * 3
+    s1 = magx.magx_sizes(n, d, magx.F32)
+    for B in (1, 3, 8):
+        sb = magx.magx_sizes(n, d, magx.F32, nbatch=B)
+        # the spectrum and its build scratch are shared by the members
+        assert sb["spectrum_bytes"] == s1["spectrum_bytes"]
+        assert sb["init_scratch_bytes"] == s1["init_scratch_bytes"]
+        assert sb["field_bytes"] == B * s1["field_bytes"]
+        assert sb["tape_bytes_per_step"] == B * s1["tape_bytes_per_step"]
+        assert sb["tape_bytes_extra"] == B * s1["tape_bytes_extra"]
+        assert sb["workspace_bytes"] >= B * (s1["workspace_bytes"] - 4096)
+    info = magx.magx_size_info()
+    g = magx.make_grid(n, d)
+    assert lib.magx_sizes_batched(ctypes.byref(g), 0, 0, ctypes.byref(info)) == -1
+    assert lib.magx_sizes_batched(ctypes.byref(g), 0, -2, ctypes.byref(info)) == -1
+    # the batch's spectral intermediates must stay below 2^31 elements
+    g = magx.make_grid((1024, 1024, 64), (3e-9,) * 3)
+    assert lib.magx_sizes_batched(ctypes.byref(g), 0, 1, ctypes.byref(info)) == 0
+    assert lib.magx_sizes_batched(ctypes.byref(g), 0, 64, ctypes.byref(info)) == -2
+    nul = ctypes.c_void_p(0)
+    h = ctypes.c_void_p(12345)
+    assert lib.magx_tensor_init_batched(ctypes.byref(h), ctypes.byref(g), 0, 2, nul, nul, nul) == -1
+    assert h.value is None
+    assert lib.magx_set_member_bias(nul, nul) == -1
+    assert lib.magx_ctx_batch(nul) == -1
+
+
 @pytest.mark.parametrize("n,d,dt,code", [
     ((0, 4, 4), (1e-9,) * 3, 0, -1),
     ((4, 4, 4), (0.0, 1e-9, 1e-9), 0, -1),
