@@ -159,6 +159,21 @@ int magx_llg_rhs(magx_ctx* ctx, const void* m, const void* H,
 int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps,
               void* tape, void* ws, void* stream);
 
+/* Advances m (device, in place) by nsteps explicit-explicit multirate steps
+ * of size dt (Section III-C, integrator comparison): the LLG torque of the
+ * exchange field is the fast partition, that of every other enabled term
+ * the slow one (Eq. (1) is linear in H, so the two add up to the full
+ * right-hand side).  Both scales use the three-stage third-order method of
+ * Knoth and Wolke in multirate-infinitesimal-step form: three slow torque
+ * evaluations (one FFT convolution each) per step, and between them the fast
+ * ODE with the slow forcing, in equal substeps no longer than dt_fast (the
+ * paper uses dt/10: 4 + 5 + 3 substeps of 3 stages, 36 exchange evaluations
+ * per step).  Renormalisation per p->renorm: 2 renormalises every slow
+ * stage value and the new state, 1 the new state only.  ws: workspace of
+ * workspace_bytes.  MAGX_EINVAL if dt < 0, dt_fast <= 0 or dt/dt_fast > 2^20. */
+int magx_step_mri(magx_ctx* ctx, void* m, const magx_params* p, double dt, double dt_fast,
+                  int nsteps, void* ws, void* stream);
+
 /* Reverse mode of the linear part of the field: for a cotangent gH of H_eff
  * (device, read), gm = K^T gH = K gH, where H_eff(m) = K m + H_bias (K is
  * symmetric: the demag tensor is, and the ghost-cell DMI boundary condition

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libmagx.so")
-SOURCES = ["magx_api.cpp", "tensor.hip", "conv.hip", "pencil.hip"]
+SOURCES = ["magx_api.cpp", "tensor.hip", "conv.hip", "pencil.hip", "mri.hip"]
 
 
 def hipcc():

@@ -1,0 +1,289 @@
+// Device helpers shared by the x-pass kernels and the multirate kernels:
+// cell-pair accesses, the local field terms with the boundary ghost rule,
+// the LLG torque and its transpose, and the x-line transforms in LDS.
+//
+// Boundary condition (Eq. (10) with the outward normal n): one ghost per face,
+// m_ghost = m_b + h (-D/2A) (e_z x n) x m_b, shared by the exchange and DMI
+// stencils; on z faces and without DMI it is plain zero-flux Neumann.
+#pragma once
+
+#include "magx_internal.hpp"
+
+namespace magx {
+
+// Two register budgets: BIG = false holds 16 FFT elements and 4 cell-pair
+// slots per thread (np * Lh <= 1024, every grid with nx <= 1024); BIG = true
+// holds 32 and 8 (nx up to 2048, float only).
+template <bool BIG> constexpr int pemax() { return BIG ? 32 : 16; }
+template <bool BIG> constexpr int maxslot() { return BIG ? 8 : 4; }
+
+struct PG {
+    int nx, ny, nz, Lh, lgLh, Hx, Sx, lgPx, np, npen_total;   // npen_total: pencils of one member
+    int bpm;                                                 // blocks per member
+    long long N;                                             // cells of one member
+};
+
+// LDS bytes of a pencil block (3 np lines of Lh complex values) and its register budget
+inline size_t pencil_lds(const Plan& pl) { return (size_t)3 * pl.np * pl.Lh * pl.esize * 2; }
+inline bool pencil_big(const Plan& pl) { return pl.np * pl.Lh > 1024; }
+
+inline PG make_pg(const Plan& pl) {
+    PG g;
+    g.nx = pl.nx; g.ny = pl.ny; g.nz = pl.nz;
+    g.Lh = pl.Lh; g.lgLh = pl.lgLh; g.Hx = pl.Hx; g.Sx = pl.Sx; g.lgPx = pl.lgPx;
+    g.np = pl.np; g.npen_total = pl.ny * pl.nz; g.bpm = pl.blocks_per_member; g.N = pl.ncell;
+    return g;
+}
+
+template <typename R>
+__device__ __forceinline__ void load3(const R* __restrict__ f, long long N, long long id, R v[3]) {
+    v[0] = f[id];
+    v[1] = f[N + id];
+    v[2] = f[2 * N + id];
+}
+
+template <typename R>
+__device__ __forceinline__ void store3(R* __restrict__ f, long long N, long long id, const R v[3]) {
+    f[id] = v[0];
+    f[N + id] = v[1];
+    f[2 * N + id] = v[2];
+}
+
+// ---- cell pairs (2n, 2n+1) along x ------------------------------------------------
+// With nx even every pair is complete and 8-byte (float) / 16-byte (double)
+// aligned, so a pair is one vector access per component; with nx odd the last
+// pair of a row has a single cell and scalar accesses are used.
+template <typename R>
+__device__ __forceinline__ void load_pair(const R* __restrict__ f, long long N, long long id, bool vec, bool two,
+                                          R a[3], R b[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const R* p = f + c * N + id;
+        if (vec) {
+            const cx<R> v = *reinterpret_cast<const cx<R>*>(p);
+            a[c] = v.x;
+            b[c] = v.y;
+        } else {
+            a[c] = p[0];
+            b[c] = two ? p[1] : (R)0;
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void store_pair(R* __restrict__ f, long long N, long long id, bool vec, bool two,
+                                           const R a[3], const R b[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        R* p = f + c * N + id;
+        if (vec) {
+            *reinterpret_cast<cx<R>*>(p) = mk<R>(a[c], b[c]);
+        } else {
+            p[0] = a[c];
+            if (two) p[1] = b[c];
+        }
+    }
+}
+
+// Exchange + DMI + anisotropy of the linear field f for the pair of cells
+// (x0 = 2n, x0 + 1) of row (y, z); h*[0] belongs to cell x0, h*[1] to x0 + 1.
+// The ghost rule is the same as in local_field.
+template <typename R>
+__device__ __forceinline__ void local_field_pair(const R* __restrict__ f, const PG& g, int x0, int y, int z,
+                                                 bool vec, bool two, const Phys<R>& ph, R m[2][3], R h[2][3],
+                                                 R hex_dot[2], R hdmi_dot[2], R hani_dot[2], bool want_parts) {
+    const long long N = g.N;
+    const long long id = ((long long)z * g.ny + y) * g.nx + x0;
+    load_pair(f, N, id, vec, two, m[0], m[1]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) h[q][c] = (R)0;
+        hex_dot[q] = hdmi_dot[q] = hani_dot[q] = (R)0;
+    }
+    if (ph.terms & (MAGX_EXCH | MAGX_DMI)) {
+        const R kdx = ph.kap * ph.dx, kdy = ph.kap * ph.dy;
+        R xl[3], xr[3], yp[2][3], ym[2][3], zp[2][3], zm[2][3];
+        // outer x neighbours of the pair: cell x0 - 1 and cell x0 + 2 (or x0 + 1 if alone)
+        R last[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) last[c] = two ? m[1][c] : m[0][c];
+        if (x0 > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xl[c] = f[c * N + id - 1];
+        } else {
+            xl[0] = m[0][0] - kdx * m[0][2]; xl[1] = m[0][1]; xl[2] = m[0][2] + kdx * m[0][0];
+        }
+        const int xr_x = x0 + (two ? 2 : 1);
+        if (xr_x < g.nx) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) xr[c] = f[c * N + id + (two ? 2 : 1)];
+        } else {
+            xr[0] = last[0] + kdx * last[2]; xr[1] = last[1]; xr[2] = last[2] - kdx * last[0];
+        }
+        if (y + 1 < g.ny) load_pair(f, N, id + g.nx, vec, two, yp[0], yp[1]);
+        if (y > 0) load_pair(f, N, id - g.nx, vec, two, ym[0], ym[1]);
+        const long long pz = (long long)g.nx * g.ny;
+        if (z + 1 < g.nz) load_pair(f, N, id + pz, vec, two, zp[0], zp[1]);
+        if (z > 0) load_pair(f, N, id - pz, vec, two, zm[0], zm[1]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const R* mc = m[q];
+            R xp[3], xm[3], ypq[3], ymq[3], zpq[3], zmq[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                xm[c] = q == 0 ? xl[c] : m[0][c];
+                xp[c] = q == 0 ? (two ? m[1][c] : xr[c]) : xr[c];
+            }
+            if (y + 1 < g.ny) { ypq[0] = yp[q][0]; ypq[1] = yp[q][1]; ypq[2] = yp[q][2]; }
+            else { ypq[0] = mc[0]; ypq[1] = mc[1] + kdy * mc[2]; ypq[2] = mc[2] - kdy * mc[1]; }
+            if (y > 0) { ymq[0] = ym[q][0]; ymq[1] = ym[q][1]; ymq[2] = ym[q][2]; }
+            else { ymq[0] = mc[0]; ymq[1] = mc[1] - kdy * mc[2]; ymq[2] = mc[2] + kdy * mc[1]; }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                zpq[c] = (z + 1 < g.nz) ? zp[q][c] : mc[c];
+                zmq[c] = (z > 0) ? zm[q][c] : mc[c];
+            }
+            R hx[3] = {(R)0, (R)0, (R)0}, hd[3] = {(R)0, (R)0, (R)0};
+            if (ph.terms & MAGX_EXCH) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const R m2 = (R)2 * mc[c];
+                    hx[c] = ph.cex * ((xp[c] - m2 + xm[c]) * ph.idx2 + (ypq[c] - m2 + ymq[c]) * ph.idy2 +
+                                      (zpq[c] - m2 + zmq[c]) * ph.idz2);
+                }
+            }
+            if (ph.terms & MAGX_DMI) {
+                hd[0] = ph.cdmi * (xp[2] - xm[2]) * ph.h2x;
+                hd[1] = ph.cdmi * (ypq[2] - ymq[2]) * ph.h2y;
+                hd[2] = -ph.cdmi * ((xp[0] - xm[0]) * ph.h2x + (ypq[1] - ymq[1]) * ph.h2y);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h[q][c] = hx[c] + hd[c];
+            if (want_parts) {
+                hex_dot[q] = mc[0] * hx[0] + mc[1] * hx[1] + mc[2] * hx[2];
+                hdmi_dot[q] = mc[0] * hd[0] + mc[1] * hd[1] + mc[2] * hd[2];
+            }
+        }
+    }
+    if (ph.terms & MAGX_ANIS) {
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const R pr = m[q][0] * ph.eK[0] + m[q][1] * ph.eK[1] + m[q][2] * ph.eK[2];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) h[q][c] += ph.cani * pr * ph.eK[c];
+            if (want_parts) hani_dot[q] = ph.cani * pr * pr;
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void cross3(const R a[3], const R b[3], R o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <typename R> __device__ __forceinline__ R dot3(const R a[3], const R b[3]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+// Eq. (1) for unit m: a [m x H + alpha m x (m x H)].
+template <typename R>
+__device__ __forceinline__ void llg_rhs(const R m[3], const R H[3], R a, R alpha, R k[3]) {
+    R mxH[3], mmH[3];
+    cross3(m, H, mxH);
+    cross3(m, mxH, mmH);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) k[c] = a * (mxH[c] + alpha * mmH[c]);
+}
+
+// Cotangent of H for a cotangent kappa of R(y): a [kappa x y + alpha y x (y x kappa)].
+template <typename R>
+__device__ __forceinline__ void rhs_mu(const R y[3], const R kap[3], R a, R alpha, R mu[3]) {
+    R kxy[3], yxk[3], yyk[3];
+    cross3(kap, y, kxy);
+    cross3(y, kap, yxk);
+    cross3(y, yxk, yyk);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mu[c] = a * (kxy[c] + alpha * yyk[c]);
+}
+
+// ---- x-line transforms in LDS --------------------------------------------------
+// LDS line for (pencil p, component c) starts at (3p + c) * Lh.
+
+template <typename R>
+__device__ __forceinline__ void pen_coords(const PG& g, int pen, int& y, int& z) {
+    z = pen / g.ny;
+    y = pen - z * g.ny;
+}
+
+// Inverse x pass: Y1 rows -> real lines; afterwards the real value of cell x
+// of line l is buf[l*Lh + x/2].x (x even) or .y (x odd).
+template <typename R, bool BIG>
+__device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int mb, int pen0, int npen) {
+    const int Lh = g.Lh;
+    const int twsh = kTwLog - g.lgPx;
+    // split step of the half-length inverse, computed while the first FFT
+    // pass reads Y1: Z[k] = (X[k] + X*[Lh-k]) + i (X[k] - X*[Lh-k]) w^-k
+    auto load = [&](int line, int k) -> cx<R> {
+        const int p = line / 3, c = line - 3 * p;
+        int y, z;
+        pen_coords<R>(g, pen0 + p, y, z);
+        const cx<R>* row = Y1 + ((((mb * 3 + c) * g.nz + z) * g.ny + y) * g.Sx);
+        const cx<R> a = row[k];
+        const cx<R> b = cconj<R>(row[Lh - k]);
+        const cx<R> A = cadd<R>(a, b);
+        const cx<R> B = cmul<R>(csub<R>(a, b), cconj<R>(tw_fwd<R>(k << twsh)));
+        return mk<R>(A.x - B.y, A.y + B.x);
+    };
+    auto none_store = [&](int, int, cx<R>) {};
+    fft_io<R, true, pemax<BIG>(), false, true, kLines, 1>(buf, g.lgLh, 0, npen * 3, load, none_store);
+}
+
+// Forward x pass: buf holds packed lines z[n] = x[2n] + i x[2n+1]; writes the
+// Hx-column half spectrum of every line to X1.
+template <typename R, bool BIG>
+__device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int mb, int pen0, int npen) {
+    const int Lh = g.Lh;
+    const int twsh = kTwLog - g.lgPx;
+    auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
+    auto none_store = [&](int, int, cx<R>) {};
+    __syncthreads();
+    fft_io<R, false, pemax<BIG>(), true, true, kLines, 1>(buf, g.lgLh, 0, npen * 3, none_load, none_store);
+    const R half = (R)0.5;
+    for (int e = threadIdx.x; e < npen * 3 * g.Hx; e += kNT) {
+        const int line = e / g.Hx, k = e - line * g.Hx;
+        const int p = line / 3, c = line - 3 * p;
+        int y, z;
+        pen_coords<R>(g, pen0 + p, y, z);
+        const cx<R> Zk = buf[line * Lh + (k & (Lh - 1))];
+        const cx<R> Zm = cconj<R>(buf[line * Lh + ((Lh - k) & (Lh - 1))]);
+        const cx<R> E = cscale<R>(cadd<R>(Zk, Zm), half);
+        const cx<R> D = csub<R>(Zk, Zm);
+        const cx<R> O = mk<R>(half * D.y, -half * D.x);       // (Zk - Zm) / (2i)
+        const cx<R> X = cadd<R>(E, cmul<R>(tw_fwd<R>(k << twsh), O));
+        X1[(((mb * 3 + c) * g.nz + z) * g.ny + y) * g.Sx + k] = X;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ R demag_at(const cx<R>* buf, int line, int Lh, int n, int h) {
+    const cx<R> v = buf[line * Lh + n];
+    return h ? v.y : v.x;
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = kNT / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+
+}  // namespace magx

@@ -133,7 +133,7 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
     size_t off = 0;
     p.off_x1 = off; off = align256(off + (size_t)3 * nbatch * p.nz * p.ny * p.Sx * 2 * es);
     p.off_x2 = off; off = align256(off + (size_t)3 * nbatch * p.nz * p.Py * p.Sx * 2 * es);
-    for (int i = 0; i < 4; ++i) { p.off_f[i] = off; off = align256(off + p.field_bytes); }
+    for (int i = 0; i < 5; ++i) { p.off_f[i] = off; off = align256(off + p.field_bytes); }
     p.off_part = off; off = align256(off + (size_t)p.pencil_blocks * 8 * sizeof(double));
     p.ws_bytes = off;
     p.tape_step_bytes = (size_t)28 * N * es;
@@ -391,6 +391,93 @@ static int do_heff_backward(magx_ctx* c, const R* gH, const magx_params* p, R* g
     return MAGX_OK;
 }
 
+// Knoth-Wolke method in Williamson's two-register form (A2, B2) and, expanded
+// from it, the Butcher rows a (b as the fourth row), nodes c and the forcing
+// weights of the three fast intervals: w[i][j] = (a[i+1][j] - a[i][j]) / (c[i+1] - c[i]).
+struct KnothWolke {
+    double A2[3] = {0.0, -5.0 / 9.0, -153.0 / 128.0};
+    double B2[3] = {1.0 / 3.0, 15.0 / 16.0, 8.0 / 15.0};
+    double a[4][3], c[4], w[3][3];
+    KnothWolke() {
+        double q[3] = {0.0, 0.0, 0.0}, y[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < 3; ++k) {
+            for (int j = 0; j < 3; ++j) a[k][j] = y[j];
+            for (int j = 0; j < 3; ++j) q[j] = A2[k] * q[j] + (j == k ? 1.0 : 0.0);
+            for (int j = 0; j < 3; ++j) y[j] += B2[k] * q[j];
+        }
+        for (int j = 0; j < 3; ++j) a[3][j] = y[j];
+        for (int i = 0; i < 4; ++i) c[i] = a[i][0] + a[i][1] + a[i][2];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) w[i][j] = (a[i + 1][j] - a[i][j]) / (c[i + 1] - c[i]);
+    }
+};
+
+// Equal fast substeps covering dc*dt with steps no longer than dt_fast.
+static long long mri_substeps(double dc, double dt, double dt_fast) {
+    const double v = std::ceil(dc * dt / dt_fast * (1.0 - 1e-12));
+    return v < 1.0 ? 1 : (long long)v;
+}
+
+template <typename R>
+static int do_step_mri(magx_ctx* c, R* m, const magx_params* p, double dt, double dt_fast, int nsteps, void* ws,
+                       hipStream_t s) {
+    static const KnothWolke kw;
+    const Plan& pl = c->pl;
+    const Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
+    Phys<R> pfast = ph, pslow = ph;     // both keep the ghost rule of the full field
+    pfast.terms = ph.terms & MAGX_EXCH;
+    pslow.terms = ph.terms & ~MAGX_EXCH;
+    const bool demag = (p->terms & MAGX_DEMAG) != 0;
+    void* X1 = bptr(ws, pl.off_x1);
+    R* S1 = reinterpret_cast<R*>(bptr(ws, pl.off_f[0]));
+    R* S2 = reinterpret_cast<R*>(bptr(ws, pl.off_f[1]));
+    R* rf = reinterpret_cast<R*>(bptr(ws, pl.off_f[2]));
+    R* q = reinterpret_cast<R*>(bptr(ws, pl.off_f[3]));
+    R* W = reinterpret_cast<R*>(bptr(ws, pl.off_f[4]));
+    long long nsub[3];
+    double hsub[3];
+    for (int i = 0; i < 3; ++i) {
+        const double dc = kw.c[i + 1] - kw.c[i];
+        nsub[i] = mri_substeps(dc, dt, dt_fast);
+        hsub[i] = dc * dt / (double)nsub[i];
+    }
+    R* cur = m;
+    R* oth = W;
+    if (demag) {
+        ProfScope ps(c, kProfXfwd, s);
+        if (launch_xfwd<R>(pl, cur, X1, s) != hipSuccess) return MAGX_EHIP;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+        for (int i = 0; i < 3; ++i) {
+            if (demag) {
+                int rc = conv_passes<R>(c, ws, ph.Ms, s);
+                if (rc) return rc;
+            } else {
+                c->heff_count++;
+            }
+            R* Sout = i == 0 ? S1 : (i == 1 ? S2 : nullptr);
+            const R* Sa = i >= 1 ? S1 : nullptr;
+            const R* Sb = i >= 2 ? S2 : nullptr;
+            if (launch_mri_slow<R>(pl, pslow, X1, cur, demag ? 1 : 0, Sout, Sa, Sb, (R)kw.w[i][0], (R)kw.w[i][1],
+                                   (R)kw.w[i][i], rf, s) != hipSuccess)
+                return MAGX_EHIP;
+            for (long long sub = 0; sub < nsub[i]; ++sub) {
+                for (int k = 0; k < 3; ++k) {
+                    const bool last = sub == nsub[i] - 1 && k == 2;
+                    const int norm = last && (p->renorm == 2 || (i == 2 && p->renorm >= 1)) ? 1 : 0;
+                    const bool fwd = last && demag && !(n == nsteps - 1 && i == 2);
+                    if (launch_mri_fast<R>(pl, pfast, cur, oth, q, rf, (R)kw.A2[k], (R)kw.B2[k], (R)hsub[i],
+                                           k == 0 ? 1 : 0, norm, fwd ? X1 : nullptr, s) != hipSuccess)
+                        return MAGX_EHIP;
+                    std::swap(cur, oth);
+                }
+            }
+        }
+    }
+    if (cur != m && launch_copy<R>(cur, m, 3 * pl.ncell * pl.nbatch, s) != hipSuccess) return MAGX_EHIP;
+    return MAGX_OK;
+}
+
 }  // namespace magx
 
 // ---------------------------------------------------------------------------------
@@ -499,6 +586,22 @@ int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nstep
     if (ctx->pl.dtype == MAGX_F32)
         return do_step<float>(ctx, static_cast<float*>(m), p, dt, nsteps, static_cast<float*>(tape), ws, s);
     return do_step<double>(ctx, static_cast<double*>(m), p, dt, nsteps, static_cast<double*>(tape), ws, s);
+}
+
+int magx_step_mri(magx_ctx* ctx, void* m, const magx_params* p, double dt, double dt_fast, int nsteps, void* ws,
+                  void* stream) {
+    if (!ctx || !m || !ws || nsteps < 0 || !std::isfinite(dt) || !(dt >= 0.0) || !std::isfinite(dt_fast) ||
+        !(dt_fast > 0.0))
+        return MAGX_EINVAL;
+    // at most 2^20 fast substeps per slow step
+    if (dt / dt_fast > (double)(1 << 20)) return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (nsteps == 0) return MAGX_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->pl.dtype == MAGX_F32)
+        return do_step_mri<float>(ctx, static_cast<float*>(m), p, dt, dt_fast, nsteps, ws, s);
+    return do_step_mri<double>(ctx, static_cast<double*>(m), p, dt, dt_fast, nsteps, ws, s);
 }
 
 int magx_heff_backward(magx_ctx* ctx, const void* gH, const magx_params* p, void* gm, void* gHbias, void* ws,

@@ -34,7 +34,7 @@ struct Plan {
     int ty, tz, np;
     int pencil_blocks;
     // workspace layout (bytes)
-    size_t off_x1, off_x2, off_f[4], off_part, ws_bytes;
+    size_t off_x1, off_x2, off_f[5], off_part, ws_bytes;
     size_t field_bytes;
     size_t tape_step_bytes, tape_extra_bytes;
     size_t spectrum_bytes, scratch_bytes;
@@ -144,5 +144,13 @@ hipError_t launch_energy_finish(const double* partials, int nbatch, int blocks_p
                                 double vku_member, double* e_out, hipStream_t s);
 template <typename R>
 hipError_t launch_copy(const R* src, R* dst, long long n, hipStream_t s);
+
+// Multirate kernels (mri.hip)
+template <typename R>
+hipError_t launch_mri_slow(const Plan& pl, const Phys<R>& ph, const void* Y1, const R* y, int has_demag, R* S_out,
+                           const R* Sa, const R* Sb, R wa, R wb, R wn, R* r_out, hipStream_t s);
+template <typename R>
+hipError_t launch_mri_fast(const Plan& pl, const Phys<R>& ph, const R* v, R* vout, R* q, const R* r, R Ak, R Bk,
+                           R h, int first, int norm, void* X1, hipStream_t s);
 
 }  // namespace magx

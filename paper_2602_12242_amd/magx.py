@@ -7,7 +7,7 @@ workspace, tapes) are torch allocations sized by magx_sizes().
 
 Entry points keep the C names: magx_sizes, magx_tensor_init, magx_heff,
 magx_llg_rhs, magx_step, magx_heff_backward, magx_step_backward,
-magx_rollout_forward, magx_rollout_backward, magx_energy, plus the batched
+magx_rollout_forward, magx_rollout_backward, magx_energy, magx_step_mri, plus the batched
 magx_sizes_batched, magx_tensor_init_batched and magx_set_member_bias.
 `Context` wraps them with owned buffers; `heff` and `Rollout` are
 torch.autograd Functions.
@@ -52,7 +52,7 @@ class magx_size_info(ctypes.Structure):
 
 
 EXPORTS = ("magx_sizes", "magx_sizes_batched", "magx_tensor_init", "magx_tensor_init_batched",
-           "magx_set_member_bias", "magx_ctx_batch", "magx_heff", "magx_llg_rhs", "magx_step",
+           "magx_set_member_bias", "magx_ctx_batch", "magx_heff", "magx_llg_rhs", "magx_step", "magx_step_mri",
            "magx_heff_backward", "magx_step_backward", "magx_rollout_forward", "magx_rollout_backward",
            "magx_energy", "magx_heff_count", "magx_ctx_info", "magx_profile_start", "magx_profile_stop",
            "magx_strerror", "magx_destroy")
@@ -80,6 +80,7 @@ def load(path=LIB_PATH):
         "magx_heff": (i, [vp, vp, P(magx_params), vp, vp, vp]),
         "magx_llg_rhs": (i, [vp, vp, vp, P(magx_params), vp, vp]),
         "magx_step": (i, [vp, vp, P(magx_params), d, i, vp, vp, vp]),
+        "magx_step_mri": (i, [vp, vp, P(magx_params), d, d, i, vp, vp]),
         "magx_heff_backward": (i, [vp, vp, P(magx_params), vp, vp, vp, vp]),
         "magx_step_backward": (i, [vp, vp, i, P(magx_params), d, vp, vp, vp, vp]),
         "magx_rollout_forward": (i, [vp, vp, P(magx_params), d, i, i, vp, vp, vp]),
@@ -241,6 +242,14 @@ class Context:
         self._chk(m, "m")
         _check(self.lib.magx_step(self.h, _ptr(m), ctypes.byref(p), float(dt), int(nsteps), _ptr(tape),
                                   _ptr(self.ws), _stream()), "magx_step")
+        return m
+
+    def step_mri(self, m, p, dt, nsteps, dt_fast=None):
+        """Advances m in place by nsteps multirate steps (fast step dt/10 by default)."""
+        self._chk(m, "m")
+        dt_fast = float(dt) / 10.0 if dt_fast is None else float(dt_fast)
+        _check(self.lib.magx_step_mri(self.h, _ptr(m), ctypes.byref(p), float(dt), dt_fast, int(nsteps),
+                                      _ptr(self.ws), _stream()), "magx_step_mri")
         return m
 
     def heff_backward(self, gH, p):
