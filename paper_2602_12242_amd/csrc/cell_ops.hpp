@@ -21,6 +21,7 @@ struct PG {
     int nx, ny, nz, Lh, lgLh, Hx, Sx, lgPx, np, npen_total;   // npen_total: pencils of one member
     int bpm;                                                 // blocks per member
     long long N;                                             // cells of one member
+    FastDiv div_ny, div_hx;                                  // n / ny and n / Hx
 };
 
 // LDS bytes of a pencil block (3 np lines of Lh complex values) and its register budget
@@ -32,6 +33,8 @@ inline PG make_pg(const Plan& pl) {
     g.nx = pl.nx; g.ny = pl.ny; g.nz = pl.nz;
     g.Lh = pl.Lh; g.lgLh = pl.lgLh; g.Hx = pl.Hx; g.Sx = pl.Sx; g.lgPx = pl.lgPx;
     g.np = pl.np; g.npen_total = pl.ny * pl.nz; g.bpm = pl.blocks_per_member; g.N = pl.ncell;
+    g.div_ny = make_fastdiv(pl.ny);
+    g.div_hx = make_fastdiv(pl.Hx);
     return g;
 }
 
@@ -214,7 +217,7 @@ __device__ __forceinline__ void rhs_mu(const R y[3], const R kap[3], R a, R alph
 
 template <typename R>
 __device__ __forceinline__ void pen_coords(const PG& g, int pen, int& y, int& z) {
-    z = pen / g.ny;
+    z = fdiv(pen, g.div_ny);
     y = pen - z * g.ny;
 }
 
@@ -238,7 +241,7 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int mb, int 
         return mk<R>(A.x - B.y, A.y + B.x);
     };
     auto none_store = [&](int, int, cx<R>) {};
-    fft_io<R, true, pemax<BIG>(), false, true, kLines, 1>(buf, g.lgLh, 0, npen * 3, load, none_store);
+    fft_io<R, true, pemax<BIG>(), false, true, kLines, 1, false, true>(buf, g.lgLh, 0, npen * 3, load, none_store);
 }
 
 // Forward x pass: buf holds packed lines z[n] = x[2n] + i x[2n+1]; writes the
@@ -250,10 +253,10 @@ __device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int mb, int pen0, 
     auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
     auto none_store = [&](int, int, cx<R>) {};
     __syncthreads();
-    fft_io<R, false, pemax<BIG>(), true, true, kLines, 1>(buf, g.lgLh, 0, npen * 3, none_load, none_store);
+    fft_io<R, false, pemax<BIG>(), true, true, kLines, 1, true, false>(buf, g.lgLh, 0, npen * 3, none_load, none_store);
     const R half = (R)0.5;
     for (int e = threadIdx.x; e < npen * 3 * g.Hx; e += kNT) {
-        const int line = e / g.Hx, k = e - line * g.Hx;
+        const int line = fdiv(e, g.div_hx), k = e - line * g.Hx;
         const int p = line / 3, c = line - 3 * p;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);

@@ -9,60 +9,110 @@
 //           symmetric tensor spectrum, H_a = -Ms sum_b N_ab M_b, then the
 //           inverse z FFT; only rows z < nz are written back (in place).
 //  * yinv : inverse y FFT; only rows y < ny (inside the box) are written.
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "magx_internal.hpp"
 
 namespace magx {
 
 // EM: FFT elements held per thread (T * L <= kNT * EM); 16 or 32.
+//
+// Every kernel is persistent: the launch has as many blocks as can be
+// resident, and block lb walks the contiguous tile range
+// [ntiles*lb/G, ntiles*(lb+1)/G) (logical blocks of one XCD are contiguous,
+// so neighbouring tiles share its L2).  The first FFT pass of a tile takes its
+// inputs from registers, and right after it the next tile's inputs are
+// requested, so the loads of tile t+1 are in flight while tile t finishes.
+
+template <typename R>
+__device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
+    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+    t0 = (int)((long long)ntiles * lb / gridDim.x);
+    t1 = (int)((long long)ntiles * (lb + 1) / gridDim.x);
+}
 
 template <typename R, int EM>
 __global__ void __launch_bounds__(kNT) yfwd_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
-                                                   int lgPy, int Hx, int Sx, int lgT, int ntx) {
+                                                   int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
     const int Py = 1 << lgPy;
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int tx = lb % ntx;
-    const long long plane = lb / ntx;    // c * nz + z
-    const int kx0 = tx * T;
-    const cx<R>* src = X1 + plane * ny * (long long)Sx + kx0;
-    cx<R>* dst = X2 + plane * Py * (long long)Sx + kx0;
-    const int ncol = min(T, Hx - kx0);
+    int t0, t1;
+    tile_range<R>(ntiles, t0, t1);
+    // tile t: plane t / ntx (= c * nz + z), columns (t % ntx) * T ...
     // sequence b = column kx0 + b; rows >= ny are the zero padding, never read
-    auto load = [&](int b, int j) -> cx<R> {
-        if (j < ny && b < ncol) return src[mul24(j, Sx) + b];
-        return mk<R>(0, 0);
+    auto loader = [=](int t) {
+        const int tx = t % ntx;
+        const long long plane = t / ntx;
+        const int kx0 = tx * T;
+        const cx<R>* src = X1 + plane * ny * (long long)Sx + kx0;
+        const int ncol = min(T, Hx - kx0);
+        return [=](int b, int j) -> cx<R> {
+            if (j < ny && b < ncol) return src[mul24(j, Sx) + b];
+            return mk<R>(0, 0);
+        };
     };
-    auto store = [&](int b, int j, cx<R> v) {
-        if (b < ncol) dst[mul24(j, Sx) + b] = v;
-    };
-    fft_io<R, false, EM, false, false, kCols, 1>(buf, lgPy, lgT, T, load, store);
+    FirstIn<R, EM, true> in;
+    if (t0 < t1) first_load<R, EM, kCols, 1, true>(in, lgPy, lgT, T, loader(t0));
+    for (int t = t0; t < t1; ++t) {
+        const int tx = t % ntx;
+        const long long plane = t / ntx;
+        const int kx0 = tx * T;
+        cx<R>* dst = X2 + plane * Py * (long long)Sx + kx0;
+        const int ncol = min(T, Hx - kx0);
+        auto store = [&](int b, int j, cx<R> v) {
+            if (b < ncol) dst[mul24(j, Sx) + b] = v;
+        };
+        auto next = [&]() {
+            if (t + 1 < t1) first_load<R, EM, kCols, 1, true>(in, lgPy, lgT, T, loader(t + 1));
+        };
+        fft_reg<R, false, EM, false, kCols, 1, true, false>(buf, lgPy, lgT, T, in, next, store);
+        __syncthreads();   // the last pass read LDS; the next tile's first pass writes it
+    }
 }
 
 template <typename R, int EM>
 __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
-                                                   int lgPy, int Hx, int Sx, int lgT, int ntx) {
+                                                   int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
     const int Py = 1 << lgPy;
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int tx = lb % ntx;
-    const long long plane = lb / ntx;
-    const int kx0 = tx * T;
-    const cx<R>* src = X2 + plane * Py * (long long)Sx + kx0;
-    cx<R>* dst = Y1 + plane * ny * (long long)Sx + kx0;
-    const int ncol = min(T, Hx - kx0);
-    auto load = [&](int b, int j) -> cx<R> {
-        if (b < ncol) return src[mul24(j, Sx) + b];
-        return mk<R>(0, 0);
+    int t0, t1;
+    tile_range<R>(ntiles, t0, t1);
+    auto loader = [=](int t) {
+        const int tx = t % ntx;
+        const long long plane = t / ntx;
+        const int kx0 = tx * T;
+        const cx<R>* src = X2 + plane * Py * (long long)Sx + kx0;
+        const int ncol = min(T, Hx - kx0);
+        return [=](int b, int j) -> cx<R> {
+            if (b < ncol) return src[mul24(j, Sx) + b];
+            return mk<R>(0, 0);
+        };
     };
-    // rows inside the box only
-    auto store = [&](int b, int j, cx<R> v) {
-        if (j < ny && b < ncol) dst[mul24(j, Sx) + b] = v;
-    };
-    fft_io<R, true, EM, false, false, kCols, 1>(buf, lgPy, lgT, T, load, store);
+    FirstIn<R, EM, false> in;
+    if (t0 < t1) first_load<R, EM, kCols, 1, false>(in, lgPy, lgT, T, loader(t0));
+    for (int t = t0; t < t1; ++t) {
+        const int tx = t % ntx;
+        const long long plane = t / ntx;
+        const int kx0 = tx * T;
+        cx<R>* dst = Y1 + plane * ny * (long long)Sx + kx0;
+        const int ncol = min(T, Hx - kx0);
+        // only rows inside the box are written
+        auto store = [&](int b, int j, cx<R> v) {
+            if (j < ny && b < ncol) dst[mul24(j, Sx) + b] = v;
+        };
+        auto next = [&]() {
+            if (t + 1 < t1) first_load<R, EM, kCols, 1, false>(in, lgPy, lgT, T, loader(t + 1));
+        };
+        fft_reg<R, true, EM, false, kCols, 1, false, true>(buf, lgPy, lgT, T, in, next, store);
+        __syncthreads();
+    }
 }
 
 // LDS layout: element (z, c, col) at (z * 3 + c) * T + col, i.e. sequence
@@ -71,7 +121,7 @@ __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2,
 template <typename R, int EM>
 __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
                                                     int nz, int lgPz, int Py, int Hx, int Hy, int Hz, int Sx,
-                                                    int lgT, int ntx, int blocks_per_member) {
+                                                    int lgT, int ntx, int blocks_per_member, int ntiles) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
@@ -79,130 +129,186 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     const int Pz = 1 << lgPz;
     const int H2 = Pz >> 1;
     R* tl = reinterpret_cast<R*>(smem_raw + (size_t)Pz * T3 * sizeof(cx<R>));
-    // logical order 0, 1, Py-1, 2, Py-2, ..., Py/2: the mirrored rows ky and
-    // Py-ky read the same tensor octant rows one after the other on one XCD
-    const int lbg = xcd_logical_block(blockIdx.x, gridDim.x);
-    const int mb = lbg / blocks_per_member;            // member of a batch of systems
-    const int lb = lbg - mb * blocks_per_member;
-    const int tx = lb % ntx;
-    const int u = lb / ntx;
-    const int ky = (u & 1) ? (u + 1) >> 1 : (u == 0 ? 0 : Py - (u >> 1));
-    const int kx0 = tx * T;
-    const int kyo = ky <= Py / 2 ? ky : Py - ky;
-    const R sy = ky <= Py / 2 ? (R)1 : (R)-1;
-    // tensor tile -> LDS first; its loads are in flight while the FFT loads X2
-    {
-        const int ntl = 6 * (H2 + 1) * T;
-        const int cstride = Hz * Hy * Sx;
-        for (int e0 = threadIdx.x; e0 < ntl; e0 += kNT * 4) {
-            R v[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = e0 + q * kNT;
-                const int col = e & (T - 1), rest = e >> lgT;
-                const int c6 = rest / (H2 + 1), kzo = rest - c6 * (H2 + 1);
-                const int kx = kx0 + col;
-                v[q] = (e < ntl && kx < Hx) ? spec[c6 * cstride + mul24(mul24(kzo, Hy) + kyo, Sx) + kx] : (R)0;
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int e = e0 + q * kNT;
-                if (e < ntl) tl[e] = v[q];
-            }
-        }
-    }
     const int plane_stride = Py * Sx;     // one z row of X2 (< 2^23, checked in the plan)
     const int comp_stride = nz * plane_stride;
-    cx<R>* base = X2 + (long long)mb * 3 * comp_stride + (long long)ky * Sx + kx0;
-    const int ncol = min(T, Hx - kx0);
+    // tile t -> member mb, column tile tx and row ky; per member the logical
+    // order of rows is 0, 1, Py-1, 2, Py-2, ..., Py/2, so the mirrored rows ky
+    // and Py-ky (same tensor octant rows) follow each other on one XCD
+    struct Tile {
+        int mb, kx0, ky;
+    };
+    auto tile_of = [=](int t) {
+        Tile d;
+        d.mb = t / blocks_per_member;
+        const int lb = t - d.mb * blocks_per_member;
+        const int tx = lb % ntx;
+        const int u = lb / ntx;
+        d.ky = (u & 1) ? (u + 1) >> 1 : (u == 0 ? 0 : Py - (u >> 1));
+        d.kx0 = tx * T;
+        return d;
+    };
+    auto base_of = [=](const Tile& d) {
+        return X2 + (long long)d.mb * 3 * comp_stride + (long long)d.ky * Sx + d.kx0;
+    };
     // rows z >= nz are the zero padding (never read) and are never written back
-    auto load = [&](int b, int j) -> cx<R> {
-        const int c = b >> lgT, col = b & (T - 1);
-        if (j < nz && col < ncol) return base[c * comp_stride + mul24(j, plane_stride) + col];
-        return mk<R>(0, 0);
+    auto loader = [=](int t) {
+        const Tile d = tile_of(t);
+        const cx<R>* base = base_of(d);
+        const int ncol = min(T, Hx - d.kx0);
+        return [=](int b, int j) -> cx<R> {
+            const int c = b >> lgT, col = b & (T - 1);
+            if (j < nz && col < ncol) return base[c * comp_stride + mul24(j, plane_stride) + col];
+            return mk<R>(0, 0);
+        };
     };
-    auto store = [&](int b, int j, cx<R> v) {
-        const int c = b >> lgT, col = b & (T - 1);
-        if (j < nz && col < ncol) base[c * comp_stride + mul24(j, plane_stride) + col] = v;
-    };
-    auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
-    auto none_store = [&](int, int, cx<R>) {};
-    fft_io<R, false, EM, false, true, kCols, 3>(buf, lgPz, lgT, T3, load, none_store);
-    // 3x3 symmetric product with the real spectrum: H_a = -Ms sum_b N_ab M_b.
-    // Item (kzo, col) serves kz = kzo and its mirror Pz - kzo, where the
-    // components odd in z (xz, yz) change sign.
+    int t0, t1;
+    tile_range<R>(ntiles, t0, t1);
+    FirstIn<R, EM, true> in;
+    if (t0 < t1) first_load<R, EM, kCols, 3, true>(in, lgPz, lgT, T3, loader(t0));
     const int tslab = (H2 + 1) * T;
-    const R s = -Ms;
-    for (int e = threadIdx.x; e < tslab; e += kNT) {
-        const int kzo = e >> lgT, col = e & (T - 1);
-        const R* t = tl + e;
-        const R nxx = t[0], nyy = t[tslab], nzz = t[2 * tslab];
-        const R nxy = sy * t[3 * tslab], nxz = t[4 * tslab], nyz = sy * t[5 * tslab];
+    for (int t = t0; t < t1; ++t) {
+        const Tile d = tile_of(t);
+        const int kyo = d.ky <= Py / 2 ? d.ky : Py - d.ky;
+        const R sy = d.ky <= Py / 2 ? (R)1 : (R)-1;
+        // tensor tile -> LDS (made visible by the barrier that ends the first
+        // FFT pass); thread -> (kzo row, column), six component rows per item
+        {
+            const int cstride = Hz * Hy * Sx;
+            const int col = threadIdx.x & (T - 1);
+            const int kx = d.kx0 + col;
+            const bool okx = kx < Hx;
+            for (int kzo = threadIdx.x >> lgT; kzo <= H2; kzo += kNT >> lgT) {
+                const R* src = spec + mul24(mul24(kzo, Hy) + kyo, Sx) + kx;
+                R v[6];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            if (m == 1 && (kzo == 0 || kzo == H2)) break;
-            const int kz = m ? Pz - kzo : kzo;
-            const R sz = m ? (R)-1 : (R)1;
-            const R xz = sz * nxz, yz = sz * nyz;
-            cx<R>* p = buf + kz * T3 + col;
-            const cx<R> mx = p[0], my = p[T], mz = p[2 * T];
-            p[0] = mk<R>(s * (nxx * mx.x + nxy * my.x + xz * mz.x), s * (nxx * mx.y + nxy * my.y + xz * mz.y));
-            p[T] = mk<R>(s * (nxy * mx.x + nyy * my.x + yz * mz.x), s * (nxy * mx.y + nyy * my.y + yz * mz.y));
-            p[2 * T] = mk<R>(s * (xz * mx.x + yz * my.x + nzz * mz.x), s * (xz * mx.y + yz * my.y + nzz * mz.y));
+                for (int c6 = 0; c6 < 6; ++c6) v[c6] = okx ? src[c6 * cstride] : (R)0;
+#pragma unroll
+                for (int c6 = 0; c6 < 6; ++c6) tl[c6 * tslab + (kzo << lgT) + col] = v[c6];
+            }
         }
+        cx<R>* base = base_of(d);
+        const int ncol = min(T, Hx - d.kx0);
+        auto store = [&](int b, int j, cx<R> v) {
+            const int c = b >> lgT, col = b & (T - 1);
+            if (j < nz && col < ncol) base[c * comp_stride + mul24(j, plane_stride) + col] = v;
+        };
+        auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
+        auto none_store = [&](int, int, cx<R>) {};
+        auto next = [&]() {
+            if (t + 1 < t1) first_load<R, EM, kCols, 3, true>(in, lgPz, lgT, T3, loader(t + 1));
+        };
+        fft_reg<R, false, EM, true, kCols, 3, true, false>(buf, lgPz, lgT, T3, in, next, none_store);
+        // 3x3 symmetric product with the real spectrum: H_a = -Ms sum_b N_ab M_b.
+        // Item (kzo, col) serves kz = kzo and its mirror Pz - kzo, where the
+        // components odd in z (xz, yz) change sign.
+        const R s = -Ms;
+        for (int e = threadIdx.x; e < tslab; e += kNT) {
+            const int kzo = e >> lgT, col = e & (T - 1);
+            const R* tp = tl + e;
+            const R nxx = tp[0], nyy = tp[tslab], nzz = tp[2 * tslab];
+            const R nxy = sy * tp[3 * tslab], nxz = tp[4 * tslab], nyz = sy * tp[5 * tslab];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                if (m == 1 && (kzo == 0 || kzo == H2)) break;
+                const int kz = m ? Pz - kzo : kzo;
+                const R sz = m ? (R)-1 : (R)1;
+                const R xz = sz * nxz, yz = sz * nyz;
+                cx<R>* p = buf + kz * T3 + col;
+                const cx<R> mx = p[0], my = p[T], mz = p[2 * T];
+                p[0] = mk<R>(s * (nxx * mx.x + nxy * my.x + xz * mz.x), s * (nxx * mx.y + nxy * my.y + xz * mz.y));
+                p[T] = mk<R>(s * (nxy * mx.x + nyy * my.x + yz * mz.x), s * (nxy * mx.y + nyy * my.y + yz * mz.y));
+                p[2 * T] =
+                    mk<R>(s * (xz * mx.x + yz * my.x + nzz * mz.x), s * (xz * mx.y + yz * my.y + nzz * mz.y));
+            }
+        }
+        __syncthreads();
+        fft_io<R, true, EM, true, false, kCols, 3, false, true>(buf, lgPz, lgT, T3, none_load, store);
+        __syncthreads();   // LDS (data and tensor tile) is rewritten by the next tile
     }
-    __syncthreads();
-    fft_io<R, true, EM, true, false, kCols, 3>(buf, lgPz, lgT, T3, none_load, store);
 }
 
 static inline bool em_big(long long elements) { return elements > (long long)kNT * 16; }
 
-template <typename R>
-hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
+// Blocks of a persistent launch: as many as can be resident on the device
+// (occupancy of this kernel at this LDS size, times the CU count), at most
+// one per tile.  Cached per device, kernel and LDS size.
+static int persistent_grid(const void* kernel, size_t lds, long long ntiles) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, size_t>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    int resident = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto key = std::make_tuple(dev, kernel, lds);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            resident = it->second;
+        } else {
+            int cus = 0, per_cu = 0;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kNT, lds) != hipSuccess) return -1;
+            resident = std::max(1, per_cu) * std::max(1, cus);
+            cache.emplace(key, resident);
+        }
+    }
+    return (int)std::min<long long>(ntiles, resident);
+}
+
+template <typename R, int EM>
+static hipError_t run_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
     const int lgT = ilog2(pl.ty);
     const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
-    const unsigned blocks = (unsigned)(ntx * 3 * pl.nz * pl.nbatch);
+    const int ntiles = ntx * 3 * pl.nz * pl.nbatch;
     const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
-    if (em_big((long long)pl.Py * pl.ty))
-        hipLaunchKernelGGL((yfwd_kernel<R, 32>), dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
-                           static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
-    else
-        hipLaunchKernelGGL((yfwd_kernel<R, 16>), dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
-                           static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
+    const int grid = persistent_grid(reinterpret_cast<const void*>(&yfwd_kernel<R, EM>), lds, ntiles);
+    if (grid < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((yfwd_kernel<R, EM>), dim3(grid), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
+                       static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx, ntiles);
+    return hipGetLastError();
+}
+
+template <typename R, int EM>
+static hipError_t run_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
+    const int lgT = ilog2(pl.ty);
+    const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
+    const int ntiles = ntx * 3 * pl.nz * pl.nbatch;
+    const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
+    const int grid = persistent_grid(reinterpret_cast<const void*>(&yinv_kernel<R, EM>), lds, ntiles);
+    if (grid < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((yinv_kernel<R, EM>), dim3(grid), dim3(kNT), lds, s, static_cast<const cx<R>*>(X2),
+                       static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx, ntiles);
     return hipGetLastError();
 }
 
 template <typename R>
+hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
+    return em_big((long long)pl.Py * pl.ty) ? run_yfwd<R, 32>(pl, X1, X2, s) : run_yfwd<R, 16>(pl, X1, X2, s);
+}
+
+template <typename R>
 hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
-    const int lgT = ilog2(pl.ty);
-    const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
-    const unsigned blocks = (unsigned)(ntx * 3 * pl.nz * pl.nbatch);
-    const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
-    if (em_big((long long)pl.Py * pl.ty))
-        hipLaunchKernelGGL((yinv_kernel<R, 32>), dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X2),
-                           static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
-    else
-        hipLaunchKernelGGL((yinv_kernel<R, 16>), dim3(blocks), dim3(kNT), lds, s, static_cast<const cx<R>*>(X2),
-                           static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx);
+    return em_big((long long)pl.Py * pl.ty) ? run_yinv<R, 32>(pl, X2, Y1, s) : run_yinv<R, 16>(pl, X2, Y1, s);
+}
+
+template <typename R, int EM>
+static hipError_t run_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s) {
+    const int lgT = ilog2(pl.tz);
+    const int ntx = (pl.Hx + pl.tz - 1) / pl.tz;
+    const int bpm = ntx * pl.Py;
+    const int ntiles = bpm * pl.nbatch;
+    const size_t lds = (size_t)3 * pl.Pz * pl.tz * sizeof(cx<R>) + (size_t)6 * (pl.Pz / 2 + 1) * pl.tz * sizeof(R);
+    const int grid = persistent_grid(reinterpret_cast<const void*>(&zconv_kernel<R, EM>), lds, ntiles);
+    if (grid < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((zconv_kernel<R, EM>), dim3(grid), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
+                       static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hy, pl.Hz, pl.Sx, lgT, ntx,
+                       bpm, ntiles);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s) {
-    const int lgT = ilog2(pl.tz);
-    const int ntx = (pl.Hx + pl.tz - 1) / pl.tz;
-    const int bpm = ntx * pl.Py;
-    const unsigned blocks = (unsigned)(bpm * pl.nbatch);
-    const size_t lds = (size_t)3 * pl.Pz * pl.tz * sizeof(cx<R>) + (size_t)6 * (pl.Pz / 2 + 1) * pl.tz * sizeof(R);
-    if (em_big(3LL * pl.Pz * pl.tz))
-        hipLaunchKernelGGL((zconv_kernel<R, 32>), dim3(blocks), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
-                           static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hy, pl.Hz, pl.Sx, lgT,
-                           ntx, bpm);
-    else
-        hipLaunchKernelGGL((zconv_kernel<R, 16>), dim3(blocks), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
-                           static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hy, pl.Hz, pl.Sx, lgT,
-                           ntx, bpm);
-    return hipGetLastError();
+    return em_big(3LL * pl.Pz * pl.tz) ? run_zconv<R, 32>(pl, X2, spec, Ms, s) : run_zconv<R, 16>(pl, X2, spec, Ms, s);
 }
 
 template hipError_t launch_yfwd<float>(const Plan&, const void*, void*, hipStream_t);

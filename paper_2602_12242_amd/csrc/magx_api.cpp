@@ -99,7 +99,7 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
         6LL * p.Hz * p.Hy * p.Sx >= (1LL << 31))
         return MAGX_ESIZE;
     p.ncell = (long long)p.nx * p.ny * p.nz;
-    if (3LL * nbatch * p.ncell >= (1LL << 31)) return MAGX_ESIZE;
+    if (3LL * nbatch * p.ncell >= (1LL << 31) || nbatch > 65535) return MAGX_ESIZE;
     p.ty = std::min(16, pow2_floor(lds_cplx / p.Py));
     // tuning override of the y tile width (power of two within the LDS budget)
     if (const char* e = std::getenv("MAGX_TILE_Y")) {

@@ -103,7 +103,10 @@ template <typename R, int RAD, bool INV> __device__ __forceinline__ void dft(cx<
 //    consecutive threads take consecutive j.
 // Each thread holds at most EMAX elements (nseq * L <= kNT * EMAX).
 // load(b, j) / store(b, j, v) are used instead of LDS by the first / last
-// pass when SRC_LDS / DST_LDS is false.  The remainder radix (2 or 4) comes
+// pass when SRC_LDS / DST_LDS is false.  HALF_IN: elements j >= L/2 of every
+// input sequence are zero (zero padding of the extended grid), so the first
+// pass neither reads them nor spends arithmetic on them; HALF_OUT: only
+// outputs j < L/2 are wanted, so the last pass computes and writes no others.  The remainder radix (2 or 4) comes
 // first, then radix-8 passes.  Radix-8 twiddles w^{rk} come from three table
 // reads (w^k, w^2k, w^4k) and their products.  A barrier follows every pass
 // that writes LDS (and precedes a pass reading and writing LDS in place).
@@ -112,6 +115,15 @@ constexpr int kCols = 0;
 constexpr int kLines = 1;
 
 __device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
+
+// threadIdx.x behind an empty volatile asm statement: index arithmetic derived
+// from it is recomputed in each pass instead of being hoisted out of a tile
+// loop and held in registers across it.
+__device__ __forceinline__ int tid_opaque() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
 
 template <typename R, bool INV>
 __device__ __forceinline__ void twiddle_apply(cx<R>* v, int RAD, int k, int twshift) {
@@ -150,10 +162,26 @@ __device__ __forceinline__ void seq_split(int t, int lgT, int lgnb, int nseq, in
     }
 }
 
-template <typename R, int RAD, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, int LAYOUT, int NC, class Load,
-          class Store>
+// Source of a pass's inputs: the load functor, LDS, or registers filled
+// beforehand by first_pass_load (first pass only).
+constexpr int kSrcFn = 0;
+constexpr int kSrcLds = 1;
+constexpr int kSrcReg = 2;
+
+// Inputs of the first pass of one tile held in registers, so that the loads
+// of the next tile can be in flight while this one is transformed: EMAX
+// values per thread for any first radix (EMAX/2 when the upper half is zero).
+template <typename R, int EMAX, bool HALF_IN>
+struct FirstIn {
+    static constexpr int N = HALF_IN ? EMAX / 2 : EMAX;
+    cx<R> v[N];
+};
+
+template <typename R, int RAD, bool INV, int EMAX, int SRC, bool DST_LDS, int LAYOUT, int NC, bool HIN,
+          bool HOUT, class Load, class Store, class In>
 __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lgL, int lgNs, int lgT, int nseq,
-                                                 Load& load, Store& store) {
+                                                 Load& load, Store& store, In& in) {
+    constexpr bool SRC_LDS = SRC == kSrcLds;
     constexpr int PER = EMAX / RAD > 0 ? EMAX / RAD : 1;
     constexpr int LGR = RAD == 2 ? 1 : (RAD == 4 ? 2 : 3);
     const int lgnb = lgL - LGR;
@@ -166,21 +194,29 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
     const int out_stride = LAYOUT == kLines ? Ns : (Ns * nseq);
     cx<R> v[PER][RAD];
     int seqv[PER], pos0[PER], obase[PER];
+    const int tid = tid_opaque();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int t = threadIdx.x + i * kNT;
+        const int t = tid + i * kNT;
         if (t < total) {
             int b, j;
             seq_split<LAYOUT, NC>(t, lgT, lgnb, nseq, b, j);
             seqv[i] = b;
-            if constexpr (SRC_LDS) {
+            // with HIN the inputs r >= RAD/2 lie in the zero half (first pass: lgNs = 0)
+            constexpr int RIN = HIN ? RAD / 2 : RAD;
+            if constexpr (SRC == kSrcReg) {
+#pragma unroll
+                for (int r = 0; r < RIN; ++r) v[i][r] = in.v[i * RIN + r];
+            } else if constexpr (SRC_LDS) {
                 const int ib = LAYOUT == kLines ? (b << lgL) + j : b + mul24(j, nseq);
 #pragma unroll
-                for (int r = 0; r < RAD; ++r) v[i][r] = buf[ib + r * in_stride];
+                for (int r = 0; r < RIN; ++r) v[i][r] = buf[ib + r * in_stride];
             } else {
 #pragma unroll
-                for (int r = 0; r < RAD; ++r) v[i][r] = load(b, j + (r << lgnb));
+                for (int r = 0; r < RIN; ++r) v[i][r] = load(b, j + (r << lgnb));
             }
+#pragma unroll
+            for (int r = RIN; r < RAD; ++r) v[i][r] = mk<R>((R)0, (R)0);
             const int k = j & (Ns - 1);
             pos0[i] = ((j >> lgNs) << (lgNs + LGR)) + k;
             obase[i] = LAYOUT == kLines ? (b << lgL) + pos0[i] : b + mul24(pos0[i], nseq);
@@ -191,10 +227,11 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
     if constexpr (SRC_LDS && DST_LDS) __syncthreads();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int t = threadIdx.x + i * kNT;
+        const int t = tid + i * kNT;
         if (t < total) {
 #pragma unroll
-            for (int r = 0; r < RAD; ++r) {
+            // with HOUT the outputs r >= RAD/2 land in the unwanted half (last pass)
+            for (int r = 0; r < (HOUT ? RAD / 2 : RAD); ++r) {
                 if constexpr (DST_LDS) buf[obase[i] + r * out_stride] = v[i][r];
                 else store(seqv[i], pos0[i] + r * Ns, v[i][r]);
             }
@@ -203,7 +240,8 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
     if constexpr (DST_LDS) __syncthreads();
 }
 
-template <typename R, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, int LAYOUT, int NC, class Load, class Store>
+template <typename R, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, int LAYOUT, int NC, bool HALF_IN = false,
+          bool HALF_OUT = false, class Load, class Store>
 __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT, int nseq, Load load, Store store) {
     if (lgL == 0) {   // length 1: the transform is the identity
         for (int b = threadIdx.x; b < nseq; b += kNT) {
@@ -219,16 +257,20 @@ __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT
     const int rem = lgL % 3;
     int lgNs = 0, left = lgL;
     bool first = true;
-#define MAGX_PASS(RADIX, S, D) \
-    stockham_io_pass<R, RADIX, INV, EMAX, S, D, LAYOUT, NC>(buf, lgL, lgNs, lgT, nseq, load, store)
+    // first pass: source SRC_LDS, zero upper half if HALF_IN; last pass:
+    // destination DST_LDS, lower half only if HALF_OUT; LDS in between
+    struct NoIn { cx<R> v[1]; } noin;
+#define MAGX_PASS(RADIX, S, D, HI, HO) \
+    stockham_io_pass<R, RADIX, INV, EMAX, (S) ? kSrcLds : kSrcFn, D, LAYOUT, NC, HI, HO>(buf, lgL, lgNs, lgT, nseq, \
+                                                                                      load, store, noin)
     if (rem) {
         const bool last = (left == rem);
         if (rem == 1) {
-            if (last) MAGX_PASS(2, SRC_LDS, DST_LDS);
-            else MAGX_PASS(2, SRC_LDS, true);
+            if (last) MAGX_PASS(2, SRC_LDS, DST_LDS, HALF_IN, HALF_OUT);
+            else MAGX_PASS(2, SRC_LDS, true, HALF_IN, false);
         } else {
-            if (last) MAGX_PASS(4, SRC_LDS, DST_LDS);
-            else MAGX_PASS(4, SRC_LDS, true);
+            if (last) MAGX_PASS(4, SRC_LDS, DST_LDS, HALF_IN, HALF_OUT);
+            else MAGX_PASS(4, SRC_LDS, true, HALF_IN, false);
         }
         lgNs += rem;
         left -= rem;
@@ -237,17 +279,109 @@ __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT
     while (left > 0) {
         const bool last = (left == 3);
         if (first) {
-            if (last) MAGX_PASS(8, SRC_LDS, DST_LDS);
-            else MAGX_PASS(8, SRC_LDS, true);
+            if (last) MAGX_PASS(8, SRC_LDS, DST_LDS, HALF_IN, HALF_OUT);
+            else MAGX_PASS(8, SRC_LDS, true, HALF_IN, false);
             first = false;
         } else {
-            if (last) MAGX_PASS(8, true, DST_LDS);
-            else MAGX_PASS(8, true, true);
+            if (last) MAGX_PASS(8, true, DST_LDS, false, HALF_OUT);
+            else MAGX_PASS(8, true, true, false, false);
         }
         lgNs += 3;
         left -= 3;
     }
 #undef MAGX_PASS
+}
+
+// Loads the first pass's inputs of one tile into `in` (lgL >= 1), in the
+// order the register-sourced first pass of fft_reg consumes them.
+template <typename R, int RAD, int EMAX, int LAYOUT, int NC, bool HIN, class Load>
+__device__ __forceinline__ void first_load_rad(FirstIn<R, EMAX, HIN>& in, int lgL, int lgT, int nseq, Load& load) {
+    constexpr int PER = EMAX / RAD > 0 ? EMAX / RAD : 1;
+    constexpr int LGR = RAD == 2 ? 1 : (RAD == 4 ? 2 : 3);
+    constexpr int RIN = HIN ? RAD / 2 : RAD;
+    static_assert(PER * RIN <= FirstIn<R, EMAX, HIN>::N, "first-pass register budget");
+    const int lgnb = lgL - LGR;
+    const int total = (1 << lgnb) * nseq;
+    const int tid = tid_opaque();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const int t = tid + i * kNT;
+        if (t < total) {
+            int b, j;
+            seq_split<LAYOUT, NC>(t, lgT, lgnb, nseq, b, j);
+#pragma unroll
+            for (int r = 0; r < RIN; ++r) in.v[i * RIN + r] = load(b, j + (r << lgnb));
+        }
+    }
+}
+
+template <typename R, int EMAX, int LAYOUT, int NC, bool HIN, class Load>
+__device__ __forceinline__ void first_load(FirstIn<R, EMAX, HIN>& in, int lgL, int lgT, int nseq, Load load) {
+    const int rem = lgL % 3;
+    if (rem == 1) first_load_rad<R, 2, EMAX, LAYOUT, NC, HIN>(in, lgL, lgT, nseq, load);
+    else if (rem == 2) first_load_rad<R, 4, EMAX, LAYOUT, NC, HIN>(in, lgL, lgT, nseq, load);
+    else first_load_rad<R, 8, EMAX, LAYOUT, NC, HIN>(in, lgL, lgT, nseq, load);
+}
+
+// fft_io with the first pass taken from registers (filled by first_load);
+// after_first() runs once the first pass has consumed them, typically to
+// issue the next tile's first_load.  Requires lgL >= 1.
+template <typename R, bool INV, int EMAX, bool DST_LDS, int LAYOUT, int NC, bool HALF_IN, bool HALF_OUT, class After,
+          class Store>
+__device__ __forceinline__ void fft_reg(cx<R>* __restrict__ buf, int lgL, int lgT, int nseq,
+                                        FirstIn<R, EMAX, HALF_IN>& in, After after_first, Store store) {
+    auto none_load = [](int, int) -> cx<R> { return mk<R>((R)0, (R)0); };
+    struct NoIn { cx<R> v[1]; } noin;
+    const int rem = lgL % 3;
+    int lgNs = 0, left = lgL;
+#define MAGX_RPASS(RADIX, S, D, HI, HO, IN) \
+    stockham_io_pass<R, RADIX, INV, EMAX, S, D, LAYOUT, NC, HI, HO>(buf, lgL, lgNs, lgT, nseq, none_load, store, IN)
+    {
+        const int r0 = rem ? rem : 3;
+        const bool last = left == r0;
+        if (r0 == 1) {
+            if (last) MAGX_RPASS(2, kSrcReg, DST_LDS, HALF_IN, HALF_OUT, in);
+            else MAGX_RPASS(2, kSrcReg, true, HALF_IN, false, in);
+        } else if (r0 == 2) {
+            if (last) MAGX_RPASS(4, kSrcReg, DST_LDS, HALF_IN, HALF_OUT, in);
+            else MAGX_RPASS(4, kSrcReg, true, HALF_IN, false, in);
+        } else {
+            if (last) MAGX_RPASS(8, kSrcReg, DST_LDS, HALF_IN, HALF_OUT, in);
+            else MAGX_RPASS(8, kSrcReg, true, HALF_IN, false, in);
+        }
+        lgNs += r0;
+        left -= r0;
+    }
+    after_first();
+    while (left > 0) {
+        const bool last = (left == 3);
+        if (last) MAGX_RPASS(8, kSrcLds, DST_LDS, false, HALF_OUT, noin);
+        else MAGX_RPASS(8, kSrcLds, true, false, false, noin);
+        lgNs += 3;
+        left -= 3;
+    }
+#undef MAGX_RPASS
+}
+
+// Division of 0 <= n < 2^31 by a divisor fixed at launch: with
+// l = ceil(log2 d) and m = floor(2^(32+l) / d) - 2^32 + 1,
+// n / d = (mulhi(n, m) + n) >> l (mulhi(n, m) < n keeps the sum in 32 bits).
+struct FastDiv {
+    unsigned m;
+    int l;
+};
+
+inline FastDiv make_fastdiv(int d) {
+    FastDiv f;
+    int l = 0;
+    while ((1LL << l) < (long long)d) ++l;
+    f.l = l;
+    f.m = (unsigned)((((unsigned long long)1 << (32 + l)) / (unsigned long long)d) - ((unsigned long long)1 << 32) + 1);
+    return f;
+}
+
+__device__ __forceinline__ int fdiv(int n, const FastDiv& f) {
+    return (int)((__umulhi((unsigned)n, f.m) + (unsigned)n) >> f.l);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD

@@ -473,12 +473,11 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
 
 template <typename R>
 __global__ void rhs_kernel(const R* __restrict__ m, const R* __restrict__ H, R* __restrict__ out, long long N,
-                           long long total, R a, R alpha) {
-    // total = nbatch * N cells; member mb's fields start at mb * 3N
+                           R a, R alpha) {
+    // grid (cells / kNT, members); member mb's fields start at mb * 3N
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total) return;
-    const long long mb = t / N;
-    const long long id = t + 2 * mb * N;
+    if (t >= N) return;
+    const long long id = (long long)blockIdx.y * 3 * N + t;
     R mm[3], hh[3], k[3];
     load3(m, N, id, mm);
     load3(H, N, id, hh);
@@ -599,9 +598,9 @@ hipError_t launch_bstage(const Plan& pl, const Phys<R>& ph, const void* Y1, void
 
 template <typename R>
 hipError_t launch_rhs(const Plan& pl, const Phys<R>& ph, const R* m, const R* H, R* out, hipStream_t s) {
-    const long long N = pl.ncell, total = pl.ncell * pl.nbatch;
-    hipLaunchKernelGGL(rhs_kernel<R>, dim3((unsigned)((total + kNT - 1) / kNT)), dim3(kNT), 0, s, m, H, out, N,
-                       total, ph.a, ph.alpha);
+    const long long N = pl.ncell;
+    hipLaunchKernelGGL(rhs_kernel<R>, dim3((unsigned)((N + kNT - 1) / kNT), (unsigned)pl.nbatch), dim3(kNT), 0, s, m,
+                       H, out, N, ph.a, ph.alpha);
     return hipGetLastError();
 }
 
