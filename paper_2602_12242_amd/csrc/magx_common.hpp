@@ -86,11 +86,102 @@ template <typename R, bool INV> __device__ __forceinline__ void dft8(cx<R>* v) {
     v[7] = csub<R>(e[3], o3);
 }
 
+// cos(pi j / 16), j = 0..8 (the 32nd roots of unity follow by symmetry)
+constexpr double kCos16[9] = {1.0,
+                              0.98078528040323044913,
+                              0.92387953251128675613,
+                              0.83146961230254523708,
+                              0.70710678118654752440,
+                              0.55557023301960222474,
+                              0.38268343236508977173,
+                              0.19509032201612826785,
+                              0.0};
+
+// cos and sin of 2 pi m / 32 for 0 <= m < 32
+constexpr double cos32(int m) {
+    m &= 31;
+    return m <= 8 ? kCos16[m] : (m <= 16 ? -kCos16[16 - m] : (m <= 24 ? -kCos16[m - 16] : kCos16[32 - m]));
+}
+constexpr double sin32(int m) { return cos32(m - 8); }
+
+// a * W_32^M with W_32 = exp(-2 pi i / 32) (forward) or its conjugate
+// (inverse); the quarter turns are exact.
+template <typename R, bool INV, int M>
+__device__ __forceinline__ cx<R> mul_w32(cx<R> a) {
+    constexpr int m = M & 31;
+    if constexpr (m == 0) return a;
+    else if constexpr (m == 8) return mul_mi<R, INV>(a);
+    else if constexpr (m == 16) return mk<R>(-a.x, -a.y);
+    else if constexpr (m == 24) return mul_mi<R, !INV>(a);
+    else {
+        constexpr R c = (R)cos32(m);
+        constexpr R sn = INV ? (R)sin32(m) : (R)-sin32(m);
+        return mk<R>(a.x * c - a.y * sn, a.x * sn + a.y * c);
+    }
+}
+
+// Length 16 = 4 x 4 and 32 = 8 x 4 (Cooley-Tukey, n = 4 n1 + n2,
+// k = k1 + N1 k2): DFTs of length N1 over n1, twiddles W_N^(n2 k1), DFTs of
+// length 4 over n2.  Natural order in and out.
+template <typename R, bool INV> __device__ __forceinline__ void dft16(cx<R>* v) {
+    cx<R> y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) y[n2][n1] = v[4 * n1 + n2];
+        dft4<R, INV>(y[n2]);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        cx<R> u[4];
+        u[0] = y[0][k1];
+        if (k1 == 0) { u[1] = y[1][0]; u[2] = y[2][0]; u[3] = y[3][0]; }
+        else if (k1 == 1) { u[1] = mul_w32<R, INV, 2>(y[1][1]); u[2] = mul_w32<R, INV, 4>(y[2][1]); u[3] = mul_w32<R, INV, 6>(y[3][1]); }
+        else if (k1 == 2) { u[1] = mul_w32<R, INV, 4>(y[1][2]); u[2] = mul_w32<R, INV, 8>(y[2][2]); u[3] = mul_w32<R, INV, 12>(y[3][2]); }
+        else { u[1] = mul_w32<R, INV, 6>(y[1][3]); u[2] = mul_w32<R, INV, 12>(y[2][3]); u[3] = mul_w32<R, INV, 18>(y[3][3]); }
+        dft4<R, INV>(u);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = u[k2];
+    }
+}
+
+template <typename R, bool INV, int N2, int K1>
+__device__ __forceinline__ cx<R> tw32_n2k1(cx<R> a) {
+    return mul_w32<R, INV, N2 * K1>(a);
+}
+
+template <typename R, bool INV> __device__ __forceinline__ void dft32(cx<R>* v) {
+    cx<R> y[4][8];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < 8; ++n1) y[n2][n1] = v[4 * n1 + n2];
+        dft8<R, INV>(y[n2]);
+    }
+    // W_32^(n2 k1) with compile-time exponents
+#define MAGX_TW(K1)                                       \
+    {                                                     \
+        cx<R> u[4];                                       \
+        u[0] = y[0][K1];                                  \
+        u[1] = tw32_n2k1<R, INV, 1, K1>(y[1][K1]);        \
+        u[2] = tw32_n2k1<R, INV, 2, K1>(y[2][K1]);        \
+        u[3] = tw32_n2k1<R, INV, 3, K1>(y[3][K1]);        \
+        dft4<R, INV>(u);                                  \
+        for (int k2 = 0; k2 < 4; ++k2) v[K1 + 8 * k2] = u[k2]; \
+    }
+    MAGX_TW(0) MAGX_TW(1) MAGX_TW(2) MAGX_TW(3) MAGX_TW(4) MAGX_TW(5) MAGX_TW(6) MAGX_TW(7)
+#undef MAGX_TW
+}
+
 template <typename R, int RAD, bool INV> __device__ __forceinline__ void dft(cx<R>* v) {
     if constexpr (RAD == 2) dft2<R, INV>(v);
     else if constexpr (RAD == 4) dft4<R, INV>(v);
-    else dft8<R, INV>(v);
+    else if constexpr (RAD == 8) dft8<R, INV>(v);
+    else if constexpr (RAD == 16) dft16<R, INV>(v);
+    else dft32<R, INV>(v);
 }
+
+constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
 
 // ---- Stockham FFTs in LDS ----------------------------------------------------------
 // nseq independent sequences of length L = 2^lgL (1 <= L <= 4096).  Two LDS
@@ -125,27 +216,23 @@ __device__ __forceinline__ int tid_opaque() {
     return t;
 }
 
-template <typename R, bool INV>
-__device__ __forceinline__ void twiddle_apply(cx<R>* v, int RAD, int k, int twshift) {
+// v[r] *= w^(r k), r = 1..RAD-1, for the pass twiddle w: w^k, w^2k, w^4k, ...
+// come from the table and every other power is a product of those (at most
+// log2(RAD) - 1 products deep).
+template <typename R, bool INV, int RAD>
+__device__ __forceinline__ void twiddle_apply(cx<R>* v, int k, int twshift) {
     if (!k) return;
-    const cx<R> w1 = tw<R, INV>(k << twshift);
-    if (RAD == 2) { v[1] = cmul<R>(v[1], w1); return; }
-    const cx<R> w2 = tw<R, INV>((2 * k) << twshift);
-    if (RAD == 4) {
-        v[1] = cmul<R>(v[1], w1);
-        v[2] = cmul<R>(v[2], w2);
-        v[3] = cmul<R>(v[3], cmul<R>(w2, w1));
-        return;
+    cx<R> w[RAD];
+#pragma unroll
+    for (int p = 1; p < RAD; p <<= 1) w[p] = tw<R, INV>((p * k) << twshift);
+#pragma unroll
+    for (int r = 3; r < RAD; ++r) {
+        if ((r & (r - 1)) == 0) continue;
+        const int hi = 1 << ilog2c(r);
+        w[r] = cmul<R>(w[hi], w[r - hi]);
     }
-    const cx<R> w4 = tw<R, INV>((4 * k) << twshift);
-    const cx<R> w3 = cmul<R>(w2, w1);
-    v[1] = cmul<R>(v[1], w1);
-    v[2] = cmul<R>(v[2], w2);
-    v[3] = cmul<R>(v[3], w3);
-    v[4] = cmul<R>(v[4], w4);
-    v[5] = cmul<R>(v[5], cmul<R>(w4, w1));
-    v[6] = cmul<R>(v[6], cmul<R>(w4, w2));
-    v[7] = cmul<R>(v[7], cmul<R>(w4, w3));
+#pragma unroll
+    for (int r = 1; r < RAD; ++r) v[r] = cmul<R>(v[r], w[r]);
 }
 
 template <int LAYOUT, int NC>
@@ -183,7 +270,7 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
                                                  Load& load, Store& store, In& in) {
     constexpr bool SRC_LDS = SRC == kSrcLds;
     constexpr int PER = EMAX / RAD > 0 ? EMAX / RAD : 1;
-    constexpr int LGR = RAD == 2 ? 1 : (RAD == 4 ? 2 : 3);
+    constexpr int LGR = ilog2c(RAD);
     const int lgnb = lgL - LGR;
     const int nb = 1 << lgnb;
     const int total = nb * nseq;
@@ -220,7 +307,7 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
             const int k = j & (Ns - 1);
             pos0[i] = ((j >> lgNs) << (lgNs + LGR)) + k;
             obase[i] = LAYOUT == kLines ? (b << lgL) + pos0[i] : b + mul24(pos0[i], nseq);
-            twiddle_apply<R, INV>(v[i], RAD, k, twshift);
+            twiddle_apply<R, INV, RAD>(v[i], k, twshift);
             dft<R, RAD, INV>(v[i]);
         }
     }
@@ -240,6 +327,22 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
     if constexpr (DST_LDS) __syncthreads();
 }
 
+// Pass plan: radices up to 2^lgmax<EMAX>() (32 when a thread holds 32
+// elements, 16 for 16, else 8); the remainder radix 2^(lgL mod lgmax) comes
+// first, then full-size passes.  Fewer, larger passes mean fewer LDS round
+// trips and barriers per transform.
+template <int EMAX> constexpr int lgmax() { return EMAX >= 32 ? 5 : (EMAX >= 16 ? 4 : 3); }
+
+// Calls MAGX_BODY(RAD) with RAD = 2^lg for a runtime lg in [1, LGM].
+#define MAGX_RADIX_SWITCH(lg, LGM)                        \
+    switch (lg) {                                         \
+        case 1: MAGX_BODY(2); break;                      \
+        case 2: MAGX_BODY(4); break;                      \
+        case 3: MAGX_BODY(8); break;                      \
+        case 4: if constexpr ((LGM) >= 4) { MAGX_BODY(16); } break; \
+        default: if constexpr ((LGM) >= 5) { MAGX_BODY(32); } break; \
+    }
+
 template <typename R, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, int LAYOUT, int NC, bool HALF_IN = false,
           bool HALF_OUT = false, class Load, class Store>
 __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT, int nseq, Load load, Store store) {
@@ -254,42 +357,38 @@ __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT
         if constexpr (DST_LDS) __syncthreads();
         return;
     }
-    const int rem = lgL % 3;
+    constexpr int LGM = lgmax<EMAX>();
+    const int rem = lgL % LGM;
     int lgNs = 0, left = lgL;
-    bool first = true;
     // first pass: source SRC_LDS, zero upper half if HALF_IN; last pass:
     // destination DST_LDS, lower half only if HALF_OUT; LDS in between
     struct NoIn { cx<R> v[1]; } noin;
-#define MAGX_PASS(RADIX, S, D, HI, HO) \
-    stockham_io_pass<R, RADIX, INV, EMAX, (S) ? kSrcLds : kSrcFn, D, LAYOUT, NC, HI, HO>(buf, lgL, lgNs, lgT, nseq, \
-                                                                                      load, store, noin)
-    if (rem) {
-        const bool last = (left == rem);
-        if (rem == 1) {
-            if (last) MAGX_PASS(2, SRC_LDS, DST_LDS, HALF_IN, HALF_OUT);
-            else MAGX_PASS(2, SRC_LDS, true, HALF_IN, false);
-        } else {
-            if (last) MAGX_PASS(4, SRC_LDS, DST_LDS, HALF_IN, HALF_OUT);
-            else MAGX_PASS(4, SRC_LDS, true, HALF_IN, false);
-        }
-        lgNs += rem;
-        left -= rem;
-        first = false;
+    {
+        const int g = rem ? rem : LGM;
+        const bool last = left == g;
+#define MAGX_BODY(RADIX)                                                                                          \
+    if (last)                                                                                                     \
+        stockham_io_pass<R, RADIX, INV, EMAX, SRC_LDS ? kSrcLds : kSrcFn, DST_LDS, LAYOUT, NC, HALF_IN, HALF_OUT>(  \
+            buf, lgL, lgNs, lgT, nseq, load, store, noin);                                                        \
+    else                                                                                                          \
+        stockham_io_pass<R, RADIX, INV, EMAX, SRC_LDS ? kSrcLds : kSrcFn, true, LAYOUT, NC, HALF_IN, false>(      \
+            buf, lgL, lgNs, lgT, nseq, load, store, noin);
+        MAGX_RADIX_SWITCH(g, LGM)
+#undef MAGX_BODY
+        lgNs += g;
+        left -= g;
     }
     while (left > 0) {
-        const bool last = (left == 3);
-        if (first) {
-            if (last) MAGX_PASS(8, SRC_LDS, DST_LDS, HALF_IN, HALF_OUT);
-            else MAGX_PASS(8, SRC_LDS, true, HALF_IN, false);
-            first = false;
-        } else {
-            if (last) MAGX_PASS(8, true, DST_LDS, false, HALF_OUT);
-            else MAGX_PASS(8, true, true, false, false);
-        }
-        lgNs += 3;
-        left -= 3;
+        constexpr int RADIX = 1 << LGM;
+        if (left == LGM)
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, DST_LDS, LAYOUT, NC, false, HALF_OUT>(
+                buf, lgL, lgNs, lgT, nseq, load, store, noin);
+        else
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, true, LAYOUT, NC, false, false>(
+                buf, lgL, lgNs, lgT, nseq, load, store, noin);
+        lgNs += LGM;
+        left -= LGM;
     }
-#undef MAGX_PASS
 }
 
 // Loads the first pass's inputs of one tile into `in` (lgL >= 1), in the
@@ -297,7 +396,7 @@ __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT
 template <typename R, int RAD, int EMAX, int LAYOUT, int NC, bool HIN, class Load>
 __device__ __forceinline__ void first_load_rad(FirstIn<R, EMAX, HIN>& in, int lgL, int lgT, int nseq, Load& load) {
     constexpr int PER = EMAX / RAD > 0 ? EMAX / RAD : 1;
-    constexpr int LGR = RAD == 2 ? 1 : (RAD == 4 ? 2 : 3);
+    constexpr int LGR = ilog2c(RAD);
     constexpr int RIN = HIN ? RAD / 2 : RAD;
     static_assert(PER * RIN <= FirstIn<R, EMAX, HIN>::N, "first-pass register budget");
     const int lgnb = lgL - LGR;
@@ -317,10 +416,12 @@ __device__ __forceinline__ void first_load_rad(FirstIn<R, EMAX, HIN>& in, int lg
 
 template <typename R, int EMAX, int LAYOUT, int NC, bool HIN, class Load>
 __device__ __forceinline__ void first_load(FirstIn<R, EMAX, HIN>& in, int lgL, int lgT, int nseq, Load load) {
-    const int rem = lgL % 3;
-    if (rem == 1) first_load_rad<R, 2, EMAX, LAYOUT, NC, HIN>(in, lgL, lgT, nseq, load);
-    else if (rem == 2) first_load_rad<R, 4, EMAX, LAYOUT, NC, HIN>(in, lgL, lgT, nseq, load);
-    else first_load_rad<R, 8, EMAX, LAYOUT, NC, HIN>(in, lgL, lgT, nseq, load);
+    constexpr int LGM = lgmax<EMAX>();
+    const int rem = lgL % LGM;
+    const int g = rem ? rem : LGM;
+#define MAGX_BODY(RADIX) first_load_rad<R, RADIX, EMAX, LAYOUT, NC, HIN>(in, lgL, lgT, nseq, load);
+    MAGX_RADIX_SWITCH(g, LGM)
+#undef MAGX_BODY
 }
 
 // fft_io with the first pass taken from registers (filled by first_load);
@@ -332,35 +433,37 @@ __device__ __forceinline__ void fft_reg(cx<R>* __restrict__ buf, int lgL, int lg
                                         FirstIn<R, EMAX, HALF_IN>& in, After after_first, Store store) {
     auto none_load = [](int, int) -> cx<R> { return mk<R>((R)0, (R)0); };
     struct NoIn { cx<R> v[1]; } noin;
-    const int rem = lgL % 3;
+    constexpr int LGM = lgmax<EMAX>();
+    const int rem = lgL % LGM;
     int lgNs = 0, left = lgL;
-#define MAGX_RPASS(RADIX, S, D, HI, HO, IN) \
-    stockham_io_pass<R, RADIX, INV, EMAX, S, D, LAYOUT, NC, HI, HO>(buf, lgL, lgNs, lgT, nseq, none_load, store, IN)
     {
-        const int r0 = rem ? rem : 3;
-        const bool last = left == r0;
-        if (r0 == 1) {
-            if (last) MAGX_RPASS(2, kSrcReg, DST_LDS, HALF_IN, HALF_OUT, in);
-            else MAGX_RPASS(2, kSrcReg, true, HALF_IN, false, in);
-        } else if (r0 == 2) {
-            if (last) MAGX_RPASS(4, kSrcReg, DST_LDS, HALF_IN, HALF_OUT, in);
-            else MAGX_RPASS(4, kSrcReg, true, HALF_IN, false, in);
-        } else {
-            if (last) MAGX_RPASS(8, kSrcReg, DST_LDS, HALF_IN, HALF_OUT, in);
-            else MAGX_RPASS(8, kSrcReg, true, HALF_IN, false, in);
-        }
-        lgNs += r0;
-        left -= r0;
+        const int g = rem ? rem : LGM;
+        const bool last = left == g;
+#define MAGX_BODY(RADIX)                                                                                     \
+    if (last)                                                                                                \
+        stockham_io_pass<R, RADIX, INV, EMAX, kSrcReg, DST_LDS, LAYOUT, NC, HALF_IN, HALF_OUT>(              \
+            buf, lgL, lgNs, lgT, nseq, none_load, store, in);                                                \
+    else                                                                                                     \
+        stockham_io_pass<R, RADIX, INV, EMAX, kSrcReg, true, LAYOUT, NC, HALF_IN, false>(buf, lgL, lgNs, lgT, \
+                                                                                         nseq, none_load,    \
+                                                                                         store, in);
+        MAGX_RADIX_SWITCH(g, LGM)
+#undef MAGX_BODY
+        lgNs += g;
+        left -= g;
     }
     after_first();
     while (left > 0) {
-        const bool last = (left == 3);
-        if (last) MAGX_RPASS(8, kSrcLds, DST_LDS, false, HALF_OUT, noin);
-        else MAGX_RPASS(8, kSrcLds, true, false, false, noin);
-        lgNs += 3;
-        left -= 3;
+        constexpr int RADIX = 1 << LGM;
+        if (left == LGM)
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, DST_LDS, LAYOUT, NC, false, HALF_OUT>(
+                buf, lgL, lgNs, lgT, nseq, none_load, store, noin);
+        else
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, true, LAYOUT, NC, false, false>(
+                buf, lgL, lgNs, lgT, nseq, none_load, store, noin);
+        lgNs += LGM;
+        left -= LGM;
     }
-#undef MAGX_RPASS
 }
 
 // Division of 0 <= n < 2^31 by a divisor fixed at launch: with
