@@ -53,7 +53,7 @@ extern "C" {
 #define MAGX_EINVAL     -1   /* null pointer, non-positive size or spacing, bad flag, DMI without exchange */
 #define MAGX_ESIZE      -2   /* n > 4096 on an axis, or an extended-grid length P = next power of two
                                 >= 2n exceeds the FFT passes' limits: Py <= 4096; Px <= 4096 (float)
-                                or 2048 (double); Pz <= 1024 (float) or 512 (double) */
+                                or 2048 (double); Pz <= 1024 */
 #define MAGX_EDTYPE     -3   /* unknown element type */
 #define MAGX_EWORKSPACE -4   /* reserved: buffer sizes are the caller's contract (see magx_sizes) */
 #define MAGX_EHIP       -5   /* a HIP call failed */
@@ -112,8 +112,9 @@ typedef struct magx_ctx magx_ctx;
 /* Sizes of every buffer for grid g and element type dt.  Host only. */
 int magx_sizes(const magx_grid* g, magx_dtype dt, magx_size_info* out);
 /* The same for a batch of nbatch >= 1 systems (spectrum and init scratch do
- * not grow with nbatch; fields, workspace and tape do).  MAGX_ESIZE if the
- * batch's spectral intermediates exceed 2^31 elements. */
+ * not grow with nbatch; fields, workspace and tape do).  MAGX_ESIZE if
+ * nbatch > 65535 or the batch's fields or spectral intermediates reach 2^31
+ * elements. */
 int magx_sizes_batched(const magx_grid* g, magx_dtype dt, int nbatch, magx_size_info* out);
 
 /* Creates a context and builds the demag tensor spectrum (Section II-B: the

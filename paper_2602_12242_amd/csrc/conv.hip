@@ -6,8 +6,9 @@
 //           never read from memory; all Py output rows are written.
 //  * zconv: for one ky, all three components: forward z FFT (rows z >= nz
 //           are zero padding), then the pointwise product with the real
-//           symmetric tensor spectrum, H_a = -Ms sum_b N_ab M_b, then the
-//           inverse z FFT; only rows z < nz are written back (in place).
+//           symmetric tensor spectrum, H_a = -Ms sum_b N_ab M_b (tensor values
+//           held in registers), then the inverse z FFT; only rows z < nz are
+//           written back (in place).
 //  * yinv : inverse y FFT; only rows y < ny (inside the box) are written.
 #include <algorithm>
 #include <map>
@@ -116,8 +117,17 @@ __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2,
 }
 
 // LDS layout: element (z, c, col) at (z * 3 + c) * T + col, i.e. sequence
-// b = c*T + col with unit sequence stride and element stride 3T; behind it the
-// block's tensor tile tl[(comp * (Pz/2+1) + kzo) * T + col].
+// b = c*T + col with unit sequence stride and element stride 3T.
+//
+// The tensor values of the spectral product stay in registers: item
+// e = threadIdx.x + it * kNT of a tile is the pair (kzo, col) =
+// (e >> lgT, e & (T-1)); the same thread loads the six components of its items
+// (at most kTensorIt per thread, guaranteed by the plan) right after the
+// previous tile's product, so the loads are in flight during that tile's
+// inverse and this tile's forward transform.  The z FFT uses radix-8 passes
+// (two for Pz = 64).
+constexpr int kTensorIt = 4;
+
 template <typename R, int EM>
 __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
                                                     int nz, int lgPz, int Py, int Hx, int Hy, int Hz, int Sx,
@@ -128,9 +138,9 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     const int T3 = 3 * T;
     const int Pz = 1 << lgPz;
     const int H2 = Pz >> 1;
-    R* tl = reinterpret_cast<R*>(smem_raw + (size_t)Pz * T3 * sizeof(cx<R>));
     const int plane_stride = Py * Sx;     // one z row of X2 (< 2^23, checked in the plan)
     const int comp_stride = nz * plane_stride;
+    const int cstride = Hz * Hy * Sx;     // one component of the tensor octant
     // tile t -> member mb, column tile tx and row ky; per member the logical
     // order of rows is 0, 1, Py-1, 2, Py-2, ..., Py/2, so the mirrored rows ky
     // and Py-ky (same tensor octant rows) follow each other on one XCD
@@ -161,31 +171,34 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
             return mk<R>(0, 0);
         };
     };
+    const int tslab = (H2 + 1) * T;
+    R tv[kTensorIt][6];
+    auto tensor_load = [&](int t) {
+        const Tile d = tile_of(t);
+        const int kyo = d.ky <= Py / 2 ? d.ky : Py - d.ky;
+        const int tid = tid_opaque();
+        const int kx = d.kx0 + (tid & (T - 1));
+        const bool okx = kx < Hx;
+#pragma unroll
+        for (int it = 0; it < kTensorIt; ++it) {
+            const int kzo = (tid + it * kNT) >> lgT;
+            if (kzo <= H2) {
+                const R* src = spec + mul24(mul24(kzo, Hy) + kyo, Sx) + kx;
+#pragma unroll
+                for (int c6 = 0; c6 < 6; ++c6) tv[it][c6] = okx ? src[c6 * cstride] : (R)0;
+            }
+        }
+    };
     int t0, t1;
     tile_range<R>(ntiles, t0, t1);
     FirstIn<R, EM, true> in;
-    if (t0 < t1) first_load<R, EM, kCols, 3, true>(in, lgPz, lgT, T3, loader(t0));
-    const int tslab = (H2 + 1) * T;
+    if (t0 < t1) {
+        first_load<R, EM, kCols, 3, true, 3>(in, lgPz, lgT, T3, loader(t0));
+        tensor_load(t0);
+    }
     for (int t = t0; t < t1; ++t) {
         const Tile d = tile_of(t);
-        const int kyo = d.ky <= Py / 2 ? d.ky : Py - d.ky;
         const R sy = d.ky <= Py / 2 ? (R)1 : (R)-1;
-        // tensor tile -> LDS (made visible by the barrier that ends the first
-        // FFT pass); thread -> (kzo row, column), six component rows per item
-        {
-            const int cstride = Hz * Hy * Sx;
-            const int col = threadIdx.x & (T - 1);
-            const int kx = d.kx0 + col;
-            const bool okx = kx < Hx;
-            for (int kzo = threadIdx.x >> lgT; kzo <= H2; kzo += kNT >> lgT) {
-                const R* src = spec + mul24(mul24(kzo, Hy) + kyo, Sx) + kx;
-                R v[6];
-#pragma unroll
-                for (int c6 = 0; c6 < 6; ++c6) v[c6] = okx ? src[c6 * cstride] : (R)0;
-#pragma unroll
-                for (int c6 = 0; c6 < 6; ++c6) tl[c6 * tslab + (kzo << lgT) + col] = v[c6];
-            }
-        }
         cx<R>* base = base_of(d);
         const int ncol = min(T, Hx - d.kx0);
         auto store = [&](int b, int j, cx<R> v) {
@@ -195,18 +208,21 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
         auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
         auto none_store = [&](int, int, cx<R>) {};
         auto next = [&]() {
-            if (t + 1 < t1) first_load<R, EM, kCols, 3, true>(in, lgPz, lgT, T3, loader(t + 1));
+            if (t + 1 < t1) first_load<R, EM, kCols, 3, true, 3>(in, lgPz, lgT, T3, loader(t + 1));
         };
-        fft_reg<R, false, EM, true, kCols, 3, true, false>(buf, lgPz, lgT, T3, in, next, none_store);
+        fft_reg<R, false, EM, true, kCols, 3, true, false, 3>(buf, lgPz, lgT, T3, in, next, none_store);
         // 3x3 symmetric product with the real spectrum: H_a = -Ms sum_b N_ab M_b.
         // Item (kzo, col) serves kz = kzo and its mirror Pz - kzo, where the
         // components odd in z (xz, yz) change sign.
         const R s = -Ms;
-        for (int e = threadIdx.x; e < tslab; e += kNT) {
+        const int tid = tid_opaque();
+#pragma unroll
+        for (int it = 0; it < kTensorIt; ++it) {
+            const int e = tid + it * kNT;
+            if (e >= tslab) continue;
             const int kzo = e >> lgT, col = e & (T - 1);
-            const R* tp = tl + e;
-            const R nxx = tp[0], nyy = tp[tslab], nzz = tp[2 * tslab];
-            const R nxy = sy * tp[3 * tslab], nxz = tp[4 * tslab], nyz = sy * tp[5 * tslab];
+            const R nxx = tv[it][0], nyy = tv[it][1], nzz = tv[it][2];
+            const R nxy = sy * tv[it][3], nxz = tv[it][4], nyz = sy * tv[it][5];
 #pragma unroll
             for (int m = 0; m < 2; ++m) {
                 if (m == 1 && (kzo == 0 || kzo == H2)) break;
@@ -221,9 +237,10 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
                     mk<R>(s * (xz * mx.x + yz * my.x + nzz * mz.x), s * (xz * mx.y + yz * my.y + nzz * mz.y));
             }
         }
+        if (t + 1 < t1) tensor_load(t + 1);
         __syncthreads();
-        fft_io<R, true, EM, true, false, kCols, 3, false, true>(buf, lgPz, lgT, T3, none_load, store);
-        __syncthreads();   // LDS (data and tensor tile) is rewritten by the next tile
+        fft_io<R, true, EM, true, false, kCols, 3, false, true, 3>(buf, lgPz, lgT, T3, none_load, store);
+        __syncthreads();   // LDS is rewritten by the next tile
     }
 }
 
@@ -297,7 +314,8 @@ static hipError_t run_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hi
     const int ntx = (pl.Hx + pl.tz - 1) / pl.tz;
     const int bpm = ntx * pl.Py;
     const int ntiles = bpm * pl.nbatch;
-    const size_t lds = (size_t)3 * pl.Pz * pl.tz * sizeof(cx<R>) + (size_t)6 * (pl.Pz / 2 + 1) * pl.tz * sizeof(R);
+    const size_t lds = (size_t)3 * pl.Pz * pl.tz * sizeof(cx<R>);
+    if ((long long)(pl.Pz / 2 + 1) * pl.tz > (long long)kTensorIt * kNT) return hipErrorInvalidValue;
     const int grid = persistent_grid(reinterpret_cast<const void*>(&zconv_kernel<R, EM>), lds, ntiles);
     if (grid < 1) return hipErrorInvalidValue;
     hipLaunchKernelGGL((zconv_kernel<R, EM>), dim3(grid), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),

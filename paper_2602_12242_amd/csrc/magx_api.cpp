@@ -106,18 +106,22 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
         const int t = std::atoi(e);
         if (t >= 1 && (t & (t - 1)) == 0 && (long long)t * p.Py <= lds_cplx) p.ty = t;
     }
-    // z tile: data 3*Pz*tz complex + tensor tile 6*(Pz/2+1)*tz reals within
-    // 64 KiB, and at most 16 FFT elements per thread when possible
+    // z tile: data 3*Pz*tz complex in LDS (at most 64 KiB), at most 16 FFT
+    // elements per thread when possible (32 at most), and at most 4 tensor
+    // items (kz <= Pz/2, column) per thread: (Pz/2+1)*tz <= 4*256
     {
-        const long long per_col = (long long)p.esize * (6LL * p.Pz + 6LL * (p.Pz / 2 + 1));
-        int tz = std::min(64, pow2_floor(65536 / per_col));
-        while (tz > 1 && 3LL * p.Pz * tz > (long long)kNT * 16) tz >>= 1;
-        if (tz < 1 || 3LL * p.Pz * tz > (long long)kNT * 32 || per_col * tz > 65536) return MAGX_ESIZE;
-        // tuning override of the z tile width (power of two within both budgets)
+        const long long per_col = (long long)p.esize * 6LL * p.Pz;
+        auto fits = [&](long long t, long long emax) {
+            return 3LL * p.Pz * t <= (long long)kNT * emax && per_col * t <= 65536 &&
+                   (long long)(p.Pz / 2 + 1) * t <= 4LL * kNT;
+        };
+        int tz = 64;
+        while (tz > 1 && !fits(tz, 16)) tz >>= 1;
+        if (!fits(tz, 32)) return MAGX_ESIZE;
+        // tuning override of the z tile width (power of two within the budgets)
         if (const char* e = std::getenv("MAGX_TILE_Z")) {
             const int t = std::atoi(e);
-            if (t >= 1 && (t & (t - 1)) == 0 && 3LL * p.Pz * t <= (long long)kNT * 32 && per_col * t <= 65536)
-                tz = t;
+            if (t >= 1 && (t & (t - 1)) == 0 && fits(t, 32)) tz = t;
         }
         p.tz = tz;
     }

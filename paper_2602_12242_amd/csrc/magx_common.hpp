@@ -344,7 +344,7 @@ template <int EMAX> constexpr int lgmax() { return EMAX >= 32 ? 5 : (EMAX >= 16 
     }
 
 template <typename R, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, int LAYOUT, int NC, bool HALF_IN = false,
-          bool HALF_OUT = false, class Load, class Store>
+          bool HALF_OUT = false, int LGM = lgmax<EMAX>(), class Load, class Store>
 __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT, int nseq, Load load, Store store) {
     if (lgL == 0) {   // length 1: the transform is the identity
         for (int b = threadIdx.x; b < nseq; b += kNT) {
@@ -357,7 +357,7 @@ __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT
         if constexpr (DST_LDS) __syncthreads();
         return;
     }
-    constexpr int LGM = lgmax<EMAX>();
+    static_assert(LGM >= 3 && LGM <= lgmax<EMAX>(), "pass radix beyond the register budget");
     const int rem = lgL % LGM;
     int lgNs = 0, left = lgL;
     // first pass: source SRC_LDS, zero upper half if HALF_IN; last pass:
@@ -414,9 +414,8 @@ __device__ __forceinline__ void first_load_rad(FirstIn<R, EMAX, HIN>& in, int lg
     }
 }
 
-template <typename R, int EMAX, int LAYOUT, int NC, bool HIN, class Load>
+template <typename R, int EMAX, int LAYOUT, int NC, bool HIN, int LGM = lgmax<EMAX>(), class Load>
 __device__ __forceinline__ void first_load(FirstIn<R, EMAX, HIN>& in, int lgL, int lgT, int nseq, Load load) {
-    constexpr int LGM = lgmax<EMAX>();
     const int rem = lgL % LGM;
     const int g = rem ? rem : LGM;
 #define MAGX_BODY(RADIX) first_load_rad<R, RADIX, EMAX, LAYOUT, NC, HIN>(in, lgL, lgT, nseq, load);
@@ -427,13 +426,13 @@ __device__ __forceinline__ void first_load(FirstIn<R, EMAX, HIN>& in, int lgL, i
 // fft_io with the first pass taken from registers (filled by first_load);
 // after_first() runs once the first pass has consumed them, typically to
 // issue the next tile's first_load.  Requires lgL >= 1.
-template <typename R, bool INV, int EMAX, bool DST_LDS, int LAYOUT, int NC, bool HALF_IN, bool HALF_OUT, class After,
-          class Store>
+template <typename R, bool INV, int EMAX, bool DST_LDS, int LAYOUT, int NC, bool HALF_IN, bool HALF_OUT,
+          int LGM = lgmax<EMAX>(), class After, class Store>
 __device__ __forceinline__ void fft_reg(cx<R>* __restrict__ buf, int lgL, int lgT, int nseq,
                                         FirstIn<R, EMAX, HALF_IN>& in, After after_first, Store store) {
+    static_assert(LGM >= 3 && LGM <= lgmax<EMAX>(), "pass radix beyond the register budget");
     auto none_load = [](int, int) -> cx<R> { return mk<R>((R)0, (R)0); };
     struct NoIn { cx<R> v[1]; } noin;
-    constexpr int LGM = lgmax<EMAX>();
     const int rem = lgL % LGM;
     int lgNs = 0, left = lgL;
     {

@@ -95,6 +95,15 @@ def test_batched_sizes_scale_with_the_batch():
     assert lib.magx_ctx_batch(nul) == -1
 
 
+def test_sizes_at_the_limits():
+    magx, _ = _lib()
+    for dt in (magx.F32, magx.F64):
+        # Pz = 1024 and Py = 4096 are the longest z and y transforms
+        assert magx.magx_sizes((4, 4, 512), (1e-9,) * 3, dt)["field_bytes"] > 0
+        assert magx.magx_sizes((4, 2048, 4), (1e-9,) * 3, dt)["field_bytes"] > 0
+    assert magx.magx_sizes((2048, 4, 4), (1e-9,) * 3, magx.F32)["field_bytes"] > 0
+
+
 @pytest.mark.parametrize("n,d,dt,code", [
     ((0, 4, 4), (1e-9,) * 3, 0, -1),
     ((4, 4, 4), (0.0, 1e-9, 1e-9), 0, -1),
@@ -102,7 +111,7 @@ def test_batched_sizes_scale_with_the_batch():
     ((5000, 4, 4), (1e-9,) * 3, 0, -2),
     ((4, 4, 2048), (1e-9,) * 3, 1, -2),
     ((4, 4, 1024), (1e-9,) * 3, 0, -2),
-    ((4, 4, 512), (1e-9,) * 3, 1, -2),
+    ((4, 4, 1024), (1e-9,) * 3, 1, -2),
 ])
 def test_sizes_rejects(n, d, dt, code):
     magx, lib = _lib()

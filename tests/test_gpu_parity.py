@@ -42,6 +42,9 @@ CASES = {
              dict(Ms=8e5, alpha=0.1, Hbias=(0, 0, 2e5), terms=1 | 16)),
     "tiles": ((96, 70, 9), (2e-9, 2e-9, 3e-9),
               dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, alpha=0.1, Hbias=(1e3, 2e3, -5e3), terms=ALL)),
+    # Pz = 1024: the longest z transform, one column per z tile
+    "tall": ((3, 2, 300), (2e-9, 2e-9, 1e-9),
+             dict(Ms=8e5, A=1.3e-11, alpha=0.1, Hbias=(0, 0, 1e4), terms=1 | 2 | 16)),
 }
 
 
