@@ -141,19 +141,36 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     const int plane_stride = Py * Sx;     // one z row of X2 (< 2^23, checked in the plan)
     const int comp_stride = nz * plane_stride;
     const int cstride = Hz * Hy * Sx;     // one component of the tensor octant
-    // tile t -> member mb, column tile tx and row ky; per member the logical
-    // order of rows is 0, 1, Py-1, 2, Py-2, ..., Py/2, so the mirrored rows ky
-    // and Py-ky (same tensor octant rows) follow each other on one XCD
+    // tile t -> member mb, column tile tx and row ky.  Per member: the tiles
+    // of row 0, then for q = 1 .. Py/2-1 the rows q and Py-q interleaved by
+    // column tile ((tx, q), (tx, Py-q), (tx+1, q), ...), then row Py/2.  The
+    // mirrored rows read the same tensor octant values, so the second tile of
+    // each pair finds them in L2 (consecutive tiles run on one block).
     struct Tile {
         int mb, kx0, ky;
     };
+    const int pair_tiles = 2 * ntx;
+    const int npair = (Py >> 1) - 1;
     auto tile_of = [=](int t) {
         Tile d;
         d.mb = t / blocks_per_member;
-        const int lb = t - d.mb * blocks_per_member;
-        const int tx = lb % ntx;
-        const int u = lb / ntx;
-        d.ky = (u & 1) ? (u + 1) >> 1 : (u == 0 ? 0 : Py - (u >> 1));
+        int r = t - d.mb * blocks_per_member;
+        int tx;
+        if (r < ntx) {
+            d.ky = 0;
+            tx = r;
+        } else {
+            r -= ntx;
+            if (r < npair * pair_tiles) {
+                const int q = 1 + r / pair_tiles;
+                const int w = r - (q - 1) * pair_tiles;
+                tx = w >> 1;
+                d.ky = (w & 1) ? Py - q : q;
+            } else {
+                d.ky = Py >> 1;
+                tx = r - npair * pair_tiles;
+            }
+        }
         d.kx0 = tx * T;
         return d;
     };
