@@ -120,6 +120,54 @@ def cpu_baseline(w, budget_cells=(128, 128, 32)):
                       f"({dt:.1f} s), scaled by cell count {sub}/{w.ncell}"}
 
 
+def integrator_comparison(magx, torch, timeit):
+    """Standard Problem 4 film at 0.78125 nm (640x160x4, FP32): time to cover
+    one 1.25e-13 s interval with RK4 (5 steps of 2.5e-14 s, 20 field
+    evaluations) and with the multirate method (1 step, 3 field evaluations
+    and 36 exchange-only stages), and each one's deviation from a fine RK4
+    reference (100 steps of 1.25e-15 s)."""
+    import numpy as np
+
+    from workloads import WORKLOADS, initial_state
+    w = WORKLOADS["sp4_fine"]
+    ctx = magx.Context(w.n, w.d, magx.F32)
+    p = magx.make_params(**w.material())
+    m0 = torch.from_numpy(initial_state(w, np.float32)).cuda()
+    a, b, ref = ctx.field(), ctx.field(), ctx.field()
+    T = w.extra["interval"]
+    t_rk4 = timeit(lambda: (a.copy_(m0), ctx.step(a, p, w.dt, w.steps)), 10)
+    t_mri = timeit(lambda: (b.copy_(m0), ctx.step_mri(b, p, w.extra["dt_mri"], 1, w.extra["dt_fast"])), 10)
+    ref.copy_(m0)
+    ctx.step(ref, p, T / 100, 100)
+    torch.cuda.synchronize()
+    return {"cells": w.ncell, "interval_s": T,
+            "rk4_ms": round(1e3 * t_rk4, 4), "mri_ms": round(1e3 * t_mri, 4),
+            "rk4_field_evals": 4 * w.steps, "mri_field_evals": 3, "mri_exchange_stages": 36,
+            "err_rk4_vs_fine": float((a - ref).abs().max()), "err_mri_vs_fine": float((b - ref).abs().max()),
+            "paper_gv100_time_to_solution_s": {"rk4": 0.133, "mri": 0.069}}
+
+
+def batched_throughput(magx, torch, timeit, B=16, steps=10):
+    """B independent film systems (128x32x1) advanced as one batch versus one
+    after another through a single-system context: member-steps per second."""
+    import numpy as np
+
+    from workloads import WORKLOADS, random_unit_field
+    w = WORKLOADS["film"]
+    p = magx.make_params(**w.material())
+    single = magx.Context(w.n, w.d, magx.F32)
+    batch = magx.Context(w.n, w.d, magx.F32, nbatch=B)
+    ms = torch.from_numpy(np.stack([random_unit_field(w.n, 5000 + b, 3) for b in range(B)])).to(
+        "cuda", torch.float32).contiguous()
+    mb = ms.clone()
+    one = ms[0].clone()
+    t_batch = timeit(lambda: batch.step(mb, p, w.dt, steps), 5)
+    t_single = timeit(lambda: single.step(one, p, w.dt, steps), 5)
+    return {"members": B, "cells_per_member": w.ncell, "steps": steps,
+            "batched_member_steps_per_s": round(B * steps / t_batch, 1),
+            "sequential_member_steps_per_s": round(steps / t_single, 1)}
+
+
 def _pmc_rows(path, counter):
     """(kernel name, value) per dispatch from a rocprofv3 result: a rocpd
     SQLite database (*_results.db) or a counter_collection.csv."""
@@ -304,6 +352,8 @@ def main():
         }
         del ctx64, H64, mm64, m1_64, m0_64
         torch.cuda.empty_cache()
+        extras["sp4_fine_interval"] = integrator_comparison(magx, torch, timeit)
+        extras["batched_film"] = batched_throughput(magx, torch, timeit)
 
     cpu = None
     if not args.no_cpu_baseline:
