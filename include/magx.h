@@ -220,6 +220,13 @@ long long magx_heff_count(const magx_ctx* ctx);
 /* Grid and type of a context (host). */
 int magx_ctx_info(const magx_ctx* ctx, magx_grid* g, magx_dtype* dt);
 
+/* Diagnostics: layout of the stored tensor spectrum, dims[0..4] = (Hy, ntz,
+ * 6, Hz, tz): element (c, kz, ky, kx) of the real octant of the tensor
+ * spectrum (c = xx yy zz xy xz yz, already scaled by 1/(Px Py Pz)) is at
+ * (((ky * ntz + kx / tz) * 6 + c) * Hz + kz) * tz + kx % tz; Hy = Py/2 + 1,
+ * Hz = Pz/2 + 1, kx < Px/2 + 1 <= ntz * tz.  Host only. */
+int magx_spectrum_layout(const magx_ctx* ctx, int dims[5]);
+
 /* Diagnostics: from magx_profile_start until magx_profile_stop, every launch
  * of one kernel family enqueued through ctx is bracketed by a pair of HIP
  * events on its stream.  kind: 0 none, 1 forward x pass, 2 forward y pass,

@@ -130,8 +130,8 @@ constexpr int kTensorIt = 4;
 
 template <typename R, int EM>
 __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
-                                                    int nz, int lgPz, int Py, int Hx, int Hy, int Hz, int Sx,
-                                                    int lgT, int ntx, int blocks_per_member, int ntiles) {
+                                                    int nz, int lgPz, int Py, int Hx, int Hz, int Sx, int lgT,
+                                                    int ntx, int units_per_member, int nunits) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
@@ -140,38 +140,26 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     const int H2 = Pz >> 1;
     const int plane_stride = Py * Sx;     // one z row of X2 (< 2^23, checked in the plan)
     const int comp_stride = nz * plane_stride;
-    const int cstride = Hz * Hy * Sx;     // one component of the tensor octant
-    // tile t -> member mb, column tile tx and row ky.  Per member: the tiles
-    // of row 0, then for q = 1 .. Py/2-1 the rows q and Py-q interleaved by
-    // column tile ((tx, q), (tx, Py-q), (tx+1, q), ...), then row Py/2.  The
-    // mirrored rows read the same tensor octant values, so the second tile of
-    // each pair finds them in L2 (consecutive tiles run on one block).
+    // Work unit u -> member mb, row pair q, column tile tx (tx fastest).  The
+    // blocks of a launch come in pairs with adjacent logical indices (one XCD,
+    // the same unit range, started together): the even block of a pair takes
+    // row ky = q, the odd one row Py - q (q = 0 pairs rows 0 and Py/2).  Rows q
+    // and Py - q read the same tensor octant values, so the pair's second
+    // request for them finds them in L2.
     struct Tile {
-        int mb, kx0, ky;
+        int mb, kx0, ky, tx, kyo;
     };
-    const int pair_tiles = 2 * ntx;
-    const int npair = (Py >> 1) - 1;
-    auto tile_of = [=](int t) {
+    const int lbp = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int side = lbp & 1;
+    auto tile_of = [=](int u) {
         Tile d;
-        d.mb = t / blocks_per_member;
-        int r = t - d.mb * blocks_per_member;
-        int tx;
-        if (r < ntx) {
-            d.ky = 0;
-            tx = r;
-        } else {
-            r -= ntx;
-            if (r < npair * pair_tiles) {
-                const int q = 1 + r / pair_tiles;
-                const int w = r - (q - 1) * pair_tiles;
-                tx = w >> 1;
-                d.ky = (w & 1) ? Py - q : q;
-            } else {
-                d.ky = Py >> 1;
-                tx = r - npair * pair_tiles;
-            }
-        }
-        d.kx0 = tx * T;
+        d.mb = u / units_per_member;
+        const int r = u - d.mb * units_per_member;
+        const int q = r / ntx;
+        d.tx = r - q * ntx;
+        d.kyo = side ? (q == 0 ? Py >> 1 : q) : q;
+        d.ky = side ? (q == 0 ? Py >> 1 : Py - q) : q;
+        d.kx0 = d.tx * T;
         return d;
     };
     auto base_of = [=](const Tile& d) {
@@ -188,26 +176,28 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
             return mk<R>(0, 0);
         };
     };
-    const int tslab = (H2 + 1) * T;
+    const int tslab = (H2 + 1) * T;      // tensor values of one component and tile
     R tv[kTensorIt][6];
-    auto tensor_load = [&](int t) {
-        const Tile d = tile_of(t);
-        const int kyo = d.ky <= Py / 2 ? d.ky : Py - d.ky;
+    // the tile's tensor block [6][Hz][T] is contiguous (row kyo, column tile tx)
+    auto tensor_load = [&](int u) {
+        const Tile d = tile_of(u);
+        const R* blk = spec + (long long)(d.kyo * ntx + d.tx) * 6 * tslab;
         const int tid = tid_opaque();
-        const int kx = d.kx0 + (tid & (T - 1));
-        const bool okx = kx < Hx;
+        const bool okx = d.kx0 + (tid & (T - 1)) < Hx;
 #pragma unroll
         for (int it = 0; it < kTensorIt; ++it) {
-            const int kzo = (tid + it * kNT) >> lgT;
-            if (kzo <= H2) {
-                const R* src = spec + mul24(mul24(kzo, Hy) + kyo, Sx) + kx;
+            const int e = tid + it * kNT;
+            if (e < tslab) {
 #pragma unroll
-                for (int c6 = 0; c6 < 6; ++c6) tv[it][c6] = okx ? src[c6 * cstride] : (R)0;
+                for (int c6 = 0; c6 < 6; ++c6) tv[it][c6] = okx ? blk[c6 * tslab + e] : (R)0;
             }
         }
     };
-    int t0, t1;
-    tile_range<R>(ntiles, t0, t1);
+    // unit range of this block's pair
+    const int npairs = gridDim.x >> 1;
+    const int pr = lbp >> 1;
+    const int t0 = (int)((long long)nunits * pr / npairs);
+    const int t1 = (int)((long long)nunits * (pr + 1) / npairs);
     FirstIn<R, EM, true> in;
     if (t0 < t1) {
         first_load<R, EM, kCols, 3, true, 3>(in, lgPz, lgT, T3, loader(t0));
@@ -328,16 +318,20 @@ hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) 
 template <typename R, int EM>
 static hipError_t run_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s) {
     const int lgT = ilog2(pl.tz);
-    const int ntx = (pl.Hx + pl.tz - 1) / pl.tz;
-    const int bpm = ntx * pl.Py;
-    const int ntiles = bpm * pl.nbatch;
+    const int ntx = pl.ntz;
+    const int upm = ntx * (pl.Py / 2);          // units (row pair, column tile) per member
+    const long long nunits = (long long)upm * pl.nbatch;
     const size_t lds = (size_t)3 * pl.Pz * pl.tz * sizeof(cx<R>);
     if ((long long)(pl.Pz / 2 + 1) * pl.tz > (long long)kTensorIt * kNT) return hipErrorInvalidValue;
-    const int grid = persistent_grid(reinterpret_cast<const void*>(&zconv_kernel<R, EM>), lds, ntiles);
-    if (grid < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((zconv_kernel<R, EM>), dim3(grid), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
-                       static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hy, pl.Hz, pl.Sx, lgT, ntx,
-                       bpm, ntiles);
+    // block pairs share a unit range; pairs never straddle an XCD when the
+    // grid is a multiple of 16
+    const int resident = persistent_grid(reinterpret_cast<const void*>(&zconv_kernel<R, EM>), lds, 1LL << 30);
+    if (resident < 1) return hipErrorInvalidValue;
+    long long grid = 2 * std::min<long long>(nunits, std::max(1, resident / 2));
+    if (grid >= 16) grid -= grid % 16;
+    hipLaunchKernelGGL((zconv_kernel<R, EM>), dim3((unsigned)grid), dim3(kNT), lds, s, static_cast<cx<R>*>(X2),
+                       static_cast<const R*>(spec), Ms, pl.nz, pl.lgPz, pl.Py, pl.Hx, pl.Hz, pl.Sx, lgT, ntx, upm,
+                       (int)nunits);
     return hipGetLastError();
 }
 

@@ -124,6 +124,8 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
             if (t >= 1 && (t & (t - 1)) == 0 && fits(t, 32)) tz = t;
         }
         p.tz = tz;
+        p.ntz = (p.Hx + tz - 1) / tz;
+        if ((long long)p.Hy * p.ntz * 6 * p.Hz * tz >= (1LL << 31)) return MAGX_ESIZE;
     }
     p.np = std::max(1, 1024 / p.Lh);
     const int npen = p.ny * p.nz;
@@ -142,7 +144,7 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
     p.ws_bytes = off;
     p.tape_step_bytes = (size_t)28 * N * es;
     p.tape_extra_bytes = (size_t)3 * N * es;
-    p.spectrum_bytes = (size_t)6 * p.Hz * p.Hy * p.Sx * es;
+    p.spectrum_bytes = (size_t)p.Hy * p.ntz * 6 * p.Hz * p.tz * es;
     const long long a1 = 6 * p.ncell, a2 = 6LL * p.Hy * p.Hx * p.nz;
     p.scratch_a_elems = std::max(a1, a2);
     p.scratch_b_elems = 6LL * p.Hx * p.nz * p.ny;
@@ -697,6 +699,16 @@ int magx_rollout_backward(magx_ctx* ctx, const void* ckpt_store, const magx_para
 }
 
 long long magx_heff_count(const magx_ctx* ctx) { return ctx ? ctx->heff_count : -1; }
+
+int magx_spectrum_layout(const magx_ctx* ctx, int dims[5]) {
+    if (!ctx || !dims) return MAGX_EINVAL;
+    dims[0] = ctx->pl.Hy;
+    dims[1] = ctx->pl.ntz;
+    dims[2] = 6;
+    dims[3] = ctx->pl.Hz;
+    dims[4] = ctx->pl.tz;
+    return MAGX_OK;
+}
 
 int magx_ctx_info(const magx_ctx* ctx, magx_grid* g, magx_dtype* dt) {
     if (!ctx || !g || !dt) return MAGX_EINVAL;

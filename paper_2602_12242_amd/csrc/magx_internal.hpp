@@ -15,7 +15,8 @@ namespace magx {
 // Spectral intermediates (complex, x fastest):
 //   X1 [3][nz][ny][Sx]   after the forward x pass; reused for the inverse-y output
 //   X2 [3][nz][Py][Sx]   after the forward y pass; the z pass works in place
-// Tensor spectrum (real): [6][Hz][Hy][Sx], Hy = Py/2+1, Hz = Pz/2+1; the
+// Tensor spectrum (real), in the z pass's tile order: [Hy][ntz][6][Hz][tz],
+// Hy = Py/2+1, Hz = Pz/2+1, ntz = ceil(Hx/tz) column tiles of tz values; the
 // mirrored halves are read with the parity sign of each component.
 struct Plan {
     magx_dtype dtype;
@@ -32,6 +33,7 @@ struct Plan {
     long long scratch_a_elems, scratch_b_elems;
     // column tiles of the y and z passes, pencils per block of the x passes
     int ty, tz, np;
+    int ntz;                    // column tiles of the z pass (and of the tensor spectrum)
     int pencil_blocks;
     // workspace layout (bytes)
     size_t off_x1, off_x2, off_f[5], off_part, ws_bytes;

@@ -171,8 +171,11 @@ __global__ void __launch_bounds__(kNT) newell_octant_kernel(double* __restrict__
 // (parity bit mask `odd`, bit c), wgt_0 = 1, wgt_j = 2; scale_c = -scale for
 // components in the mask `neg`, else scale.  The output row q is
 // written at ((q / orow) * ostride + q % orow) inside component c's slab of
-// oslab elements (this lays the last pass out with padded kx rows).
-template <typename TO>
+// oslab elements.  With TILED (the last pass, q = ky * Hx + kx, k = kz) the
+// output is the z pass's layout [Hy][ntz][6][Hz][tz]: for each row ky and
+// column tile of tz values, the six components' Hz x tz blocks back to back
+// (orow = Hx, ostride = tz, oslab = ntz, and Hz = K).
+template <typename TO, bool TILED>
 __global__ void __launch_bounds__(kNT) axis_transform_kernel(const double* __restrict__ in, TO* __restrict__ out,
                                                              int Q, int J, int K, int P, int lgP, unsigned odd,
                                                              double scale, unsigned neg, long long islab,
@@ -228,8 +231,15 @@ __global__ void __launch_bounds__(kNT) axis_transform_kernel(const double* __res
         for (int b = 0; b < 4; ++b) {
             const int q = q0 + tq + 16 * b;
             if (q >= Q) continue;
-            const long long o = (long long)c * oslab + (long long)k * ((long long)(Q / orow) * ostride) +
-                                (long long)(q / orow) * ostride + (q % orow);
+            long long o;
+            if constexpr (TILED) {
+                const int ky = q / orow, kx = q % orow;
+                const int tile = kx / ostride, col = kx % ostride;
+                o = ((((long long)ky * oslab + tile) * 6 + c) * K + k) * ostride + col;
+            } else {
+                o = (long long)c * oslab + (long long)k * ((long long)(Q / orow) * ostride) +
+                    (long long)(q / orow) * ostride + (q % orow);
+            }
             out[o] = (TO)(sc * acc[a][b]);
         }
     }
@@ -295,7 +305,7 @@ hipError_t build_tensor_spectrum(const Plan& pl, void* spectrum, void* scratch, 
     {
         const int Q = nz * ny, J = nx, K = pl.Hx;
         dim3 grid((Q + 63) / 64, (K + 31) / 32, 6);
-        hipLaunchKernelGGL(axis_transform_kernel<double>, grid, dim3(kNT), 0, s, oct, t1, Q, J, K, pl.Px, pl.lgPx,
+        hipLaunchKernelGGL((axis_transform_kernel<double, false>), grid, dim3(kNT), 0, s, oct, t1, Q, J, K, pl.Px, pl.lgPx,
                            kOddX, 1.0, 0u, n, Q, Q, (long long)K * Q);
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     }
@@ -303,26 +313,26 @@ hipError_t build_tensor_spectrum(const Plan& pl, void* spectrum, void* scratch, 
     {
         const int Q = pl.Hx * nz, J = ny, K = pl.Hy;
         dim3 grid((Q + 63) / 64, (K + 31) / 32, 6);
-        hipLaunchKernelGGL(axis_transform_kernel<double>, grid, dim3(kNT), 0, s, t1, t2, Q, J, K, pl.Py, pl.lgPy,
+        hipLaunchKernelGGL((axis_transform_kernel<double, false>), grid, dim3(kNT), 0, s, t1, t2, Q, J, K, pl.Py, pl.lgPy,
                            kOddY, 1.0, 0u, (long long)pl.Hx * nz * ny, Q, Q, (long long)K * Q);
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     }
-    // z: in [6][Hy*Hx][nz] -> spectrum [6][Hz][Hy][Sx] (rows of Hx, stride Sx),
-    // scaled by 1/(Px Py Pz) and by -1 for the off-diagonal components.
+    // z: in [6][Hy*Hx][nz] -> spectrum in the z pass's layout
+    // [Hy][ntz][6][Hz][tz], scaled by 1/(Px Py Pz) and by -1 for the
+    // off-diagonal components.  Columns kx >= Hx of the last tile are never read.
     {
         const int Q = pl.Hy * pl.Hx, J = nz, K = pl.Hz;
         dim3 grid((Q + 63) / 64, (K + 31) / 32, 6);
         const double sc = 1.0 / ((double)pl.Px * pl.Py * pl.Pz);
         const unsigned offdiag = (1u << 3) | (1u << 4) | (1u << 5);
-        const long long slab = (long long)pl.Hz * pl.Hy * pl.Sx;
         if (pl.dtype == MAGX_F32) {
-            hipLaunchKernelGGL(axis_transform_kernel<float>, grid, dim3(kNT), 0, s, t2,
+            hipLaunchKernelGGL((axis_transform_kernel<float, true>), grid, dim3(kNT), 0, s, t2,
                                static_cast<float*>(spectrum), Q, J, K, pl.Pz, pl.lgPz, kOddZ, sc, offdiag,
-                               (long long)pl.Hy * pl.Hx * nz, pl.Hx, pl.Sx, slab);
+                               (long long)pl.Hy * pl.Hx * nz, pl.Hx, pl.tz, (long long)pl.ntz);
         } else {
-            hipLaunchKernelGGL(axis_transform_kernel<double>, grid, dim3(kNT), 0, s, t2,
+            hipLaunchKernelGGL((axis_transform_kernel<double, true>), grid, dim3(kNT), 0, s, t2,
                                static_cast<double*>(spectrum), Q, J, K, pl.Pz, pl.lgPz, kOddZ, sc, offdiag,
-                               (long long)pl.Hy * pl.Hx * nz, pl.Hx, pl.Sx, slab);
+                               (long long)pl.Hy * pl.Hx * nz, pl.Hx, pl.tz, (long long)pl.ntz);
         }
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     }

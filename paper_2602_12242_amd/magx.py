@@ -54,8 +54,8 @@ class magx_size_info(ctypes.Structure):
 EXPORTS = ("magx_sizes", "magx_sizes_batched", "magx_tensor_init", "magx_tensor_init_batched",
            "magx_set_member_bias", "magx_ctx_batch", "magx_heff", "magx_llg_rhs", "magx_step", "magx_step_mri",
            "magx_heff_backward", "magx_step_backward", "magx_rollout_forward", "magx_rollout_backward",
-           "magx_energy", "magx_heff_count", "magx_ctx_info", "magx_profile_start", "magx_profile_stop",
-           "magx_strerror", "magx_destroy")
+           "magx_energy", "magx_heff_count", "magx_ctx_info", "magx_spectrum_layout", "magx_profile_start",
+           "magx_profile_stop", "magx_strerror", "magx_destroy")
 
 _lib = None
 
@@ -88,6 +88,7 @@ def load(path=LIB_PATH):
         "magx_energy": (i, [vp, vp, P(magx_params), vp, vp, vp]),
         "magx_heff_count": (ctypes.c_longlong, [vp]),
         "magx_ctx_info": (i, [vp, P(magx_grid), P(ctypes.c_int)]),
+        "magx_spectrum_layout": (i, [vp, P(ctypes.c_int)]),
         "magx_profile_start": (i, [vp, i]),
         "magx_profile_stop": (i, [vp, P(ctypes.c_longlong), P(ctypes.c_double)]),
         "magx_strerror": (ctypes.c_char_p, [i]),
@@ -195,13 +196,16 @@ class Context:
             raise ValueError(f"{name}: expected contiguous {self.tdtype} {self.shape} on {self.device}")
 
     def spectrum_array(self):
-        """The stored tensor spectrum as a (6, Hz, Hy, Sx) view (for tests)."""
+        """The stored tensor spectrum as a logical (6, Hz, Hy, Hx) array (for tests)."""
         nx, ny, nz = self.n
         Px, Py, Pz = (max(2, 1 << (2 * v - 1).bit_length()) for v in (nx, ny, nz))
-        Hx, Hy, Hz = Px // 2 + 1, Py // 2 + 1, Pz // 2 + 1
-        Sx = (Hx + 15) // 16 * 16
-        el = self.spectrum.view(self.tdtype)
-        return el[: 6 * Hz * Hy * Sx].view(6, Hz, Hy, Sx)[..., :Hx], (Px, Py, Pz)
+        Hx = Px // 2 + 1
+        dims = (ctypes.c_int * 5)()
+        _check(self.lib.magx_spectrum_layout(self.h, dims), "magx_spectrum_layout")
+        Hy, ntz, six, Hz, tz = (int(v) for v in dims)
+        el = self.spectrum.view(self.tdtype)[: Hy * ntz * six * Hz * tz]
+        arr = el.view(Hy, ntz, six, Hz, tz).permute(2, 3, 0, 1, 4).reshape(six, Hz, Hy, ntz * tz)
+        return arr[..., :Hx], (Px, Py, Pz)
 
     def set_member_bias(self, hbias):
         """Per-member bias fields, a (nbatch, 3) tensor of the context type on its

@@ -138,6 +138,15 @@ def test_entry_points_reject_null_arguments_without_a_gpu():
     assert lib.magx_strerror(-2) == b"grid too large for the FFT passes"
 
 
+def test_binding_wraps_every_entry_point():
+    from paper_2602_12242_amd import magx
+    for name in ("heff", "llg_rhs", "step", "step_mri", "heff_backward", "step_backward", "rollout_forward",
+                 "rollout_backward", "energy", "set_member_bias", "spectrum_array", "profile_start",
+                 "profile_stop", "tape", "checkpoint_store", "field"):
+        assert callable(getattr(magx.Context, name)), name
+    assert isinstance(magx.Context.heff_count, property)
+
+
 def test_context_requires_library(monkeypatch, tmp_path):
     from paper_2602_12242_amd import magx
     monkeypatch.setattr(magx, "_lib", None)
