@@ -128,6 +128,11 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
         if ((long long)p.Hy * p.ntz * 6 * p.Hz * tz >= (1LL << 31)) return MAGX_ESIZE;
     }
     p.np = std::max(1, 1024 / p.Lh);
+    // tuning override of the pencils per block (within the register budget)
+    if (const char* e = std::getenv("MAGX_PENCILS")) {
+        const int t = std::atoi(e);
+        if (t >= 1 && t <= p.np) p.np = t;
+    }
     const int npen = p.ny * p.nz;
     if (p.np > npen) p.np = npen;
     // pencil blocks never straddle two members (the last one of a member may be ragged)

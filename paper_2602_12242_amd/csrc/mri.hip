@@ -98,16 +98,20 @@ __global__ void __launch_bounds__(kNT) mri_fast_kernel(const R* __restrict__ v, 
     qbuf += mo;
     rbuf += mo;
     const bool vec = (g.nx & 1) == 0;
-    R keep[maxslot<BIG>()][2][3];
+    // v_out also goes into this thread's LDS line entries for the forward x pass
 #pragma unroll
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) keep[i][q][0] = keep[i][q][1] = keep[i][q][2] = (R)0;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
         const int x0 = 2 * n;
-        if (x0 >= g.nx) continue;
+        if (x0 >= g.nx) {
+            if (fwd) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>((R)0, (R)0);
+            }
+            continue;
+        }
         const bool two = x0 + 1 < g.nx;
         int yy, z;
         pen_coords<R>(g, pen0 + p, yy, z);
@@ -136,21 +140,12 @@ __global__ void __launch_bounds__(kNT) mri_fast_kernel(const R* __restrict__ v, 
         }
         store_pair(qbuf, g.N, id, vec, two, q[0], q[1]);
         store_pair(vout, g.N, id, vec, two, xn[0], xn[1]);
+        if (fwd) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            keep[i][0][c] = xn[0][c];
-            keep[i][1][c] = two ? xn[1][c] : (R)0;
+            for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(xn[0][c], two ? xn[1][c] : (R)0);
         }
     }
     if (!fwd) return;
-#pragma unroll
-    for (int i = 0; i < maxslot<BIG>(); ++i) {
-        const int e = threadIdx.x + i * kNT;
-        if (e >= npen * g.Lh) continue;
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
-    }
     r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 

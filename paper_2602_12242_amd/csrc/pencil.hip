@@ -156,16 +156,22 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
     const R cw[4] = {(R)0, (R)0.5, (R)0.5, (R)1};
     const int s = a.stage;
     const bool norm = (s < 4) ? (ph.renorm == 2) : (ph.renorm >= 1);
-    R keep[maxslot<BIG>()][2][3];
+    // the next stage input goes straight into this thread's own LDS line
+    // entries (the ones it read the demag field from) for the forward x pass
+    const bool fwd = a.want_next && has_demag;
 #pragma unroll
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) keep[i][q][0] = keep[i][q][1] = keep[i][q][2] = (R)0;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
         const int x0 = 2 * n;
-        if (x0 >= g.nx) continue;
+        if (x0 >= g.nx) {
+            if (fwd) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>((R)0, (R)0);
+            }
+            continue;
+        }
         const bool two = x0 + 1 < g.nx;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
@@ -221,22 +227,12 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
         }
         store_pair(a.yout, g.N, id, vec, two, xn[0], xn[1]);
         if (a.yout2) store_pair(a.yout2, g.N, id, vec, two, xn[0], xn[1]);
+        if (fwd) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            keep[i][0][c] = xn[0][c];
-            keep[i][1][c] = two ? xn[1][c] : (R)0;
+            for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(xn[0][c], two ? xn[1][c] : (R)0);
         }
     }
-    if (!(a.want_next && has_demag)) return;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < maxslot<BIG>(); ++i) {
-        const int e = threadIdx.x + i * kNT;
-        if (e >= npen * g.Lh) continue;
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
-    }
+    if (!fwd) return;
     r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 
@@ -264,16 +260,20 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
     const bool norm = ph.renorm >= 1;
     const R b4 = (R)(1.0 / 6.0);
     double hs[3] = {0, 0, 0};
-    R keep[maxslot<BIG>()][2][3];
+    // mu_4 goes straight into this thread's LDS line entries for the forward x pass
 #pragma unroll
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) keep[i][q][0] = keep[i][q][1] = keep[i][q][2] = (R)0;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
         const int x0 = 2 * n;
-        if (x0 >= g.nx) continue;
+        if (x0 >= g.nx) {
+            if (has_demag) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>((R)0, (R)0);
+            }
+            continue;
+        }
         const bool two = x0 + 1 < g.nx;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
@@ -313,8 +313,7 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
         for (int c = 0; c < 3; ++c) {
             const R m1 = two ? mu[1][c] : (R)0;
             hs[c] += (double)mu[0][c] + (double)m1;
-            keep[i][0][c] = mu[0][c];
-            keep[i][1][c] = m1;
+            if (has_demag) buf[(3 * p + c) * g.Lh + n] = mk<R>(mu[0][c], m1);
         }
     }
     if (ph.terms & MAGX_ZEEMAN) {
@@ -324,15 +323,6 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
         }
     }
     if (!has_demag) return;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < maxslot<BIG>(); ++i) {
-        const int e = threadIdx.x + i * kNT;
-        if (e >= npen * g.Lh) continue;
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
-    }
     r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 
@@ -366,16 +356,22 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
     const int s = a.stage;
     const bool norm = ph.renorm == 2;
     double hs[3] = {0, 0, 0};
-    R keep[maxslot<BIG>()][2][3];
+    // mu_{s-1} goes straight into this thread's own LDS line entries (read
+    // above for K mu_s) for the forward x pass
+    const bool fwd = s > 1 && has_demag;
 #pragma unroll
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
-#pragma unroll
-        for (int q = 0; q < 2; ++q) keep[i][q][0] = keep[i][q][1] = keep[i][q][2] = (R)0;
         if (e >= npen * g.Lh) continue;
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
         const int x0 = 2 * n;
-        if (x0 >= g.nx) continue;
+        if (x0 >= g.nx) {
+            if (fwd) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>((R)0, (R)0);
+            }
+            continue;
+        }
         const bool two = x0 + 1 < g.nx;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
@@ -441,8 +437,7 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
             for (int c = 0; c < 3; ++c) {
                 const R m1 = two ? mup[1][c] : (R)0;
                 hs[c] += (double)mup[0][c] + (double)m1;
-                keep[i][0][c] = mup[0][c];
-                keep[i][1][c] = m1;
+                if (fwd) buf[(3 * p + c) * g.Lh + n] = mk<R>(mup[0][c], m1);
             }
         } else {
 #pragma unroll
@@ -458,16 +453,7 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
             if (threadIdx.x == 0) partials[lb * 8 + v] += sm;
         }
     }
-    if (s == 1 || !has_demag) return;
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < maxslot<BIG>(); ++i) {
-        const int e = threadIdx.x + i * kNT;
-        if (e >= npen * g.Lh) continue;
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(keep[i][0][c], keep[i][1][c]);
-    }
+    if (!fwd) return;
     r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 
