@@ -11,6 +11,9 @@ Test infrastructure only.
 * Classical RK4 with fixed dt and four right-hand-side evaluations per step
   (Section III-C and its integrator comparison table): c = (0, 1/2, 1/2, 1),
   b = (1/6, 1/3, 1/3, 1/6).
+* Forward Euler (the integrator of the paper's scaling runs) and a
+  time-dependent uniform bias H_bias(t) (piecewise linear in time), the bias
+  of each stage taken at that stage's time.
 * Energy: sum of the densities of Eqs. (4), (6), (8), the DMI density whose
   variational derivative is Eq. (9), and the Zeeman density.  Because
   H_eff = K m + H_bias with K symmetric, the total equals
@@ -18,6 +21,8 @@ Test infrastructure only.
   printed lacks the factor Ms; the dimensionally consistent -(mu0 Ms/2) m.H
   is used.
 """
+from dataclasses import replace
+
 import numpy as np
 
 from . import field
@@ -58,9 +63,36 @@ RK4_C = (0.0, 0.5, 0.5, 1.0)
 RK4_B = (1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0)
 
 
-def rk4_step(grid, p, m, dt, spec=None, pshape=None, record=None):
+def bias_schedule(times, values):
+    """Time-dependent uniform bias field (NEXT row f3): piecewise-linear
+    interpolation of the (time, H) knots, held constant before the first and
+    after the last knot.  Returns t -> H (3,)."""
+    times = np.asarray(times, dtype=np.float64)
+    values = np.asarray(values, dtype=np.float64).reshape(-1, 3)
+
+    def at(t):
+        return np.array([np.interp(t, times, values[:, c]) for c in range(3)])
+    return at
+
+
+def with_bias(p, h):
+    return replace(p, Hbias=tuple(float(v) for v in h))
+
+
+def euler_step(grid, p, m, dt, spec=None, pshape=None, t0=0.0, bias_at=None):
+    """Forward Euler (used by the paper for its weak-scaling runs):
+    m_{n+1} = m_n + dt R(m_n), renormalised when renorm >= 1.  With bias_at,
+    H_bias is taken at the step's start time t0."""
+    m = np.asarray(m, dtype=np.float64)
+    q = with_bias(p, bias_at(t0)) if bias_at is not None else p
+    x = m + dt * rhs(grid, q, m, spec, pshape)
+    return normalize(x)[0] if p.renorm >= 1 else x
+
+
+def rk4_step(grid, p, m, dt, spec=None, pshape=None, record=None, t0=0.0, bias_at=None):
     """One classical RK4 step.  If `record` is a list, the stage inputs y_s,
-    fields H_s, pre-normalisation vectors x_s and their norms are appended."""
+    fields H_s, pre-normalisation vectors x_s and their norms are appended.
+    With bias_at (time -> H_bias), stage s sees the bias at t0 + c_s dt."""
     stage_norm = p.renorm == 2
     m = np.asarray(m, dtype=np.float64)
     y = m
@@ -69,8 +101,9 @@ def rk4_step(grid, p, m, dt, spec=None, pshape=None, record=None):
     ys = [m]
     Hs = []
     for s in range(4):
-        H = field.heff(grid, p, y, spec, pshape)
-        k = rhs_from_field(p, y, H)
+        ps = with_bias(p, bias_at(t0 + RK4_C[s] * dt)) if bias_at is not None else p
+        H = field.heff(grid, ps, y, spec, pshape)
+        k = rhs_from_field(ps, y, H)
         Hs.append(H)
         ks.append(k)
         if s < 3:

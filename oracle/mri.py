@@ -84,10 +84,12 @@ def substeps(dc, dt, dt_fast):
     return max(1, int(math.ceil(dc * dt / dt_fast * (1.0 - 1e-12))))
 
 
-def mis_step(f_fast, f_slow, y, dt, dt_fast, stage_map=None):
+def mis_step(f_fast, f_slow, y, dt, dt_fast, stage_map=None, slow_time=False):
     """One MIS step of the Knoth-Wolke pair for y' = f_fast(y) + f_slow(y).
     stage_map (optional) is applied to each slow stage value Y_2..Y_{s+1}
-    (renormalisation).  Returns (y_{n+1}, slow stage values, fast evaluations)."""
+    (renormalisation).  With slow_time, f_slow(Y, c) also receives the node
+    c_i of the slow stage (non-autonomous slow part, e.g. a time-dependent
+    bias field).  Returns (y_{n+1}, slow stage values, fast evaluations)."""
     A, b, c = _float_table()
     Arows = A + [b]
     cc = c + [1.0]
@@ -95,7 +97,7 @@ def mis_step(f_fast, f_slow, y, dt, dt_fast, stage_map=None):
     S = []
     nfast = 0
     for i in range(1, 4):
-        S.append(f_slow(Y[i - 1]))
+        S.append(f_slow(Y[i - 1], cc[i - 1]) if slow_time else f_slow(Y[i - 1]))
         dc = cc[i] - cc[i - 1]
         r = 0.0
         for j in range(i):
@@ -137,19 +139,24 @@ def slow_rhs(grid, p, m, spec=None, pshape=None):
     return rhs_from_field(p, m, hs)
 
 
-def mri_step(grid, p, m, dt, dt_fast, spec=None, pshape=None):
+def mri_step(grid, p, m, dt, dt_fast, spec=None, pshape=None, t0=0.0, bias_at=None):
     """One multirate step of the LLG equation.  Returns (m_{n+1}, number of
-    slow evaluations, number of fast evaluations)."""
+    slow evaluations, number of fast evaluations).  With bias_at (time ->
+    H_bias), slow stage i sees the bias at t0 + c_i dt."""
+    from .llg import with_bias
     m = np.asarray(m, dtype=np.float64)
     stage_map = (lambda v: normalize(v)[0]) if p.renorm == 2 else None
-    out, _, nfast = mis_step(lambda u: fast_rhs(grid, p, u), lambda u: slow_rhs(grid, p, u, spec, pshape), m, dt,
-                             dt_fast, stage_map)
+    if bias_at is None:
+        f_slow = lambda u, c: slow_rhs(grid, p, u, spec, pshape)  # noqa: E731
+    else:
+        f_slow = lambda u, c: slow_rhs(grid, with_bias(p, bias_at(t0 + c * dt)), u, spec, pshape)  # noqa: E731
+    out, _, nfast = mis_step(lambda u: fast_rhs(grid, p, u), f_slow, m, dt, dt_fast, stage_map, slow_time=True)
     if p.renorm >= 1 and stage_map is None:
         out = normalize(out)[0]
     return out, 3, nfast
 
 
-def mri_run(grid, p, m, dt, dt_fast, nsteps, spec=None, pshape=None):
-    for _ in range(nsteps):
-        m = mri_step(grid, p, m, dt, dt_fast, spec, pshape)[0]
+def mri_run(grid, p, m, dt, dt_fast, nsteps, spec=None, pshape=None, t0=0.0, bias_at=None):
+    for n in range(nsteps):
+        m = mri_step(grid, p, m, dt, dt_fast, spec, pshape, t0 + n * dt, bias_at)[0]
     return m
