@@ -58,7 +58,7 @@ extern "C" {
 #define MAGX_EWORKSPACE -4   /* reserved: buffer sizes are the caller's contract (see magx_sizes) */
 #define MAGX_EHIP       -5   /* a HIP call failed */
 #define MAGX_ENONFINITE -6   /* reserved: non-finite state */
-#define MAGX_ESTATE     -7   /* reserved */
+#define MAGX_ESTATE     -7   /* reverse mode or checkpointed rollout asked for while a bias schedule is set */
 
 /* ---- field terms (bit mask), Eq. (2) -------------------------------------- */
 #define MAGX_DEMAG   1u   /* Eq. (3): demagnetising field                    */
@@ -159,6 +159,29 @@ int magx_llg_rhs(magx_ctx* ctx, const void* m, const void* H,
  * field and pre-normalisation length is recorded for magx_step_backward. */
 int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps,
               void* tape, void* ws, void* stream);
+
+/* Advances m (device, in place) by nsteps forward Euler steps
+ * m <- m + dt R(m) (the integrator of the paper's scaling runs, Section IV),
+ * one field evaluation per step, renormalising the new state when
+ * p->renorm >= 1.  ws: workspace of workspace_bytes. */
+int magx_step_euler(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps,
+                    void* ws, void* stream);
+
+/* Time-dependent uniform bias field.  times (host, n strictly increasing
+ * values, s) and values (host, n x 3, A/m) are knots of a piecewise-linear
+ * H_bias(t), held constant before the first and after the last knot; the
+ * context copies them.  t0 sets the context's clock.  While a schedule is set
+ * it replaces p->Hbias: magx_heff and magx_energy use H_bias(clock), every
+ * stage of magx_step, magx_step_euler and magx_step_mri uses the bias at its
+ * own stage time, and those calls advance the clock by nsteps*dt.  A
+ * per-member bias table (magx_set_member_bias) takes precedence.  The reverse
+ * mode and the checkpointed rollouts return MAGX_ESTATE while a schedule is
+ * set (their gradient is with respect to a constant bias).  n = 0 removes
+ * the schedule (times and values may then be NULL).  Host only. */
+int magx_set_bias_schedule(magx_ctx* ctx, int n, const double* times, const double* values,
+                           double t0);
+/* The context's clock (s), see magx_set_bias_schedule.  Host only. */
+int magx_get_time(const magx_ctx* ctx, double* t);
 
 /* Advances m (device, in place) by nsteps explicit-explicit multirate steps
  * of size dt (Section III-C, integrator comparison): the LLG torque of the

@@ -1,6 +1,7 @@
 // C ABI of the magx library: argument validation, planning, buffer layout and
 // launch sequencing on the caller's stream.  Every numeric step runs in the
 // HIP kernels of tensor.hip, conv.hip and pencil.hip.
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -17,6 +18,9 @@ struct magx_ctx {
     Plan pl;
     void* spectrum;
     const void* hbias_members;   // optional per-member bias fields (device, nbatch x 3)
+    // time-dependent uniform bias: knots (host) and the context's clock
+    std::vector<double> sched_t, sched_h;
+    double time;
     long long heff_count;
     int device;
     // launch timing of one kernel family (diagnostics)
@@ -200,6 +204,38 @@ static Phys<R> make_phys(const Plan& pl, const magx_params* p, const void* hbias
     return ph;
 }
 
+// H_bias at time t: the schedule's piecewise-linear value (held constant
+// outside its knots) if one is set, else the parameter's constant bias.
+static void bias_at(const magx_ctx* c, const magx_params* p, double t, double h[3]) {
+    const size_t n = c->sched_t.size();
+    if (n == 0) {
+        for (int k = 0; k < 3; ++k) h[k] = p->Hbias[k];
+        return;
+    }
+    const std::vector<double>& T = c->sched_t;
+    const std::vector<double>& V = c->sched_h;
+    if (t <= T[0] || n == 1) {
+        for (int k = 0; k < 3; ++k) h[k] = V[k];
+        return;
+    }
+    if (t >= T[n - 1]) {
+        for (int k = 0; k < 3; ++k) h[k] = V[3 * (n - 1) + k];
+        return;
+    }
+    size_t i = std::upper_bound(T.begin(), T.end(), t) - T.begin();   // T[i-1] <= t < T[i]
+    const double w = (t - T[i - 1]) / (T[i] - T[i - 1]);
+    for (int k = 0; k < 3; ++k) h[k] = V[3 * (i - 1) + k] + w * (V[3 * i + k] - V[3 * (i - 1) + k]);
+}
+
+template <typename R>
+static Phys<R> phys_at(const magx_ctx* c, const magx_params* p, double t) {
+    Phys<R> ph = make_phys<R>(c->pl, p, c->hbias_members);
+    double h[3];
+    bias_at(c, p, t, h);
+    for (int k = 0; k < 3; ++k) ph.hb[k] = (R)h[k];
+    return ph;
+}
+
 static std::mutex g_tw_mutex;
 static bool g_tw_ready[64];
 
@@ -245,7 +281,7 @@ template <typename R>
 static int do_heff(magx_ctx* c, const R* m, const magx_params* p, R* H, void* ws, hipStream_t s, int energy,
                    double* e_out) {
     const Plan& pl = c->pl;
-    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
+    Phys<R> ph = phys_at<R>(c, p, c->time);
     void* X1 = bptr(ws, pl.off_x1);
     double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
     if (p->terms & MAGX_DEMAG) {
@@ -288,6 +324,8 @@ static int do_step(magx_ctx* c, R* m, const magx_params* p, double dt, int nstep
                    hipStream_t s) {
     const Plan& pl = c->pl;
     Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
+    const bool timed = !c->sched_t.empty();
+    static const double kC[4] = {0.0, 0.5, 0.5, 1.0};   // stage times of classical RK4
     const bool demag = (p->terms & MAGX_DEMAG) != 0;
     void* X1 = bptr(ws, pl.off_x1);
     R* acc = reinterpret_cast<R*>(bptr(ws, pl.off_f[0]));
@@ -318,9 +356,53 @@ static int do_step(magx_ctx* c, R* m, const magx_params* p, double dt, int nstep
             a.dt = (R)dt;
             a.want_next = !(n == nsteps - 1 && st == 4);
             ProfScope ps(c, kProfStage, s);
-            if (launch_stage<R>(pl, ph, X1, X1, a, s) != hipSuccess) return MAGX_EHIP;
+            const Phys<R> phs = timed ? phys_at<R>(c, p, c->time + (n + kC[st - 1]) * dt) : ph;
+            if (launch_stage<R>(pl, phs, X1, X1, a, s) != hipSuccess) return MAGX_EHIP;
         }
     }
+    if (timed) c->time += nsteps * dt;
+    return MAGX_OK;
+}
+
+// Forward Euler (stage 0 of the stage kernel), ping-pong between m and a
+// workspace field.
+template <typename R>
+static int do_step_euler(magx_ctx* c, R* m, const magx_params* p, double dt, int nsteps, void* ws,
+                         hipStream_t s) {
+    const Plan& pl = c->pl;
+    const bool demag = (p->terms & MAGX_DEMAG) != 0;
+    const bool timed = !c->sched_t.empty();
+    void* X1 = bptr(ws, pl.off_x1);
+    R* acc = reinterpret_cast<R*>(bptr(ws, pl.off_f[0]));
+    R* W = reinterpret_cast<R*>(bptr(ws, pl.off_f[1]));
+    R* cur = m;
+    R* oth = W;
+    if (demag) {
+        ProfScope ps(c, kProfXfwd, s);
+        if (launch_xfwd<R>(pl, cur, X1, s) != hipSuccess) return MAGX_EHIP;
+    }
+    for (int n = 0; n < nsteps; ++n) {
+        if (demag) {
+            int rc = conv_passes<R>(c, ws, (R)p->Ms, s);
+            if (rc) return rc;
+        } else {
+            c->heff_count++;
+        }
+        StageArgs<R> a{};
+        a.yin = cur;
+        a.mn = cur;
+        a.acc = acc;
+        a.yout = oth;
+        a.stage = 0;
+        a.dt = (R)dt;
+        a.want_next = n < nsteps - 1;
+        const Phys<R> ph = phys_at<R>(c, p, c->time + n * dt);
+        ProfScope ps(c, kProfStage, s);
+        if (launch_stage<R>(pl, ph, X1, X1, a, s) != hipSuccess) return MAGX_EHIP;
+        std::swap(cur, oth);
+    }
+    if (cur != m && launch_copy<R>(cur, m, 3 * pl.ncell * pl.nbatch, s) != hipSuccess) return MAGX_EHIP;
+    if (timed) c->time += nsteps * dt;
     return MAGX_OK;
 }
 
@@ -439,6 +521,7 @@ static int do_step_mri(magx_ctx* c, R* m, const magx_params* p, double dt, doubl
     pfast.terms = ph.terms & MAGX_EXCH;
     pslow.terms = ph.terms & ~MAGX_EXCH;
     const bool demag = (p->terms & MAGX_DEMAG) != 0;
+    const bool timed = !c->sched_t.empty();
     void* X1 = bptr(ws, pl.off_x1);
     R* S1 = reinterpret_cast<R*>(bptr(ws, pl.off_f[0]));
     R* S2 = reinterpret_cast<R*>(bptr(ws, pl.off_f[1]));
@@ -469,8 +552,13 @@ static int do_step_mri(magx_ctx* c, R* m, const magx_params* p, double dt, doubl
             R* Sout = i == 0 ? S1 : (i == 1 ? S2 : nullptr);
             const R* Sa = i >= 1 ? S1 : nullptr;
             const R* Sb = i >= 2 ? S2 : nullptr;
-            if (launch_mri_slow<R>(pl, pslow, X1, cur, demag ? 1 : 0, Sout, Sa, Sb, (R)kw.w[i][0], (R)kw.w[i][1],
-                                   (R)kw.w[i][i], rf, s) != hipSuccess)
+            Phys<R> pslow_t = pslow;
+            if (timed) {
+                pslow_t = phys_at<R>(c, p, c->time + (n + kw.c[i]) * dt);
+                pslow_t.terms = ph.terms & ~MAGX_EXCH;
+            }
+            if (launch_mri_slow<R>(pl, pslow_t, X1, cur, demag ? 1 : 0, Sout, Sa, Sb, (R)kw.w[i][0],
+                                   (R)kw.w[i][1], (R)kw.w[i][i], rf, s) != hipSuccess)
                 return MAGX_EHIP;
             for (long long sub = 0; sub < nsub[i]; ++sub) {
                 for (int k = 0; k < 3; ++k) {
@@ -486,6 +574,7 @@ static int do_step_mri(magx_ctx* c, R* m, const magx_params* p, double dt, doubl
         }
     }
     if (cur != m && launch_copy<R>(cur, m, 3 * pl.ncell * pl.nbatch, s) != hipSuccess) return MAGX_EHIP;
+    if (timed) c->time += nsteps * dt;
     return MAGX_OK;
 }
 
@@ -530,6 +619,7 @@ int magx_tensor_init_batched(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, 
     c->pl = pl;
     c->spectrum = spectrum;
     c->hbias_members = nullptr;
+    c->time = 0.0;
     c->heff_count = 0;
     c->device = dev;
     c->prof_kind = 0;
@@ -599,6 +689,37 @@ int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nstep
     return do_step<double>(ctx, static_cast<double*>(m), p, dt, nsteps, static_cast<double*>(tape), ws, s);
 }
 
+int magx_step_euler(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps, void* ws, void* stream) {
+    if (!ctx || !m || !ws || nsteps < 0 || !std::isfinite(dt)) return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (nsteps == 0) return MAGX_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->pl.dtype == MAGX_F32)
+        return do_step_euler<float>(ctx, static_cast<float*>(m), p, dt, nsteps, ws, s);
+    return do_step_euler<double>(ctx, static_cast<double*>(m), p, dt, nsteps, ws, s);
+}
+
+int magx_set_bias_schedule(magx_ctx* ctx, int n, const double* times, const double* values, double t0) {
+    if (!ctx || n < 0 || !std::isfinite(t0)) return MAGX_EINVAL;
+    if (n > 0 && (!times || !values)) return MAGX_EINVAL;
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(times[i]) || (i > 0 && !(times[i] > times[i - 1]))) return MAGX_EINVAL;
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(values[3 * i + k])) return MAGX_EINVAL;
+    }
+    ctx->sched_t.assign(times, times + n);
+    ctx->sched_h.assign(values, values + 3 * (size_t)n);
+    ctx->time = t0;
+    return MAGX_OK;
+}
+
+int magx_get_time(const magx_ctx* ctx, double* t) {
+    if (!ctx || !t) return MAGX_EINVAL;
+    *t = ctx->time;
+    return MAGX_OK;
+}
+
 int magx_step_mri(magx_ctx* ctx, void* m, const magx_params* p, double dt, double dt_fast, int nsteps, void* ws,
                   void* stream) {
     if (!ctx || !m || !ws || nsteps < 0 || !std::isfinite(dt) || !(dt >= 0.0) || !std::isfinite(dt_fast) ||
@@ -618,6 +739,7 @@ int magx_step_mri(magx_ctx* ctx, void* m, const magx_params* p, double dt, doubl
 int magx_heff_backward(magx_ctx* ctx, const void* gH, const magx_params* p, void* gm, void* gHbias, void* ws,
                        void* stream) {
     if (!ctx || !gH || !gm || !gHbias || !ws) return MAGX_EINVAL;
+    if (!ctx->sched_t.empty()) return MAGX_ESTATE;
     int rc = check_params(p);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -631,6 +753,7 @@ int magx_heff_backward(magx_ctx* ctx, const void* gH, const magx_params* p, void
 int magx_step_backward(magx_ctx* ctx, const void* tape, int nsteps, const magx_params* p, double dt, void* gm,
                        void* gHbias, void* ws, void* stream) {
     if (!ctx || !tape || !gm || !gHbias || !ws || nsteps < 0 || !std::isfinite(dt)) return MAGX_EINVAL;
+    if (!ctx->sched_t.empty()) return MAGX_ESTATE;
     int rc = check_params(p);
     if (rc) return rc;
     if (nsteps == 0) return MAGX_OK;
@@ -645,6 +768,7 @@ int magx_step_backward(magx_ctx* ctx, const void* tape, int nsteps, const magx_p
 int magx_rollout_forward(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps, int ckpt,
                          void* ckpt_store, void* ws, void* stream) {
     if (!ctx || !m || !ckpt_store || !ws || nsteps < 0 || ckpt < 1 || !std::isfinite(dt)) return MAGX_EINVAL;
+    if (!ctx->sched_t.empty()) return MAGX_ESTATE;
     int rc = check_params(p);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -667,6 +791,7 @@ int magx_rollout_backward(magx_ctx* ctx, const void* ckpt_store, const magx_para
     if (!ctx || !ckpt_store || !gm || !gHbias || !tape || !mwork || !ws || nsteps < 0 || ckpt < 1 ||
         !std::isfinite(dt))
         return MAGX_EINVAL;
+    if (!ctx->sched_t.empty()) return MAGX_ESTATE;
     int rc = check_params(p);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -732,7 +857,7 @@ const char* magx_strerror(int code) {
         case MAGX_EWORKSPACE: return "buffer too small";
         case MAGX_EHIP: return "HIP error";
         case MAGX_ENONFINITE: return "non-finite value";
-        case MAGX_ESTATE: return "context has no demag tensor";
+        case MAGX_ESTATE: return "not available while a bias schedule is set";
         default: return "unknown error";
     }
 }

@@ -86,7 +86,7 @@ struct StageArgs {
     R* tapeH;          // optional: field H_s
     R* tapeNx;         // optional: |x_{s+1}| before normalisation
     R* tapeYin;        // optional: copy of y_s
-    int stage;         // 1..4
+    int stage;         // 1..4, or 0 for a forward Euler step
     R dt;
     int want_next;     // 1: forward x pass of y_{s+1} into X1
 };

@@ -155,7 +155,8 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
     const R bw[4] = {(R)(1.0 / 6.0), (R)(1.0 / 3.0), (R)(1.0 / 3.0), (R)(1.0 / 6.0)};
     const R cw[4] = {(R)0, (R)0.5, (R)0.5, (R)1};
     const int s = a.stage;
-    const bool norm = (s < 4) ? (ph.renorm == 2) : (ph.renorm >= 1);
+    // stage 0 is a forward Euler step: m_{n+1} = y + dt k, renormalised like a new state
+    const bool norm = (s >= 1 && s < 4) ? (ph.renorm == 2) : (ph.renorm >= 1);
     // the next stage input goes straight into this thread's own LDS line
     // entries (the ones it read the demag field from) for the forward x pass
     const bool fwd = a.want_next && has_demag;
@@ -190,7 +191,7 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
         R k[2][3], mn[2][3], acc[2][3], xn[2][3], nrm[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) llg_rhs<R>(ys[q], H[q], ph.a, ph.alpha, k[q]);
-        if (s == 1) {
+        if (s <= 1) {
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -203,7 +204,9 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
         for (int q = 0; q < 2; ++q) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                if (s < 4) {
+                if (s == 0) {
+                    xn[q][c] = mn[q][c] + a.dt * k[q][c];
+                } else if (s < 4) {
                     acc[q][c] = (s == 1 ? (R)0 : acc[q][c]) + bw[s - 1] * k[q][c];
                     xn[q][c] = mn[q][c] + cw[s] * a.dt * k[q][c];
                 } else {
@@ -220,7 +223,7 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
                 }
             }
         }
-        if (s < 4) store_pair(a.acc, g.N, id, vec, two, acc[0], acc[1]);
+        if (s >= 1 && s < 4) store_pair(a.acc, g.N, id, vec, two, acc[0], acc[1]);
         if (a.tapeNx) {
             if (vec) *reinterpret_cast<cx<R>*>(a.tapeNx + id) = mk<R>(nrm[0], nrm[1]);
             else { a.tapeNx[id] = nrm[0]; if (two) a.tapeNx[id + 1] = nrm[1]; }

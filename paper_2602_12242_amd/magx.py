@@ -24,7 +24,8 @@ DEMAG, EXCH, DMI, ANIS, ZEEMAN = 1, 2, 4, 8, 16
 F32, F64 = 0, 1
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "grid too large", -3: "unknown element type",
-          -4: "buffer too small", -5: "HIP error", -6: "non-finite value", -7: "no demag tensor"}
+          -4: "buffer too small", -5: "HIP error", -6: "non-finite value",
+          -7: "not available while a bias schedule is set"}
 
 
 class MagxError(RuntimeError):
@@ -53,6 +54,7 @@ class magx_size_info(ctypes.Structure):
 
 EXPORTS = ("magx_sizes", "magx_sizes_batched", "magx_tensor_init", "magx_tensor_init_batched",
            "magx_set_member_bias", "magx_ctx_batch", "magx_heff", "magx_llg_rhs", "magx_step", "magx_step_mri",
+           "magx_step_euler", "magx_set_bias_schedule", "magx_get_time",
            "magx_heff_backward", "magx_step_backward", "magx_rollout_forward", "magx_rollout_backward",
            "magx_energy", "magx_heff_count", "magx_ctx_info", "magx_spectrum_layout", "magx_profile_start",
            "magx_profile_stop", "magx_strerror", "magx_destroy")
@@ -81,6 +83,9 @@ def load(path=LIB_PATH):
         "magx_llg_rhs": (i, [vp, vp, vp, P(magx_params), vp, vp]),
         "magx_step": (i, [vp, vp, P(magx_params), d, i, vp, vp, vp]),
         "magx_step_mri": (i, [vp, vp, P(magx_params), d, d, i, vp, vp]),
+        "magx_step_euler": (i, [vp, vp, P(magx_params), d, i, vp, vp]),
+        "magx_set_bias_schedule": (i, [vp, i, P(d), P(d), d]),
+        "magx_get_time": (i, [vp, P(d)]),
         "magx_heff_backward": (i, [vp, vp, P(magx_params), vp, vp, vp, vp]),
         "magx_step_backward": (i, [vp, vp, i, P(magx_params), d, vp, vp, vp, vp]),
         "magx_rollout_forward": (i, [vp, vp, P(magx_params), d, i, i, vp, vp, vp]),
@@ -255,6 +260,30 @@ class Context:
         _check(self.lib.magx_step_mri(self.h, _ptr(m), ctypes.byref(p), float(dt), dt_fast, int(nsteps),
                                       _ptr(self.ws), _stream()), "magx_step_mri")
         return m
+
+    def step_euler(self, m, p, dt, nsteps):
+        """Advances m in place by nsteps forward Euler steps."""
+        self._chk(m, "m")
+        _check(self.lib.magx_step_euler(self.h, _ptr(m), ctypes.byref(p), float(dt), int(nsteps), _ptr(self.ws),
+                                        _stream()), "magx_step_euler")
+        return m
+
+    def set_bias_schedule(self, times=None, values=None, t0=0.0):
+        """Piecewise-linear H_bias(t) knots (times (n,), values (n, 3), A/m);
+        None or empty removes the schedule.  Sets the context clock to t0."""
+        n = 0 if times is None else len(times)
+        if n:
+            tt = (ctypes.c_double * n)(*[float(v) for v in times])
+            vv = (ctypes.c_double * (3 * n))(*[float(x) for row in values for x in row])
+        else:
+            tt = vv = None
+        _check(self.lib.magx_set_bias_schedule(self.h, n, tt, vv, float(t0)), "magx_set_bias_schedule")
+
+    @property
+    def time(self):
+        t = ctypes.c_double()
+        _check(self.lib.magx_get_time(self.h, ctypes.byref(t)), "magx_get_time")
+        return float(t.value)
 
     def heff_backward(self, gH, p):
         self._chk(gH, "gH")
