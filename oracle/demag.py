@@ -18,7 +18,8 @@ from . import newell
 
 def demag_direct(grid, Ms, m):
     """O(N^2) sum over all source cells; the tensor is evaluated at every
-    signed offset directly (no parity folding)."""
+    signed offset directly (no parity folding).  Ms may be a scalar or a
+    per-cell array (nz, ny, nx): the source is M = Ms m."""
     nz, ny, nx = grid.shape
     k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     pos = np.stack([i.ravel(), j.ravel(), k.ravel()], axis=1)  # (N, 3) cell indices
@@ -31,13 +32,14 @@ def demag_direct(grid, Ms, m):
     full[0, 1] = full[1, 0] = T[3]
     full[0, 2] = full[2, 0] = T[4]
     full[1, 2] = full[2, 1] = T[5]
-    mv = m.reshape(3, n)
-    H = -Ms * np.einsum("abij,bj->ai", full, mv)
+    Mv = (np.asarray(Ms, dtype=np.float64) * m).reshape(3, n)
+    H = -np.einsum("abij,bj->ai", full, Mv)
     return H.reshape(m.shape)
 
 
 def demag_fft(grid, Ms, m, spec=None, pshape=None):
-    """Extended-grid FFT convolution.  spec: output of newell.spectrum."""
+    """Extended-grid FFT convolution.  spec: output of newell.spectrum.  Ms
+    may be a scalar or a per-cell array (nz, ny, nx)."""
     pz, py, px = pshape if pshape is not None else newell.padded_shape(grid)
     if spec is None:
         spec = newell.spectrum(grid, (pz, py, px))

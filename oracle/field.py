@@ -102,10 +102,78 @@ def check_params(p):
             raise ValueError("DMI boundary condition needs exchange with A > 0")
 
 
+# ---- geometry masks and space-dependent Ms (NEXT row f3) -------------------------
+# Ms(r) = Ms s(r) with s = p.ms_profile; s = 0 marks cells outside the magnet.
+# The demagnetising field is that of M = Ms(r) m (Eq. (3)); the local terms of
+# a cell use its own Ms in their prefactors (Eqs. (5), (7), (9)); the surface of
+# the magnet is a boundary like the faces of the grid: a neighbour outside the
+# magnet is replaced by the ghost of Eq. (10) built from the cell itself.  Cells
+# outside the magnet carry no field.
+
+def _masked_neighbours(grid, p, m, s):
+    """For each of the six directions, the neighbour values seen by every cell:
+    the neighbouring cell if it lies in the grid and in the magnet, else the
+    ghost m + h dm/dn of the boundary condition."""
+    dmi_on = p.has(TERM_DMI) and p.D != 0.0
+    kappa = -p.D / (2.0 * p.A) if dmi_on else 0.0
+    inside = s > 0
+    out = {}
+    for name, axis, sign, h in (("xp", 3, 1, grid.dx), ("xm", 3, -1, grid.dx), ("yp", 2, 1, grid.dy),
+                                ("ym", 2, -1, grid.dy), ("zp", 1, 1, grid.dz), ("zm", 1, -1, grid.dz)):
+        nb = np.zeros_like(m)
+        ok = np.zeros(m.shape[1:], dtype=bool)
+        src = [slice(None)] * 4
+        dst = [slice(None)] * 4
+        if sign > 0:
+            src[axis], dst[axis] = slice(1, None), slice(0, -1)
+        else:
+            src[axis], dst[axis] = slice(0, -1), slice(1, None)
+        nb[tuple(dst)] = m[tuple(src)]
+        ok[tuple(dst[1:])] = inside[tuple(src[1:])]
+        normal = np.zeros(3)
+        normal[3 - axis] = float(sign)          # axis 3 -> x, 2 -> y, 1 -> z
+        if dmi_on:
+            ax = np.cross(EZ, normal).reshape(3, 1, 1, 1)
+            ghost = m + h * kappa * _cross(np.broadcast_to(ax, m.shape), m)
+        else:
+            ghost = m
+        out[name] = np.where(ok[None], nb, ghost)
+    return out
+
+
+def heff_parts_masked(grid, p, m, spec=None, pshape=None):
+    s = np.asarray(p.ms_profile, dtype=np.float64)
+    if s.shape != tuple(grid.shape) or np.any(s < 0):
+        raise ValueError("ms_profile must be a non-negative (nz, ny, nx) array")
+    inside = s > 0
+    inv = np.where(inside, 1.0 / np.where(inside, s, 1.0), 0.0)      # 1/s inside, 0 outside
+    parts = {}
+    if p.has(TERM_DEMAG):
+        parts["demag"] = demag.demag_fft(grid, p.Ms * s, m, spec=spec, pshape=pshape) * inside[None]
+    if p.has(TERM_EXCH) or p.has(TERM_DMI):
+        nb = _masked_neighbours(grid, p, m, s)
+        if p.has(TERM_EXCH):
+            lap = ((nb["xp"] - 2 * m + nb["xm"]) / grid.dx ** 2 + (nb["yp"] - 2 * m + nb["ym"]) / grid.dy ** 2 +
+                   (nb["zp"] - 2 * m + nb["zm"]) / grid.dz ** 2)
+            parts["exch"] = (2.0 * p.A / (p.mu0 * p.Ms)) * inv[None] * lap
+        if p.has(TERM_DMI):
+            ddx = (nb["xp"] - nb["xm"]) / (2 * grid.dx)
+            ddy = (nb["yp"] - nb["ym"]) / (2 * grid.dy)
+            k = (2.0 * p.D / (p.mu0 * p.Ms)) * inv
+            parts["dmi"] = np.stack([k * ddx[2], k * ddy[2], -k * (ddx[0] + ddy[1])])
+    if p.has(TERM_ANIS):
+        parts["anis"] = anisotropy(p, m) * inv[None]
+    if p.has(TERM_ZEEMAN):
+        parts["zeeman"] = np.asarray(p.Hbias, np.float64).reshape(3, 1, 1, 1) * inside[None]
+    return parts
+
+
 def heff_parts(grid, p, m, spec=None, pshape=None):
     """Dictionary of the enabled field terms (A/m)."""
     check_params(p)
     m = np.asarray(m, dtype=np.float64)
+    if getattr(p, "ms_profile", None) is not None:
+        return heff_parts_masked(grid, p, m, spec, pshape)
     parts = {}
     if p.has(TERM_DEMAG):
         parts["demag"] = demag.demag_fft(grid, p.Ms, m, spec=spec, pshape=pshape)

@@ -122,13 +122,15 @@ def energy_parts(grid, p, m, spec=None, pshape=None):
     """Per-term energies (J): demag, exch, dmi, anis, zeeman, and total."""
     parts = field.heff_parts(grid, p, m, spec, pshape)
     V = grid.volume
+    # Ms of every cell (space-dependent with a profile; 0 outside the magnet)
+    s = np.ones(grid.shape) if getattr(p, "ms_profile", None) is None else np.asarray(p.ms_profile, np.float64)
     out = {}
     for name, H in parts.items():
-        e = -0.5 * p.mu0 * p.Ms * V * float(np.sum(m * H))
+        e = -0.5 * p.mu0 * p.Ms * V * float(np.sum(s[None] * m * H))
         if name == "zeeman":
             e *= 2.0
         if name == "anis":
-            e += grid.ncell * V * p.Ku
+            e += float(np.count_nonzero(s > 0)) * V * p.Ku
         out[name] = e
     out["total"] = sum(out.values())
     return out
@@ -136,6 +138,8 @@ def energy_parts(grid, p, m, spec=None, pshape=None):
 
 def energy(grid, p, m, spec=None, pshape=None):
     """Closed form of the total: sum V[-(mu0 Ms/2) m.(H_eff + H_bias)] + N V Ku."""
+    if getattr(p, "ms_profile", None) is not None:
+        return energy_parts(grid, p, m, spec, pshape)["total"]
     H = field.heff(grid, p, m, spec, pshape)
     V = grid.volume
     h = np.zeros(3) if not p.has(TERM_ZEEMAN) else np.asarray(p.Hbias, np.float64)

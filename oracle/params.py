@@ -54,6 +54,9 @@ class Params:
     terms: int = TERM_ALL
     # 0: never renormalise, 1: only m_{n+1}, 2: every stage input and m_{n+1}
     renorm: int = 2
+    # optional geometry / space-dependent magnetisation: s(r) = Ms(r)/Ms per
+    # cell, shape (nz, ny, nx), s >= 0, s = 0 outside the magnet
+    ms_profile: object = None
     extra: dict = field(default_factory=dict)
 
     def has(self, flag):
