@@ -32,6 +32,7 @@ Readings (the paper gives neither):
   Y_2, Y_3 and the new state; renorm = 1: the new state only; fast substeps
   are not renormalised.
 """
+from dataclasses import replace
 from fractions import Fraction as Fr
 import math
 
@@ -39,7 +40,7 @@ import numpy as np
 
 from . import field
 from .llg import normalize, rhs_from_field
-from .params import TERM_EXCH
+from .params import TERM_DMI, TERM_EXCH
 
 KW3_C = (Fr(0), Fr(1, 3), Fr(3, 4))
 
@@ -126,9 +127,14 @@ def split_fields(grid, p, m, spec=None, pshape=None):
 
 
 def fast_rhs(grid, p, m):
-    """Torque of the exchange field alone (no FFT)."""
+    """Torque of the exchange field alone (no FFT), with the boundary rule of
+    the full field (the DMI condition of Eq. (10) and, with a magnetisation
+    profile, the surface of the magnet)."""
     if not p.has(TERM_EXCH):
         return np.zeros(np.shape(m))
+    if getattr(p, "ms_profile", None) is not None:
+        q = replace(p, terms=p.terms & (TERM_EXCH | TERM_DMI))
+        return rhs_from_field(p, m, field.heff_parts_masked(grid, q, np.asarray(m, np.float64))["exch"])
     g = field.ghost_padded(grid, p, m)
     return rhs_from_field(p, m, field.exchange(grid, p, m, g))
 

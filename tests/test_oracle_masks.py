@@ -19,6 +19,7 @@ import pytest
 from oracle import demag as odemag
 from oracle import field as ofield
 from oracle import llg as ollg
+from oracle import mri as omri
 from oracle import newell as onewell
 from oracle.params import Grid, Params
 from workloads import random_unit_field
@@ -91,3 +92,21 @@ def test_local_terms_scale_with_the_cell_ms():
     full = ofield.heff(g, replace(p, ms_profile=np.ones(g.shape)), m)
     half = ofield.heff(g, replace(p, ms_profile=np.full(g.shape, 0.5)), m)
     assert np.abs(half - 2.0 * full).max() <= 1e-12 * np.abs(full).max()
+
+
+def test_multirate_split_with_a_profile_sums_to_the_full_rhs():
+    # the fast (exchange) and slow torques of a masked magnet add up to the
+    # full right-hand side of the masked field, and the fast part already
+    # honours the magnet's surface (it differs from the unmasked exchange there)
+    g = Grid(8, 6, 2, *D3)
+    spec, P = _spec(g)
+    m = random_unit_field((8, 6, 2), 51, 1)
+    s = np.ones(g.shape)
+    s[:, :2, :3] = 0.0
+    s[:, 4:, :] = 0.5
+    p = Params(**MAT, terms=31, ms_profile=s)
+    full = ollg.rhs(g, p, m, spec, P)
+    split = omri.fast_rhs(g, p, m) + omri.slow_rhs(g, p, m, spec, P)
+    assert np.abs(split - full).max() <= 1e-12 * np.abs(full).max()
+    plain = omri.fast_rhs(g, replace(p, ms_profile=None), m)
+    assert np.abs(omri.fast_rhs(g, p, m) - plain).max() > 1e-3 * np.abs(plain).max()
