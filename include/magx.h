@@ -141,6 +141,20 @@ int magx_set_member_bias(magx_ctx* ctx, const void* hbias);
 /* Number of systems of a context (host), -1 for NULL. */
 int magx_ctx_batch(const magx_ctx* ctx);
 
+/* Geometry and space-dependent saturation magnetisation: s (device, nx*ny*nz
+ * elements of the context type, layout (nz, ny, nx), owned by the caller and
+ * kept valid while in use, shared by all members of a batch) gives
+ * Ms(r) = p->Ms * s(r) with s >= 0; s = 0 marks cells outside the magnet
+ * (nanodots, patterned films).  The demagnetising field is then that of
+ * M = Ms(r) m (Eq. (3)); exchange, DMI and anisotropy use each cell's own
+ * Ms in their prefactors (Eqs. (5), (7), (9)); the surface of the magnet is a
+ * boundary like the faces of the grid (ghost of Eq. (10) in place of a
+ * neighbour outside the magnet); cells outside the magnet carry no field and
+ * do not move; energies weight each cell by its Ms.  The reverse mode and the
+ * checkpointed rollouts return MAGX_ESTATE while a profile is set.  NULL
+ * returns to a uniform Ms.  Host only; enqueues nothing. */
+int magx_set_ms_profile(magx_ctx* ctx, const void* s);
+
 /* Effective field, Eq. (2), of the unit field m (device, read) into H (device,
  * written), in A/m.  `ws`: device workspace of workspace_bytes. */
 int magx_heff(magx_ctx* ctx, const void* m, const magx_params* p, void* H,

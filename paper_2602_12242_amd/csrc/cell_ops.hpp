@@ -88,16 +88,52 @@ __device__ __forceinline__ void store_pair(R* __restrict__ f, long long N, long 
     }
 }
 
+// Ghost values of the boundary condition (Eq. (10)) for a cell c on a face
+// with outward normal -x, +x, -y, +y (kd = -D/(2A) times the cell size; on z
+// faces the ghost is c itself).
+template <typename R> __device__ __forceinline__ void ghost_xm(const R c[3], R kd, R o[3]) {
+    o[0] = c[0] - kd * c[2]; o[1] = c[1]; o[2] = c[2] + kd * c[0];
+}
+template <typename R> __device__ __forceinline__ void ghost_xp(const R c[3], R kd, R o[3]) {
+    o[0] = c[0] + kd * c[2]; o[1] = c[1]; o[2] = c[2] - kd * c[0];
+}
+template <typename R> __device__ __forceinline__ void ghost_ym(const R c[3], R kd, R o[3]) {
+    o[0] = c[0]; o[1] = c[1] - kd * c[2]; o[2] = c[2] + kd * c[1];
+}
+template <typename R> __device__ __forceinline__ void ghost_yp(const R c[3], R kd, R o[3]) {
+    o[0] = c[0]; o[1] = c[1] + kd * c[2]; o[2] = c[2] - kd * c[1];
+}
+
+template <typename R>
+__device__ __forceinline__ void load_s_pair(const R* __restrict__ s, long long id, bool vec, bool two, R o[2]) {
+    if (vec) {
+        const cx<R> v = *reinterpret_cast<const cx<R>*>(s + id);
+        o[0] = v.x;
+        o[1] = v.y;
+    } else {
+        o[0] = s[id];
+        o[1] = two ? s[id + 1] : (R)0;
+    }
+}
+
 // Exchange + DMI + anisotropy of the linear field f for the pair of cells
 // (x0 = 2n, x0 + 1) of row (y, z); h*[0] belongs to cell x0, h*[1] to x0 + 1.
-// The ghost rule is the same as in local_field.
+// A neighbour outside the grid, or (with a magnetisation profile ph.msp)
+// outside the magnet, is replaced by the ghost of the boundary condition built
+// from the cell itself.  With a profile the local prefactors are divided by the
+// cell's s = Ms(r)/Ms and cells with s = 0 get no field; sw returns s of the
+// two cells (1 without a profile).
 template <typename R>
 __device__ __forceinline__ void local_field_pair(const R* __restrict__ f, const PG& g, int x0, int y, int z,
                                                  bool vec, bool two, const Phys<R>& ph, R m[2][3], R h[2][3],
-                                                 R hex_dot[2], R hdmi_dot[2], R hani_dot[2], bool want_parts) {
+                                                 R hex_dot[2], R hdmi_dot[2], R hani_dot[2], bool want_parts,
+                                                 R sw[2]) {
     const long long N = g.N;
     const long long id = ((long long)z * g.ny + y) * g.nx + x0;
+    const R* __restrict__ sp = ph.msp;
     load_pair(f, N, id, vec, two, m[0], m[1]);
+    sw[0] = sw[1] = (R)1;
+    if (sp) load_s_pair(sp, id, vec, two, sw);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
 #pragma unroll
@@ -107,45 +143,84 @@ __device__ __forceinline__ void local_field_pair(const R* __restrict__ f, const 
     if (ph.terms & (MAGX_EXCH | MAGX_DMI)) {
         const R kdx = ph.kap * ph.dx, kdy = ph.kap * ph.dy;
         R xl[3], xr[3], yp[2][3], ym[2][3], zp[2][3], zm[2][3];
+        // neighbour availability: in the grid and (with a profile) in the magnet
+        bool okxl = x0 > 0, okxr;
+        bool okyp[2], okym[2], okzp[2], okzm[2];
+        const int xr_off = two ? 2 : 1;
+        okxr = x0 + xr_off < g.nx;
+        const long long pz = (long long)g.nx * g.ny;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            okyp[q] = y + 1 < g.ny;
+            okym[q] = y > 0;
+            okzp[q] = z + 1 < g.nz;
+            okzm[q] = z > 0;
+        }
+        if (sp) {
+            if (okxl) okxl = sp[id - 1] > (R)0;
+            if (okxr) okxr = sp[id + xr_off] > (R)0;
+            R t[2];
+            if (y + 1 < g.ny) { load_s_pair(sp, id + g.nx, vec, two, t); okyp[0] = t[0] > (R)0; okyp[1] = t[1] > (R)0; }
+            if (y > 0) { load_s_pair(sp, id - g.nx, vec, two, t); okym[0] = t[0] > (R)0; okym[1] = t[1] > (R)0; }
+            if (z + 1 < g.nz) { load_s_pair(sp, id + pz, vec, two, t); okzp[0] = t[0] > (R)0; okzp[1] = t[1] > (R)0; }
+            if (z > 0) { load_s_pair(sp, id - pz, vec, two, t); okzm[0] = t[0] > (R)0; okzm[1] = t[1] > (R)0; }
+        }
         // outer x neighbours of the pair: cell x0 - 1 and cell x0 + 2 (or x0 + 1 if alone)
         R last[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) last[c] = two ? m[1][c] : m[0][c];
-        if (x0 > 0) {
+        if (okxl) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) xl[c] = f[c * N + id - 1];
         } else {
-            xl[0] = m[0][0] - kdx * m[0][2]; xl[1] = m[0][1]; xl[2] = m[0][2] + kdx * m[0][0];
+            ghost_xm<R>(m[0], kdx, xl);
         }
-        const int xr_x = x0 + (two ? 2 : 1);
-        if (xr_x < g.nx) {
+        if (okxr) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) xr[c] = f[c * N + id + (two ? 2 : 1)];
+            for (int c = 0; c < 3; ++c) xr[c] = f[c * N + id + xr_off];
         } else {
-            xr[0] = last[0] + kdx * last[2]; xr[1] = last[1]; xr[2] = last[2] - kdx * last[0];
+            ghost_xp<R>(last, kdx, xr);
         }
         if (y + 1 < g.ny) load_pair(f, N, id + g.nx, vec, two, yp[0], yp[1]);
         if (y > 0) load_pair(f, N, id - g.nx, vec, two, ym[0], ym[1]);
-        const long long pz = (long long)g.nx * g.ny;
         if (z + 1 < g.nz) load_pair(f, N, id + pz, vec, two, zp[0], zp[1]);
         if (z > 0) load_pair(f, N, id - pz, vec, two, zm[0], zm[1]);
+        // the two cells of the pair see each other unless one is outside the magnet
+        const bool in0 = sw[0] > (R)0, in1 = sw[1] > (R)0;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const R* mc = m[q];
             R xp[3], xm[3], ypq[3], ymq[3], zpq[3], zmq[3];
+            if (q == 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                xm[c] = q == 0 ? xl[c] : m[0][c];
-                xp[c] = q == 0 ? (two ? m[1][c] : xr[c]) : xr[c];
+                for (int c = 0; c < 3; ++c) xm[c] = xl[c];
+                if (!two) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) xp[c] = xr[c];
+                } else if (in1) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) xp[c] = m[1][c];
+                } else {
+                    ghost_xp<R>(m[0], kdx, xp);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) xp[c] = xr[c];
+                if (in0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) xm[c] = m[0][c];
+                } else {
+                    ghost_xm<R>(m[1], kdx, xm);
+                }
             }
-            if (y + 1 < g.ny) { ypq[0] = yp[q][0]; ypq[1] = yp[q][1]; ypq[2] = yp[q][2]; }
-            else { ypq[0] = mc[0]; ypq[1] = mc[1] + kdy * mc[2]; ypq[2] = mc[2] - kdy * mc[1]; }
-            if (y > 0) { ymq[0] = ym[q][0]; ymq[1] = ym[q][1]; ymq[2] = ym[q][2]; }
-            else { ymq[0] = mc[0]; ymq[1] = mc[1] - kdy * mc[2]; ymq[2] = mc[2] + kdy * mc[1]; }
+            if (okyp[q]) { ypq[0] = yp[q][0]; ypq[1] = yp[q][1]; ypq[2] = yp[q][2]; }
+            else ghost_yp<R>(mc, kdy, ypq);
+            if (okym[q]) { ymq[0] = ym[q][0]; ymq[1] = ym[q][1]; ymq[2] = ym[q][2]; }
+            else ghost_ym<R>(mc, kdy, ymq);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                zpq[c] = (z + 1 < g.nz) ? zp[q][c] : mc[c];
-                zmq[c] = (z > 0) ? zm[q][c] : mc[c];
+                zpq[c] = okzp[q] ? zp[q][c] : mc[c];
+                zmq[c] = okzm[q] ? zm[q][c] : mc[c];
             }
             R hx[3] = {(R)0, (R)0, (R)0}, hd[3] = {(R)0, (R)0, (R)0};
             if (ph.terms & MAGX_EXCH) {
@@ -161,6 +236,11 @@ __device__ __forceinline__ void local_field_pair(const R* __restrict__ f, const 
                 hd[1] = ph.cdmi * (ypq[2] - ymq[2]) * ph.h2y;
                 hd[2] = -ph.cdmi * ((xp[0] - xm[0]) * ph.h2x + (ypq[1] - ymq[1]) * ph.h2y);
             }
+            if (sp) {
+                const R inv = sw[q] > (R)0 ? (R)1 / sw[q] : (R)0;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { hx[c] *= inv; hd[c] *= inv; }
+            }
 #pragma unroll
             for (int c = 0; c < 3; ++c) h[q][c] = hx[c] + hd[c];
             if (want_parts) {
@@ -173,9 +253,11 @@ __device__ __forceinline__ void local_field_pair(const R* __restrict__ f, const 
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const R pr = m[q][0] * ph.eK[0] + m[q][1] * ph.eK[1] + m[q][2] * ph.eK[2];
+            R ca = ph.cani;
+            if (sp) ca = sw[q] > (R)0 ? ca / sw[q] : (R)0;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) h[q][c] += ph.cani * pr * ph.eK[c];
-            if (want_parts) hani_dot[q] = ph.cani * pr * pr;
+            for (int c = 0; c < 3; ++c) h[q][c] += ca * pr * ph.eK[c];
+            if (want_parts) hani_dot[q] = ca * pr * pr;
         }
     }
 }

@@ -18,6 +18,7 @@ struct magx_ctx {
     Plan pl;
     void* spectrum;
     const void* hbias_members;   // optional per-member bias fields (device, nbatch x 3)
+    const void* ms_profile;      // optional s = Ms(r)/Ms per cell (device, ncell), 0 outside the magnet
     // time-dependent uniform bias: knots (host) and the context's clock
     std::vector<double> sched_t, sched_h;
     double time;
@@ -177,9 +178,11 @@ static int check_params(const magx_params* p) {
 }
 
 template <typename R>
-static Phys<R> make_phys(const Plan& pl, const magx_params* p, const void* hbias_members = nullptr) {
+static Phys<R> make_phys(const Plan& pl, const magx_params* p, const void* hbias_members = nullptr,
+                         const void* ms_profile = nullptr) {
     Phys<R> ph{};
     ph.hbm = static_cast<const R*>(hbias_members);
+    ph.msp = static_cast<const R*>(ms_profile);
     const double mu0Ms = p->mu0 * p->Ms;
     ph.Ms = (R)p->Ms;
     ph.cex = (R)(2.0 * p->A / mu0Ms);
@@ -229,7 +232,7 @@ static void bias_at(const magx_ctx* c, const magx_params* p, double t, double h[
 
 template <typename R>
 static Phys<R> phys_at(const magx_ctx* c, const magx_params* p, double t) {
-    Phys<R> ph = make_phys<R>(c->pl, p, c->hbias_members);
+    Phys<R> ph = make_phys<R>(c->pl, p, c->hbias_members, c->ms_profile);
     double h[3];
     bias_at(c, p, t, h);
     for (int k = 0; k < 3; ++k) ph.hb[k] = (R)h[k];
@@ -287,7 +290,7 @@ static int do_heff(magx_ctx* c, const R* m, const magx_params* p, R* H, void* ws
     if (p->terms & MAGX_DEMAG) {
         {
             ProfScope ps(c, kProfXfwd, s);
-            if (launch_xfwd<R>(pl, m, X1, s) != hipSuccess) return MAGX_EHIP;
+            if (launch_xfwd<R>(pl, m, X1, ph.msp, s) != hipSuccess) return MAGX_EHIP;
         }
         int rc = conv_passes<R>(c, ws, ph.Ms, s);
         if (rc) return rc;
@@ -299,7 +302,7 @@ static int do_heff(magx_ctx* c, const R* m, const magx_params* p, R* H, void* ws
     if (energy) {
         const double V = pl.dx * pl.dy * pl.dz;
         const double pref = -0.5 * p->mu0 * p->Ms * V;
-        const double vku = (p->terms & MAGX_ANIS) ? (double)pl.ncell * V * p->Ku : 0.0;
+        const double vku = (p->terms & MAGX_ANIS) ? V * p->Ku : 0.0;     // per magnetic cell
         if (launch_energy_finish(part, pl.nbatch, pl.blocks_per_member, pref, vku, e_out, s) != hipSuccess)
             return MAGX_EHIP;
     }
@@ -323,7 +326,7 @@ template <typename R>
 static int do_step(magx_ctx* c, R* m, const magx_params* p, double dt, int nsteps, R* tape, void* ws,
                    hipStream_t s) {
     const Plan& pl = c->pl;
-    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
+    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members, c->ms_profile);
     const bool timed = !c->sched_t.empty();
     static const double kC[4] = {0.0, 0.5, 0.5, 1.0};   // stage times of classical RK4
     const bool demag = (p->terms & MAGX_DEMAG) != 0;
@@ -333,7 +336,7 @@ static int do_step(magx_ctx* c, R* m, const magx_params* p, double dt, int nstep
     TapeView<R> tv{tape, pl.ncell * pl.nbatch, nsteps};
     if (demag) {
         ProfScope ps(c, kProfXfwd, s);
-        if (launch_xfwd<R>(pl, m, X1, s) != hipSuccess) return MAGX_EHIP;
+        if (launch_xfwd<R>(pl, m, X1, ph.msp, s) != hipSuccess) return MAGX_EHIP;
     }
     for (int n = 0; n < nsteps; ++n) {
         for (int st = 1; st <= 4; ++st) {
@@ -379,7 +382,7 @@ static int do_step_euler(magx_ctx* c, R* m, const magx_params* p, double dt, int
     R* oth = W;
     if (demag) {
         ProfScope ps(c, kProfXfwd, s);
-        if (launch_xfwd<R>(pl, cur, X1, s) != hipSuccess) return MAGX_EHIP;
+        if (launch_xfwd<R>(pl, cur, X1, static_cast<const R*>(c->ms_profile), s) != hipSuccess) return MAGX_EHIP;
     }
     for (int n = 0; n < nsteps; ++n) {
         if (demag) {
@@ -410,7 +413,7 @@ template <typename R>
 static int do_step_backward(magx_ctx* c, const R* tape, int nsteps, const magx_params* p, double dt, R* gm,
                             R* gHbias, void* ws, hipStream_t s, bool fresh = true, bool finish = true) {
     const Plan& pl = c->pl;
-    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
+    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members, c->ms_profile);
     const bool demag = (p->terms & MAGX_DEMAG) != 0;
     void* X1 = bptr(ws, pl.off_x1);
     R* xi5 = reinterpret_cast<R*>(bptr(ws, pl.off_f[0]));
@@ -468,12 +471,12 @@ template <typename R>
 static int do_heff_backward(magx_ctx* c, const R* gH, const magx_params* p, R* gm, R* gHbias, void* ws,
                             hipStream_t s) {
     const Plan& pl = c->pl;
-    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
+    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members, c->ms_profile);
     void* X1 = bptr(ws, pl.off_x1);
     double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
     if (launch_fill_zero(part, (long long)pl.pencil_blocks * 8, s) != hipSuccess) return MAGX_EHIP;
     if (p->terms & MAGX_DEMAG) {
-        if (launch_xfwd<R>(pl, gH, X1, s) != hipSuccess) return MAGX_EHIP;
+        if (launch_xfwd<R>(pl, gH, X1, nullptr, s) != hipSuccess) return MAGX_EHIP;
         int rc = conv_passes<R>(c, ws, ph.Ms, s);
         if (rc) return rc;
     }
@@ -516,7 +519,7 @@ static int do_step_mri(magx_ctx* c, R* m, const magx_params* p, double dt, doubl
                        hipStream_t s) {
     static const KnothWolke kw;
     const Plan& pl = c->pl;
-    const Phys<R> ph = make_phys<R>(pl, p, c->hbias_members);
+    const Phys<R> ph = make_phys<R>(pl, p, c->hbias_members, c->ms_profile);
     Phys<R> pfast = ph, pslow = ph;     // both keep the ghost rule of the full field
     pfast.terms = ph.terms & MAGX_EXCH;
     pslow.terms = ph.terms & ~MAGX_EXCH;
@@ -539,7 +542,7 @@ static int do_step_mri(magx_ctx* c, R* m, const magx_params* p, double dt, doubl
     R* oth = W;
     if (demag) {
         ProfScope ps(c, kProfXfwd, s);
-        if (launch_xfwd<R>(pl, cur, X1, s) != hipSuccess) return MAGX_EHIP;
+        if (launch_xfwd<R>(pl, cur, X1, ph.msp, s) != hipSuccess) return MAGX_EHIP;
     }
     for (int n = 0; n < nsteps; ++n) {
         for (int i = 0; i < 3; ++i) {
@@ -619,6 +622,7 @@ int magx_tensor_init_batched(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, 
     c->pl = pl;
     c->spectrum = spectrum;
     c->hbias_members = nullptr;
+    c->ms_profile = nullptr;
     c->time = 0.0;
     c->heff_count = 0;
     c->device = dev;
@@ -640,6 +644,12 @@ int magx_set_member_bias(magx_ctx* ctx, const void* hbias) {
 }
 
 int magx_ctx_batch(const magx_ctx* ctx) { return ctx ? ctx->pl.nbatch : -1; }
+
+int magx_set_ms_profile(magx_ctx* ctx, const void* s) {
+    if (!ctx) return MAGX_EINVAL;
+    ctx->ms_profile = s;
+    return MAGX_OK;
+}
 
 int magx_heff(magx_ctx* ctx, const void* m, const magx_params* p, void* H, void* ws, void* stream) {
     if (!ctx || !m || !H || !ws) return MAGX_EINVAL;
@@ -739,7 +749,7 @@ int magx_step_mri(magx_ctx* ctx, void* m, const magx_params* p, double dt, doubl
 int magx_heff_backward(magx_ctx* ctx, const void* gH, const magx_params* p, void* gm, void* gHbias, void* ws,
                        void* stream) {
     if (!ctx || !gH || !gm || !gHbias || !ws) return MAGX_EINVAL;
-    if (!ctx->sched_t.empty()) return MAGX_ESTATE;
+    if (!ctx->sched_t.empty() || ctx->ms_profile) return MAGX_ESTATE;
     int rc = check_params(p);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -753,7 +763,7 @@ int magx_heff_backward(magx_ctx* ctx, const void* gH, const magx_params* p, void
 int magx_step_backward(magx_ctx* ctx, const void* tape, int nsteps, const magx_params* p, double dt, void* gm,
                        void* gHbias, void* ws, void* stream) {
     if (!ctx || !tape || !gm || !gHbias || !ws || nsteps < 0 || !std::isfinite(dt)) return MAGX_EINVAL;
-    if (!ctx->sched_t.empty()) return MAGX_ESTATE;
+    if (!ctx->sched_t.empty() || ctx->ms_profile) return MAGX_ESTATE;
     int rc = check_params(p);
     if (rc) return rc;
     if (nsteps == 0) return MAGX_OK;
@@ -768,7 +778,7 @@ int magx_step_backward(magx_ctx* ctx, const void* tape, int nsteps, const magx_p
 int magx_rollout_forward(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps, int ckpt,
                          void* ckpt_store, void* ws, void* stream) {
     if (!ctx || !m || !ckpt_store || !ws || nsteps < 0 || ckpt < 1 || !std::isfinite(dt)) return MAGX_EINVAL;
-    if (!ctx->sched_t.empty()) return MAGX_ESTATE;
+    if (!ctx->sched_t.empty() || ctx->ms_profile) return MAGX_ESTATE;
     int rc = check_params(p);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -791,7 +801,7 @@ int magx_rollout_backward(magx_ctx* ctx, const void* ckpt_store, const magx_para
     if (!ctx || !ckpt_store || !gm || !gHbias || !tape || !mwork || !ws || nsteps < 0 || ckpt < 1 ||
         !std::isfinite(dt))
         return MAGX_EINVAL;
-    if (!ctx->sched_t.empty()) return MAGX_ESTATE;
+    if (!ctx->sched_t.empty() || ctx->ms_profile) return MAGX_ESTATE;
     int rc = check_params(p);
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -857,7 +867,7 @@ const char* magx_strerror(int code) {
         case MAGX_EWORKSPACE: return "buffer too small";
         case MAGX_EHIP: return "HIP error";
         case MAGX_ENONFINITE: return "non-finite value";
-        case MAGX_ESTATE: return "not available while a bias schedule is set";
+        case MAGX_ESTATE: return "not available while a bias schedule or a magnetisation profile is set";
         default: return "unknown error";
     }
 }

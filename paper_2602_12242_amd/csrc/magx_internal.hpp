@@ -55,6 +55,7 @@ struct Phys {
     R eK[3];
     R hb[3];         // bias field (Zeeman)
     const R* hbm;    // optional per-member bias fields (nbatch x 3, device); overrides hb
+    const R* msp;    // optional magnetisation profile s = Ms(r)/Ms per cell (device, shared by members)
     R a;             // mu0 gamma/(1+alpha^2) (Eq. (1))
     R alpha;
     R idx2, idy2, idz2;   // 1/d^2
@@ -119,7 +120,7 @@ struct StartArgs {
 };
 
 template <typename R>
-hipError_t launch_xfwd(const Plan& pl, const R* f, void* X1, hipStream_t s);
+hipError_t launch_xfwd(const Plan& pl, const R* f, void* X1, const R* msp, hipStream_t s);
 // mode 0: H = field of f (with bias if with_bias); mode 1: energy partials of f;
 // if sum_input, per-block sums of f are added into partials (for dL/dH_bias).
 template <typename R>
@@ -142,8 +143,9 @@ hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
 template <typename R>
 hipError_t launch_reduce_partials(const double* partials, int nbatch, int blocks_per_member, int nval, R* out,
                                   int accumulate, hipStream_t s);
+// vku_cell = V Ku per magnetic cell; their count is partial 5 of every block.
 hipError_t launch_energy_finish(const double* partials, int nbatch, int blocks_per_member, double pref,
-                                double vku_member, double* e_out, hipStream_t s);
+                                double vku_cell, double* e_out, hipStream_t s);
 template <typename R>
 hipError_t launch_copy(const R* src, R* dst, long long n, hipStream_t s);
 

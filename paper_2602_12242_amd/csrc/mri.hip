@@ -49,14 +49,16 @@ __global__ void __launch_bounds__(kNT) mri_slow_kernel(const cx<R>* __restrict__
         int yy, z;
         pen_coords<R>(g, pen0 + p, yy, z);
         const long long id = ((long long)z * g.ny + yy) * g.nx + x0;
-        R m[2][3], H[2][3], ex[2], dm[2], an[2], S[2][3], r[2][3];
-        local_field_pair<R>(y, g, x0, yy, z, vec, two, ph, m, H, ex, dm, an, false);
+        R m[2][3], H[2][3], ex[2], dm[2], an[2], S[2][3], r[2][3], sw[2];
+        local_field_pair<R>(y, g, x0, yy, z, vec, two, ph, m, H, ex, dm, an, false, sw);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
+            // with a profile: no field outside the magnet
+            const R inside = (!ph.msp || sw[q] > (R)0) ? (R)1 : (R)0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                if (has_demag) H[q][c] += demag_at<R>(buf, 3 * p + c, g.Lh, n, q);
-                if (ph.terms & MAGX_ZEEMAN) H[q][c] += hbv[c];
+                if (has_demag) H[q][c] += inside * demag_at<R>(buf, 3 * p + c, g.Lh, n, q);
+                if (ph.terms & MAGX_ZEEMAN) H[q][c] += inside * hbv[c];
             }
             llg_rhs<R>(m[q], H[q], ph.a, ph.alpha, S[q]);
 #pragma unroll
@@ -116,8 +118,8 @@ __global__ void __launch_bounds__(kNT) mri_fast_kernel(const R* __restrict__ v, 
         int yy, z;
         pen_coords<R>(g, pen0 + p, yy, z);
         const long long id = ((long long)z * g.ny + yy) * g.nx + x0;
-        R m[2][3], H[2][3], ex[2], dm[2], an[2], r[2][3], q[2][3], k[2][3], xn[2][3];
-        local_field_pair<R>(v, g, x0, yy, z, vec, two, ph, m, H, ex, dm, an, false);
+        R m[2][3], H[2][3], ex[2], dm[2], an[2], r[2][3], q[2][3], k[2][3], xn[2][3], sw[2];
+        local_field_pair<R>(v, g, x0, yy, z, vec, two, ph, m, H, ex, dm, an, false, sw);
         load_pair(rbuf, g.N, id, vec, two, r[0], r[1]);
         if (!first) load_pair(qbuf, g.N, id, vec, two, q[0], q[1]);
 #pragma unroll
@@ -141,8 +143,10 @@ __global__ void __launch_bounds__(kNT) mri_fast_kernel(const R* __restrict__ v, 
         store_pair(qbuf, g.N, id, vec, two, q[0], q[1]);
         store_pair(vout, g.N, id, vec, two, xn[0], xn[1]);
         if (fwd) {
+            // demag source of the next slow stage: Ms(r) m = Ms s m
 #pragma unroll
-            for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(xn[0][c], two ? xn[1][c] : (R)0);
+            for (int c = 0; c < 3; ++c)
+                buf[(3 * p + c) * g.Lh + n] = mk<R>(sw[0] * xn[0][c], two ? sw[1] * xn[1][c] : (R)0);
         }
     }
     if (!fwd) return;

@@ -26,7 +26,8 @@ namespace magx {
 // ---- kernels -------------------------------------------------------------------
 
 template <typename R, bool BIG>
-__global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R>* __restrict__ X1, PG g) {
+__global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R>* __restrict__ X1, PG g,
+                                                   const R* __restrict__ msp) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     // logical block -> member mb and its first pencil; members own contiguous block ranges
@@ -42,11 +43,17 @@ __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R
         pen_coords<R>(g, pen0 + p, y, z);
         const long long row = ((long long)z * g.ny + y) * g.nx;
         const int x0 = 2 * n, x1 = 2 * n + 1;
+        // the demag source is Ms(r) m = Ms s m with a magnetisation profile
+        R s0 = (R)1, s1 = (R)1;
+        if (msp) {
+            s0 = x0 < g.nx ? msp[row + x0] : (R)0;
+            s1 = x1 < g.nx ? msp[row + x1] : (R)0;
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const R a = x0 < g.nx ? f[c * g.N + row + x0] : (R)0;
             const R b = x1 < g.nx ? f[c * g.N + row + x1] : (R)0;
-            buf[(3 * p + c) * g.Lh + n] = mk<R>(a, b);
+            buf[(3 * p + c) * g.Lh + n] = mk<R>(s0 * a, s1 * b);
         }
     }
     r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
@@ -74,7 +81,7 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
     for (int c = 0; c < 3; ++c) hbv[c] = ph.hbm ? ph.hbm[mb * 3 + c] : ph.hb[c];
     const bool vec = (g.nx & 1) == 0;
     if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, mb, pen0, npen);
-    double acc[5] = {0, 0, 0, 0, 0};
+    double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
         const int p = e >> g.lgLh, n = e & (g.Lh - 1);
         const int x0 = 2 * n;
@@ -82,8 +89,8 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
         const bool two = x0 + 1 < g.nx;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
-        R m[2][3], hl[2][3], ex[2], dm[2], an[2], out[2][3];
-        local_field_pair<R>(f, g, x0, y, z, vec, two, ph, m, hl, ex, dm, an, energy != 0);
+        R m[2][3], hl[2][3], ex[2], dm[2], an[2], out[2][3], sw[2];
+        local_field_pair<R>(f, g, x0, y, z, vec, two, ph, m, hl, ex, dm, an, energy != 0, sw);
         const long long id = ((long long)z * g.ny + y) * g.nx + x0;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -91,19 +98,23 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
 #pragma unroll
             for (int c = 0; c < 3; ++c) hd[c] = has_demag ? demag_at<R>(buf, 3 * p + c, g.Lh, n, q) : (R)0;
             const bool live = q == 0 || two;
+            // with a profile: no field outside the magnet, densities weighted by s
+            const R inside = sw[q] > (R)0 ? (R)1 : (R)0;
             if (energy) {
                 if (live) {
-                    acc[0] += (double)dot3(m[q], hd);
-                    acc[1] += (double)ex[q];
-                    acc[2] += (double)dm[q];
-                    acc[3] += (double)an[q];
-                    if (ph.terms & MAGX_ZEEMAN) acc[4] += (double)dot3(m[q], hbv);
+                    const double w = (double)sw[q];
+                    acc[0] += w * (double)(inside * dot3(m[q], hd));
+                    acc[1] += w * (double)ex[q];
+                    acc[2] += w * (double)dm[q];
+                    acc[3] += w * (double)an[q];
+                    if (ph.terms & MAGX_ZEEMAN) acc[4] += w * (double)dot3(m[q], hbv);
+                    acc[5] += (double)inside;
                 }
             } else {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    out[q][c] = hd[c] + hl[q][c];
-                    if (with_bias && (ph.terms & MAGX_ZEEMAN)) out[q][c] += hbv[c];
+                    out[q][c] = inside * hd[c] + hl[q][c];
+                    if (with_bias && (ph.terms & MAGX_ZEEMAN)) out[q][c] += inside * hbv[c];
                 }
                 if (sum_input && live) {
 #pragma unroll
@@ -114,7 +125,7 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
         if (!energy) store_pair(H, g.N, id, vec, two, out[0], out[1]);
     }
     if (energy) {
-        for (int v = 0; v < 5; ++v) {
+        for (int v = 0; v < 6; ++v) {
             const double sm = block_sum(acc[v], red);
             if (threadIdx.x == 0) partials[lb * 8 + v] = sm;
         }
@@ -177,15 +188,18 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
         const long long id = ((long long)z * g.ny + y) * g.nx + x0;
-        R ys[2][3], H[2][3], ex[2], dm[2], an[2];
-        local_field_pair<R>(a.yin, g, x0, y, z, vec, two, ph, ys, H, ex, dm, an, false);
+        R ys[2][3], H[2][3], ex[2], dm[2], an[2], sw[2];
+        local_field_pair<R>(a.yin, g, x0, y, z, vec, two, ph, ys, H, ex, dm, an, false, sw);
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < 2; ++q) {
+            // with a profile: no field (so no motion) outside the magnet
+            const R inside = (!ph.msp || sw[q] > (R)0) ? (R)1 : (R)0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                if (has_demag) H[q][c] += demag_at<R>(buf, 3 * p + c, g.Lh, n, q);
-                if (ph.terms & MAGX_ZEEMAN) H[q][c] += hbv[c];
+                if (has_demag) H[q][c] += inside * demag_at<R>(buf, 3 * p + c, g.Lh, n, q);
+                if (ph.terms & MAGX_ZEEMAN) H[q][c] += inside * hbv[c];
             }
+        }
         if (a.tapeH) store_pair(a.tapeH, g.N, id, vec, two, H[0], H[1]);
         if (a.tapeYin) store_pair(a.tapeYin, g.N, id, vec, two, ys[0], ys[1]);
         R k[2][3], mn[2][3], acc[2][3], xn[2][3], nrm[2];
@@ -231,8 +245,10 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
         store_pair(a.yout, g.N, id, vec, two, xn[0], xn[1]);
         if (a.yout2) store_pair(a.yout2, g.N, id, vec, two, xn[0], xn[1]);
         if (fwd) {
+            // demag source of the next stage: Ms(r) m = Ms s m
 #pragma unroll
-            for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(xn[0][c], two ? xn[1][c] : (R)0);
+            for (int c = 0; c < 3; ++c)
+                buf[(3 * p + c) * g.Lh + n] = mk<R>(sw[0] * xn[0][c], two ? sw[1] * xn[1][c] : (R)0);
         }
     }
     if (!fwd) return;
@@ -380,7 +396,8 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
         pen_coords<R>(g, pen0 + p, y, z);
         const long long id = ((long long)z * g.ny + y) * g.nx + x0;
         R mu[2][3], Kmu[2][3], ex[2], dm[2], an[2];
-        local_field_pair<R>(a.mu, g, x0, y, z, vec, two, ph, mu, Kmu, ex, dm, an, false);
+        R sw[2];
+        local_field_pair<R>(a.mu, g, x0, y, z, vec, two, ph, mu, Kmu, ex, dm, an, false, sw);
         if (has_demag) {
 #pragma unroll
             for (int q = 0; q < 2; ++q)
@@ -495,21 +512,22 @@ __global__ void reduce_partials_kernel(const double* __restrict__ partials, int 
 }
 
 // e_out[6 mb + ...]: demag, exch, dmi, anis, zeeman, total (J) of member mb.
-// pref = -(mu0 Ms V)/2, vku_member = ncell V Ku (anisotropy constant term).
+// pref = -(mu0 Ms V)/2, vku_cell = V Ku (anisotropy constant term per magnetic
+// cell; partial 5 counts the magnetic cells).
 __global__ void energy_finish_kernel(const double* __restrict__ partials, int bpm, double pref,
-                                     double vku_member, double* e_out) {
+                                     double vku_cell, double* e_out) {
     __shared__ double red[kNT];
     const int mb = blockIdx.x;
     const double* pp = partials + (long long)mb * bpm * 8;
-    double e[5];
-    for (int v = 0; v < 5; ++v) {
+    double e[6];
+    for (int v = 0; v < 6; ++v) {
         double acc = 0.0;
         for (int b = threadIdx.x; b < bpm; b += kNT) acc += pp[b * 8 + v];
         e[v] = block_sum(acc, red);
     }
     if (threadIdx.x == 0) {
         const double ed = pref * e[0], ee = pref * e[1], em = pref * e[2];
-        const double ea = pref * e[3] + vku_member, ez = 2.0 * pref * e[4];
+        const double ea = pref * e[3] + vku_cell * e[5], ez = 2.0 * pref * e[4];
         double* o = e_out + 6 * mb;
         o[0] = ed;
         o[1] = ee;
@@ -529,11 +547,11 @@ __global__ void copy_kernel(const R* __restrict__ src, R* __restrict__ dst, long
 // ---- launchers -----------------------------------------------------------------
 
 template <typename R>
-hipError_t launch_xfwd(const Plan& pl, const R* f, void* X1, hipStream_t s) {
+hipError_t launch_xfwd(const Plan& pl, const R* f, void* X1, const R* msp, hipStream_t s) {
     if (pencil_big(pl)) hipLaunchKernelGGL((xfwd_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s, f,
-                       static_cast<cx<R>*>(X1), make_pg(pl));
+                       static_cast<cx<R>*>(X1), make_pg(pl), msp);
     else hipLaunchKernelGGL((xfwd_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s, f,
-                       static_cast<cx<R>*>(X1), make_pg(pl));
+                       static_cast<cx<R>*>(X1), make_pg(pl), msp);
     return hipGetLastError();
 }
 
@@ -607,9 +625,9 @@ hipError_t launch_reduce_partials(const double* partials, int nbatch, int blocks
 }
 
 hipError_t launch_energy_finish(const double* partials, int nbatch, int blocks_per_member, double pref,
-                                double vku_member, double* e_out, hipStream_t s) {
+                                double vku_cell, double* e_out, hipStream_t s) {
     hipLaunchKernelGGL(energy_finish_kernel, dim3(nbatch), dim3(kNT), 0, s, partials, blocks_per_member, pref,
-                       vku_member, e_out);
+                       vku_cell, e_out);
     return hipGetLastError();
 }
 
@@ -620,7 +638,7 @@ hipError_t launch_copy(const R* src, R* dst, long long n, hipStream_t s) {
 }
 
 #define MAGX_INST(R)                                                                                            \
-    template hipError_t launch_xfwd<R>(const Plan&, const R*, void*, hipStream_t);                               \
+    template hipError_t launch_xfwd<R>(const Plan&, const R*, void*, const R*, hipStream_t);                               \
     template hipError_t launch_field<R>(const Plan&, const Phys<R>&, const void*, const R*, R*, int, int, int,   \
                                         double*, hipStream_t);                                                  \
     template hipError_t launch_stage<R>(const Plan&, const Phys<R>&, const void*, void*, const StageArgs<R>&,   \

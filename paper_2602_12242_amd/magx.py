@@ -53,7 +53,7 @@ class magx_size_info(ctypes.Structure):
 
 
 EXPORTS = ("magx_sizes", "magx_sizes_batched", "magx_tensor_init", "magx_tensor_init_batched",
-           "magx_set_member_bias", "magx_ctx_batch", "magx_heff", "magx_llg_rhs", "magx_step", "magx_step_mri",
+           "magx_set_member_bias", "magx_ctx_batch", "magx_set_ms_profile", "magx_heff", "magx_llg_rhs", "magx_step", "magx_step_mri",
            "magx_step_euler", "magx_set_bias_schedule", "magx_get_time",
            "magx_heff_backward", "magx_step_backward", "magx_rollout_forward", "magx_rollout_backward",
            "magx_energy", "magx_heff_count", "magx_ctx_info", "magx_spectrum_layout", "magx_profile_start",
@@ -79,6 +79,7 @@ def load(path=LIB_PATH):
         "magx_tensor_init_batched": (i, [P(vp), P(magx_grid), i, i, vp, vp, vp]),
         "magx_set_member_bias": (i, [vp, vp]),
         "magx_ctx_batch": (i, [vp]),
+        "magx_set_ms_profile": (i, [vp, vp]),
         "magx_heff": (i, [vp, vp, P(magx_params), vp, vp, vp]),
         "magx_llg_rhs": (i, [vp, vp, vp, P(magx_params), vp, vp]),
         "magx_step": (i, [vp, vp, P(magx_params), d, i, vp, vp, vp]),
@@ -173,6 +174,7 @@ class Context:
             self.lead = (self.nbatch,)
             self.shape = self.lead + self.shape
         self.member_bias = None
+        self.ms_profile = None
         with torch.cuda.device(self.device):
             self.spectrum = torch.empty(self.sizes["spectrum_bytes"], dtype=torch.uint8, device=self.device)
             scratch = torch.empty(self.sizes["init_scratch_bytes"], dtype=torch.uint8, device=self.device)
@@ -221,6 +223,17 @@ class Context:
                 raise ValueError(f"hbias: expected contiguous {self.tdtype} ({self.nbatch}, 3) on {self.device}")
         _check(self.lib.magx_set_member_bias(self.h, _ptr(hbias)), "magx_set_member_bias")
         self.member_bias = hbias
+
+    def set_ms_profile(self, s):
+        """Magnetisation profile s = Ms(r)/Ms, a (nz, ny, nx) tensor of the
+        context type on its device (kept referenced here; 0 outside the
+        magnet), or None for a uniform Ms."""
+        if s is not None:
+            shape = (self.n[2], self.n[1], self.n[0])
+            if s.dtype != self.tdtype or not s.is_contiguous() or tuple(s.shape) != shape or s.device != self.device:
+                raise ValueError(f"s: expected contiguous {self.tdtype} {shape} on {self.device}")
+        _check(self.lib.magx_set_ms_profile(self.h, _ptr(s)), "magx_set_ms_profile")
+        self.ms_profile = s
 
     @property
     def heff_count(self):
