@@ -22,7 +22,8 @@ random states stand in for the standard-problem initial conditions):
            cells, 640x160x4, permalloy, field 1 (mu0 H = (-24.6, 4.3, 0) mT),
            demag + exchange + Zeeman: the integrator comparison of the paper
            (RK4 at dt 2.5e-14 s against multirate at 1.25e-13 s with fast
-           steps of 1.25e-14 s over one 1.25e-13 s interval)
+           steps of 1.25e-14 s over one 1.25e-13 s interval), starting from
+           a smooth S-like texture (no seed)
 
 Magnetisation starts are random unit vectors (normalised N(0,1)^3), optionally
 smoothed by damped neighbour-averaging passes and renormalised, generated in
@@ -101,7 +102,8 @@ def _workloads():
         "sp4_fine": Workload("sp4_fine", (640, 160, 4), (0.78125e-9, 0.78125e-9, 0.78125e-9), 8.0e5, 1.3e-11,
                              0.02, TERM_DEMAG | TERM_EXCH | TERM_ZEEMAN,
                              Hbias=(-0.0246 / MU0, 0.0043 / MU0, 0.0), steps=5, dt=2.5e-14, seed=1006,
-                             smooth=8, extra=dict(dt_mri=1.25e-13, dt_fast=1.25e-14, interval=1.25e-13)),
+                             smooth=0, extra=dict(dt_mri=1.25e-13, dt_fast=1.25e-14, interval=1.25e-13,
+                                                  texture="s_like")),
     }
 
 
@@ -144,8 +146,25 @@ def random_unit_field(n, seed, smooth=0):
     return v
 
 
+def s_like_texture(n):
+    """Smooth in-plane texture standing in for the relaxed S-state of the
+    Standard Problem 4 film: m = (cos t cos p, cos t sin p, sin t) with
+    p = 0.6 cos(pi u) sin(pi (v - 1/2)) and t = 0.08 sin(pi u), u, v the cell
+    centres scaled to [0, 1] along x and y (the same in every layer)."""
+    nx, ny, nz = n
+    u = (np.arange(nx) + 0.5) / nx
+    v = (np.arange(ny) + 0.5) / ny
+    U, V = np.meshgrid(u, v, indexing="xy")             # (ny, nx)
+    ph = 0.6 * np.cos(np.pi * U) * np.sin(np.pi * (V - 0.5))
+    th = 0.08 * np.sin(np.pi * U)
+    m = np.stack([np.cos(th) * np.cos(ph), np.cos(th) * np.sin(ph), np.sin(th)])
+    return np.broadcast_to(m[:, None], (3, nz, ny, nx)).copy()
+
+
 def initial_state(w, dtype=np.float32):
     """Initial magnetisation of a workload, rounded once to `dtype`."""
+    if w.extra.get("texture") == "s_like":
+        return s_like_texture(w.n).astype(dtype)
     return random_unit_field(w.n, w.seed, w.smooth).astype(dtype)
 
 
