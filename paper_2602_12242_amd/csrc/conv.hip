@@ -11,6 +11,7 @@
 //           written back (in place).
 //  * yinv : inverse y FFT; only rows y < ny (inside the box) are written.
 #include <algorithm>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -28,22 +29,46 @@ namespace magx {
 // inputs from registers, and right after it the next tile's inputs are
 // requested, so the loads of tile t+1 are in flight while tile t finishes.
 
-template <typename R>
-__device__ __forceinline__ void tile_range(int ntiles, int& t0, int& t1) {
-    const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
-    t0 = (int)((long long)ntiles * lb / gridDim.x);
-    t1 = (int)((long long)ntiles * (lb + 1) / gridDim.x);
-}
+// Walk of a block of a pair over the y-pass tiles (plane, tx): units are
+// (plane, txp) with txp = tx / 2; a pair of blocks (adjacent logical indices,
+// one XCD) shares a contiguous unit range and its even / odd block takes
+// column tile 2 txp / 2 txp + 1 (skipped when past the last tile).
+struct PairWalk {
+    int ntx, ntxp, side, u0, u1;
+    __device__ PairWalk(int ntiles, int ntx_) : ntx(ntx_) {
+        ntxp = (ntx + 1) >> 1;
+        const int lbp = xcd_logical_block(blockIdx.x, gridDim.x);
+        side = lbp & 1;
+        const int npairs = gridDim.x >> 1, pr = lbp >> 1;
+        const long long nunits = (long long)(ntiles / ntx) * ntxp;
+        u0 = (int)(nunits * pr / npairs);
+        u1 = (int)(nunits * (pr + 1) / npairs);
+    }
+    __device__ bool valid(int u) const { return 2 * (u % ntxp) + side < ntx; }
+    __device__ int first() const {
+        int u = u0;
+        while (u < u1 && !valid(u)) ++u;
+        return u;
+    }
+    __device__ int next(int u) const {
+        ++u;
+        while (u < u1 && !valid(u)) ++u;
+        return u;
+    }
+    __device__ int tile(int u) const { return (u / ntxp) * ntx + 2 * (u % ntxp) + side; }
+};
 
-template <typename R, int EM>
-__global__ void __launch_bounds__(kNT) yfwd_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
-                                                   int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
+template <typename R, int EM, int NT>
+__global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
+                                                  int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
     const int Py = 1 << lgPy;
-    int t0, t1;
-    tile_range<R>(ntiles, t0, t1);
+    // block pairs: unit u = (plane, column-tile pair); the even block of a pair
+    // takes column tile 2 txp, the odd one 2 txp + 1, at the same time, so the
+    // two halves of every 128-byte row segment are requested together
+    const PairWalk pw(ntiles, ntx);
     // tile t: plane t / ntx (= c * nz + z), columns (t % ntx) * T ...
     // sequence b = column kx0 + b; rows >= ny are the zero padding, never read
     auto loader = [=](int t) {
@@ -58,8 +83,11 @@ __global__ void __launch_bounds__(kNT) yfwd_kernel(const cx<R>* __restrict__ X1,
         };
     };
     FirstIn<R, EM, true> in;
-    if (t0 < t1) first_load<R, EM, kCols, 1, true>(in, lgPy, lgT, T, loader(t0));
-    for (int t = t0; t < t1; ++t) {
+    int u = pw.first();
+    if (u < pw.u1) first_load<R, EM, kCols, 1, true, lgmax<EM>(), NT>(in, lgPy, lgT, T, loader(pw.tile(u)));
+    while (u < pw.u1) {
+        const int un = pw.next(u);
+        const int t = pw.tile(u);
         const int tx = t % ntx;
         const long long plane = t / ntx;
         const int kx0 = tx * T;
@@ -69,22 +97,23 @@ __global__ void __launch_bounds__(kNT) yfwd_kernel(const cx<R>* __restrict__ X1,
             if (b < ncol) dst[mul24(j, Sx) + b] = v;
         };
         auto next = [&]() {
-            if (t + 1 < t1) first_load<R, EM, kCols, 1, true>(in, lgPy, lgT, T, loader(t + 1));
+            if (un < pw.u1)
+                first_load<R, EM, kCols, 1, true, lgmax<EM>(), NT>(in, lgPy, lgT, T, loader(pw.tile(un)));
         };
-        fft_reg<R, false, EM, false, kCols, 1, true, false>(buf, lgPy, lgT, T, in, next, store);
+        fft_reg<R, false, EM, false, kCols, 1, true, false, lgmax<EM>(), NT>(buf, lgPy, lgT, T, in, next, store);
         __syncthreads();   // the last pass read LDS; the next tile's first pass writes it
+        u = un;
     }
 }
 
-template <typename R, int EM>
-__global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
-                                                   int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
+template <typename R, int EM, int NT>
+__global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
+                                                  int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
     const int Py = 1 << lgPy;
-    int t0, t1;
-    tile_range<R>(ntiles, t0, t1);
+    const PairWalk pw(ntiles, ntx);
     auto loader = [=](int t) {
         const int tx = t % ntx;
         const long long plane = t / ntx;
@@ -97,8 +126,11 @@ __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2,
         };
     };
     FirstIn<R, EM, false> in;
-    if (t0 < t1) first_load<R, EM, kCols, 1, false>(in, lgPy, lgT, T, loader(t0));
-    for (int t = t0; t < t1; ++t) {
+    int u = pw.first();
+    if (u < pw.u1) first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(in, lgPy, lgT, T, loader(pw.tile(u)));
+    while (u < pw.u1) {
+        const int un = pw.next(u);
+        const int t = pw.tile(u);
         const int tx = t % ntx;
         const long long plane = t / ntx;
         const int kx0 = tx * T;
@@ -109,10 +141,12 @@ __global__ void __launch_bounds__(kNT) yinv_kernel(const cx<R>* __restrict__ X2,
             if (j < ny && b < ncol) dst[mul24(j, Sx) + b] = v;
         };
         auto next = [&]() {
-            if (t + 1 < t1) first_load<R, EM, kCols, 1, false>(in, lgPy, lgT, T, loader(t + 1));
+            if (un < pw.u1)
+                first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(in, lgPy, lgT, T, loader(pw.tile(un)));
         };
-        fft_reg<R, true, EM, false, kCols, 1, false, true>(buf, lgPy, lgT, T, in, next, store);
+        fft_reg<R, true, EM, false, kCols, 1, false, true, lgmax<EM>(), NT>(buf, lgPy, lgT, T, in, next, store);
         __syncthreads();
+        u = un;
     }
 }
 
@@ -256,7 +290,7 @@ static inline bool em_big(long long elements) { return elements > (long long)kNT
 // Blocks of a persistent launch: as many as can be resident on the device
 // (occupancy of this kernel at this LDS size, times the CU count), at most
 // one per tile.  Cached per device, kernel and LDS size.
-static int persistent_grid(const void* kernel, size_t lds, long long ntiles) {
+static int persistent_grid(const void* kernel, size_t lds, long long ntiles, int nt = kNT) {
     static std::mutex mu;
     static std::map<std::tuple<int, const void*, size_t>, int> cache;
     int dev = 0;
@@ -264,14 +298,14 @@ static int persistent_grid(const void* kernel, size_t lds, long long ntiles) {
     int resident = 0;
     {
         std::lock_guard<std::mutex> lk(mu);
-        auto key = std::make_tuple(dev, kernel, lds);
+        auto key = std::make_tuple(dev, kernel, lds + ((size_t)nt << 40));
         auto it = cache.find(key);
         if (it != cache.end()) {
             resident = it->second;
         } else {
             int cus = 0, per_cu = 0;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kNT, lds) != hipSuccess) return -1;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, lds) != hipSuccess) return -1;
             resident = std::max(1, per_cu) * std::max(1, cus);
             cache.emplace(key, resident);
         }
@@ -279,40 +313,66 @@ static int persistent_grid(const void* kernel, size_t lds, long long ntiles) {
     return (int)std::min<long long>(ntiles, resident);
 }
 
-template <typename R, int EM>
+// Even grid of block pairs (at most one pair per unit); a multiple of 16 when
+// large enough, so that no pair straddles two XCDs.
+static int pair_grid(int resident, long long nunits) {
+    if (resident < 2) return -1;
+    long long g = 2 * std::min<long long>(nunits, resident / 2);
+    if (g >= 16) g -= g % 16;
+    return (int)g;
+}
+
+template <typename R, int EM, int NT>
 static hipError_t run_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
     const int lgT = ilog2(pl.ty);
     const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
     const int ntiles = ntx * 3 * pl.nz * pl.nbatch;
     const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
-    const int grid = persistent_grid(reinterpret_cast<const void*>(&yfwd_kernel<R, EM>), lds, ntiles);
-    if (grid < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((yfwd_kernel<R, EM>), dim3(grid), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
+    const int grid = pair_grid(persistent_grid(reinterpret_cast<const void*>(&yfwd_kernel<R, EM, NT>), lds,
+                                               1LL << 30, NT),
+                               (long long)(ntiles / ntx) * ((ntx + 1) / 2));
+    if (grid < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((yfwd_kernel<R, EM, NT>), dim3(grid), dim3(NT), lds, s, static_cast<const cx<R>*>(X1),
                        static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx, ntiles);
     return hipGetLastError();
 }
 
-template <typename R, int EM>
+template <typename R, int EM, int NT>
 static hipError_t run_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
     const int lgT = ilog2(pl.ty);
     const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
     const int ntiles = ntx * 3 * pl.nz * pl.nbatch;
     const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
-    const int grid = persistent_grid(reinterpret_cast<const void*>(&yinv_kernel<R, EM>), lds, ntiles);
-    if (grid < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((yinv_kernel<R, EM>), dim3(grid), dim3(kNT), lds, s, static_cast<const cx<R>*>(X2),
+    const int grid = pair_grid(persistent_grid(reinterpret_cast<const void*>(&yinv_kernel<R, EM, NT>), lds,
+                                               1LL << 30, NT),
+                               (long long)(ntiles / ntx) * ((ntx + 1) / 2));
+    if (grid < 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((yinv_kernel<R, EM, NT>), dim3(grid), dim3(NT), lds, s, static_cast<const cx<R>*>(X2),
                        static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx, ntiles);
     return hipGetLastError();
 }
 
+// Tiles of more than 256 x 16 elements: 256 threads of 32 elements (two
+// radix-32 passes for Py = 1024), or with MAGX_Y_THREADS=512 512 threads of 16.
+static bool y_wide(const Plan& pl) {
+    static const int nt = [] {
+        const char* e = std::getenv("MAGX_Y_THREADS");
+        return e ? std::atoi(e) : 256;
+    }();
+    (void)pl;
+    return nt != 256;
+}
+
 template <typename R>
 hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
-    return em_big((long long)pl.Py * pl.ty) ? run_yfwd<R, 32>(pl, X1, X2, s) : run_yfwd<R, 16>(pl, X1, X2, s);
+    if (!em_big((long long)pl.Py * pl.ty)) return run_yfwd<R, 16, kNT>(pl, X1, X2, s);
+    return y_wide(pl) ? run_yfwd<R, 16, 512>(pl, X1, X2, s) : run_yfwd<R, 32, kNT>(pl, X1, X2, s);
 }
 
 template <typename R>
 hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
-    return em_big((long long)pl.Py * pl.ty) ? run_yinv<R, 32>(pl, X2, Y1, s) : run_yinv<R, 16>(pl, X2, Y1, s);
+    if (!em_big((long long)pl.Py * pl.ty)) return run_yinv<R, 16, kNT>(pl, X2, Y1, s);
+    return y_wide(pl) ? run_yinv<R, 16, 512>(pl, X2, Y1, s) : run_yinv<R, 32, kNT>(pl, X2, Y1, s);
 }
 
 template <typename R, int EM>

@@ -12,7 +12,7 @@
 
 namespace magx {
 
-constexpr int kNT = 256;          // threads per block for every FFT/pencil kernel
+constexpr int kNT = 256;          // threads per block of the pencil kernels (and default of the FFT core)
 constexpr int kTwLog = 12;        // twiddle table covers lengths up to 4096
 constexpr int kTwN = 1 << kTwLog;
 
@@ -192,7 +192,8 @@ constexpr int ilog2c(int v) { return v <= 1 ? 0 : 1 + ilog2c(v >> 1); }
 //    thread -> (b, j) split needs no runtime division);
 //  * lines (LAYOUT = kLines): element j of sequence b at (b << lgL) + j;
 //    consecutive threads take consecutive j.
-// Each thread holds at most EMAX elements (nseq * L <= kNT * EMAX).
+// Each of the NT threads of the block holds at most EMAX elements
+// (nseq * L <= NT * EMAX).
 // load(b, j) / store(b, j, v) are used instead of LDS by the first / last
 // pass when SRC_LDS / DST_LDS is false.  HALF_IN: elements j >= L/2 of every
 // input sequence are zero (zero padding of the extended grid), so the first
@@ -265,7 +266,7 @@ struct FirstIn {
 };
 
 template <typename R, int RAD, bool INV, int EMAX, int SRC, bool DST_LDS, int LAYOUT, int NC, bool HIN,
-          bool HOUT, class Load, class Store, class In>
+          bool HOUT, int NT, class Load, class Store, class In>
 __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lgL, int lgNs, int lgT, int nseq,
                                                  Load& load, Store& store, In& in) {
     constexpr bool SRC_LDS = SRC == kSrcLds;
@@ -284,7 +285,7 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
     const int tid = tid_opaque();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int t = tid + i * kNT;
+        const int t = tid + i * NT;
         if (t < total) {
             int b, j;
             seq_split<LAYOUT, NC>(t, lgT, lgnb, nseq, b, j);
@@ -314,7 +315,7 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
     if constexpr (SRC_LDS && DST_LDS) __syncthreads();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int t = tid + i * kNT;
+        const int t = tid + i * NT;
         if (t < total) {
 #pragma unroll
             // with HOUT the outputs r >= RAD/2 land in the unwanted half (last pass)
@@ -344,10 +345,10 @@ template <int EMAX> constexpr int lgmax() { return EMAX >= 32 ? 5 : (EMAX >= 16 
     }
 
 template <typename R, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, int LAYOUT, int NC, bool HALF_IN = false,
-          bool HALF_OUT = false, int LGM = lgmax<EMAX>(), class Load, class Store>
+          bool HALF_OUT = false, int LGM = lgmax<EMAX>(), int NT = kNT, class Load, class Store>
 __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT, int nseq, Load load, Store store) {
     if (lgL == 0) {   // length 1: the transform is the identity
-        for (int b = threadIdx.x; b < nseq; b += kNT) {
+        for (int b = threadIdx.x; b < nseq; b += NT) {
             cx<R> x;
             if constexpr (SRC_LDS) x = buf[b];
             else x = load(b, 0);
@@ -368,10 +369,10 @@ __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT
         const bool last = left == g;
 #define MAGX_BODY(RADIX)                                                                                          \
     if (last)                                                                                                     \
-        stockham_io_pass<R, RADIX, INV, EMAX, SRC_LDS ? kSrcLds : kSrcFn, DST_LDS, LAYOUT, NC, HALF_IN, HALF_OUT>(  \
+        stockham_io_pass<R, RADIX, INV, EMAX, SRC_LDS ? kSrcLds : kSrcFn, DST_LDS, LAYOUT, NC, HALF_IN, HALF_OUT, NT>(  \
             buf, lgL, lgNs, lgT, nseq, load, store, noin);                                                        \
     else                                                                                                          \
-        stockham_io_pass<R, RADIX, INV, EMAX, SRC_LDS ? kSrcLds : kSrcFn, true, LAYOUT, NC, HALF_IN, false>(      \
+        stockham_io_pass<R, RADIX, INV, EMAX, SRC_LDS ? kSrcLds : kSrcFn, true, LAYOUT, NC, HALF_IN, false, NT>(      \
             buf, lgL, lgNs, lgT, nseq, load, store, noin);
         MAGX_RADIX_SWITCH(g, LGM)
 #undef MAGX_BODY
@@ -381,10 +382,10 @@ __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT
     while (left > 0) {
         constexpr int RADIX = 1 << LGM;
         if (left == LGM)
-            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, DST_LDS, LAYOUT, NC, false, HALF_OUT>(
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, DST_LDS, LAYOUT, NC, false, HALF_OUT, NT>(
                 buf, lgL, lgNs, lgT, nseq, load, store, noin);
         else
-            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, true, LAYOUT, NC, false, false>(
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, true, LAYOUT, NC, false, false, NT>(
                 buf, lgL, lgNs, lgT, nseq, load, store, noin);
         lgNs += LGM;
         left -= LGM;
@@ -393,7 +394,7 @@ __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT
 
 // Loads the first pass's inputs of one tile into `in` (lgL >= 1), in the
 // order the register-sourced first pass of fft_reg consumes them.
-template <typename R, int RAD, int EMAX, int LAYOUT, int NC, bool HIN, class Load>
+template <typename R, int RAD, int EMAX, int LAYOUT, int NC, bool HIN, int NT, class Load>
 __device__ __forceinline__ void first_load_rad(FirstIn<R, EMAX, HIN>& in, int lgL, int lgT, int nseq, Load& load) {
     constexpr int PER = EMAX / RAD > 0 ? EMAX / RAD : 1;
     constexpr int LGR = ilog2c(RAD);
@@ -404,7 +405,7 @@ __device__ __forceinline__ void first_load_rad(FirstIn<R, EMAX, HIN>& in, int lg
     const int tid = tid_opaque();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int t = tid + i * kNT;
+        const int t = tid + i * NT;
         if (t < total) {
             int b, j;
             seq_split<LAYOUT, NC>(t, lgT, lgnb, nseq, b, j);
@@ -414,11 +415,11 @@ __device__ __forceinline__ void first_load_rad(FirstIn<R, EMAX, HIN>& in, int lg
     }
 }
 
-template <typename R, int EMAX, int LAYOUT, int NC, bool HIN, int LGM = lgmax<EMAX>(), class Load>
+template <typename R, int EMAX, int LAYOUT, int NC, bool HIN, int LGM = lgmax<EMAX>(), int NT = kNT, class Load>
 __device__ __forceinline__ void first_load(FirstIn<R, EMAX, HIN>& in, int lgL, int lgT, int nseq, Load load) {
     const int rem = lgL % LGM;
     const int g = rem ? rem : LGM;
-#define MAGX_BODY(RADIX) first_load_rad<R, RADIX, EMAX, LAYOUT, NC, HIN>(in, lgL, lgT, nseq, load);
+#define MAGX_BODY(RADIX) first_load_rad<R, RADIX, EMAX, LAYOUT, NC, HIN, NT>(in, lgL, lgT, nseq, load);
     MAGX_RADIX_SWITCH(g, LGM)
 #undef MAGX_BODY
 }
@@ -427,7 +428,7 @@ __device__ __forceinline__ void first_load(FirstIn<R, EMAX, HIN>& in, int lgL, i
 // after_first() runs once the first pass has consumed them, typically to
 // issue the next tile's first_load.  Requires lgL >= 1.
 template <typename R, bool INV, int EMAX, bool DST_LDS, int LAYOUT, int NC, bool HALF_IN, bool HALF_OUT,
-          int LGM = lgmax<EMAX>(), class After, class Store>
+          int LGM = lgmax<EMAX>(), int NT = kNT, class After, class Store>
 __device__ __forceinline__ void fft_reg(cx<R>* __restrict__ buf, int lgL, int lgT, int nseq,
                                         FirstIn<R, EMAX, HALF_IN>& in, After after_first, Store store) {
     static_assert(LGM >= 3 && LGM <= lgmax<EMAX>(), "pass radix beyond the register budget");
@@ -440,10 +441,10 @@ __device__ __forceinline__ void fft_reg(cx<R>* __restrict__ buf, int lgL, int lg
         const bool last = left == g;
 #define MAGX_BODY(RADIX)                                                                                     \
     if (last)                                                                                                \
-        stockham_io_pass<R, RADIX, INV, EMAX, kSrcReg, DST_LDS, LAYOUT, NC, HALF_IN, HALF_OUT>(              \
+        stockham_io_pass<R, RADIX, INV, EMAX, kSrcReg, DST_LDS, LAYOUT, NC, HALF_IN, HALF_OUT, NT>(              \
             buf, lgL, lgNs, lgT, nseq, none_load, store, in);                                                \
     else                                                                                                     \
-        stockham_io_pass<R, RADIX, INV, EMAX, kSrcReg, true, LAYOUT, NC, HALF_IN, false>(buf, lgL, lgNs, lgT, \
+        stockham_io_pass<R, RADIX, INV, EMAX, kSrcReg, true, LAYOUT, NC, HALF_IN, false, NT>(buf, lgL, lgNs, lgT, \
                                                                                          nseq, none_load,    \
                                                                                          store, in);
         MAGX_RADIX_SWITCH(g, LGM)
@@ -455,10 +456,10 @@ __device__ __forceinline__ void fft_reg(cx<R>* __restrict__ buf, int lgL, int lg
     while (left > 0) {
         constexpr int RADIX = 1 << LGM;
         if (left == LGM)
-            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, DST_LDS, LAYOUT, NC, false, HALF_OUT>(
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, DST_LDS, LAYOUT, NC, false, HALF_OUT, NT>(
                 buf, lgL, lgNs, lgT, nseq, none_load, store, noin);
         else
-            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, true, LAYOUT, NC, false, false>(
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, true, LAYOUT, NC, false, false, NT>(
                 buf, lgL, lgNs, lgT, nseq, none_load, store, noin);
         lgNs += LGM;
         left -= LGM;
