@@ -20,6 +20,7 @@ template <bool BIG> constexpr int maxslot() { return BIG ? 8 : 4; }
 struct PG {
     int nx, ny, nz, Lh, lgLh, Hx, Sx, lgPx, np, npen_total;   // npen_total: pencils of one member
     int bpm;                                                 // blocks per member
+    int zmajor;                                              // block order: z fastest (see block_pencils)
     long long N;                                             // cells of one member
     FastDiv div_ny, div_hx;                                  // n / ny and n / Hx
 };
@@ -35,7 +36,27 @@ inline PG make_pg(const Plan& pl) {
     g.np = pl.np; g.npen_total = pl.ny * pl.nz; g.bpm = pl.blocks_per_member; g.N = pl.ncell;
     g.div_ny = make_fastdiv(pl.ny);
     g.div_hx = make_fastdiv(pl.Hx);
+    g.zmajor = pl.pencil_zmajor;
     return g;
+}
+
+// Pencils of block lbm of a member: np consecutive rows y of one plane z.
+// With zmajor the blocks run through z fastest ((y group, z) -> lbm =
+// group * nz + z), so the blocks holding a row's z neighbours run right
+// before and after it on the same XCD and the stencil finds them in L2;
+// otherwise pencils are numbered z * ny + y and a block takes np of them.
+// Either way its pencils are consecutive in the z * ny + y numbering.
+__device__ __forceinline__ void block_pencils(const PG& g, int lbm, int& pen0, int& npen) {
+    if (g.zmajor) {
+        const int grp = lbm / g.nz;
+        const int z = lbm - grp * g.nz;
+        const int y0 = grp * g.np;
+        pen0 = z * g.ny + y0;
+        npen = min(g.np, g.ny - y0);
+    } else {
+        pen0 = lbm * g.np;
+        npen = min(g.np, g.npen_total - pen0);
+    }
 }
 
 template <typename R>

@@ -140,8 +140,12 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
     }
     const int npen = p.ny * p.nz;
     if (p.np > npen) p.np = npen;
-    // pencil blocks never straddle two members (the last one of a member may be ragged)
-    p.blocks_per_member = (npen + p.np - 1) / p.np;
+    // pencil blocks never straddle two members (the last one of a member may be
+    // ragged); with ny >= np and nz > 1 a block holds np rows of one plane and
+    // blocks run through z fastest
+    p.pencil_zmajor = (p.ny >= p.np && p.nz > 1) ? 1 : 0;
+    if (const char* e = std::getenv("MAGX_PENCIL_ORDER")) p.pencil_zmajor = (std::atoi(e) == 1 && p.nz > 1) ? 1 : 0;
+    p.blocks_per_member = p.pencil_zmajor ? p.nz * ((p.ny + p.np - 1) / p.np) : (npen + p.np - 1) / p.np;
     p.pencil_blocks = nbatch * p.blocks_per_member;
     const size_t es = (size_t)p.esize;
     const long long N = p.ncell * nbatch;

@@ -28,7 +28,8 @@ struct Plan {
     int Hx, Hy, Hz, Sx;
     long long ncell;            // cells of one member
     int nbatch;                 // independent systems sharing the tensor spectrum
-    int blocks_per_member;      // pencil blocks of one member (np divides ny*nz)
+    int blocks_per_member;      // pencil blocks of one member
+    int pencil_zmajor;          // pencil blocks ordered (y group, z) with z fastest
     // tensor build scratch (doubles): slab A = max(octant, y-pass output), then slab B
     long long scratch_a_elems, scratch_b_elems;
     // column tiles of the y and z passes, pencils per block of the x passes

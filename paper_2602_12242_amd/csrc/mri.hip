@@ -28,8 +28,8 @@ __global__ void __launch_bounds__(kNT) mri_slow_kernel(const cx<R>* __restrict__
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int mb = lb / g.bpm;
-    const int pen0 = (lb - mb * g.bpm) * g.np;
-    const int npen = min(g.np, g.npen_total - pen0);
+    int pen0, npen;
+    block_pencils(g, lb - mb * g.bpm, pen0, npen);
     const long long mo = (long long)mb * 3 * g.N;
     y += mo;
     r_out += mo;
@@ -92,8 +92,8 @@ __global__ void __launch_bounds__(kNT) mri_fast_kernel(const R* __restrict__ v, 
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int mb = lb / g.bpm;
-    const int pen0 = (lb - mb * g.bpm) * g.np;
-    const int npen = min(g.np, g.npen_total - pen0);
+    int pen0, npen;
+    block_pencils(g, lb - mb * g.bpm, pen0, npen);
     const long long mo = (long long)mb * 3 * g.N;
     v += mo;
     vout += mo;

@@ -33,8 +33,8 @@ __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R
     // logical block -> member mb and its first pencil; members own contiguous block ranges
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int mb = lb / g.bpm;
-    const int pen0 = (lb - mb * g.bpm) * g.np;
-    const int npen = min(g.np, g.npen_total - pen0);
+    int pen0, npen;
+    block_pencils(g, lb - mb * g.bpm, pen0, npen);
     const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
     f += mo;
     for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
@@ -71,8 +71,8 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
     // logical block -> member mb and its first pencil; members own contiguous block ranges
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int mb = lb / g.bpm;
-    const int pen0 = (lb - mb * g.bpm) * g.np;
-    const int npen = min(g.np, g.npen_total - pen0);
+    int pen0, npen;
+    block_pencils(g, lb - mb * g.bpm, pen0, npen);
     const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
     f += mo;
     if (H) H += mo;
@@ -145,8 +145,8 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
     // logical block -> member mb and its first pencil; members own contiguous block ranges
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int mb = lb / g.bpm;
-    const int pen0 = (lb - mb * g.bpm) * g.np;
-    const int npen = min(g.np, g.npen_total - pen0);
+    int pen0, npen;
+    block_pencils(g, lb - mb * g.bpm, pen0, npen);
     const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
     const long long mo1 = (long long)mb * g.N;      // member offset of scalar fields
     a.yin += mo;
@@ -264,8 +264,8 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
     // logical block -> member mb and its first pencil; members own contiguous block ranges
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int mb = lb / g.bpm;
-    const int pen0 = (lb - mb * g.bpm) * g.np;
-    const int npen = min(g.np, g.npen_total - pen0);
+    int pen0, npen;
+    block_pencils(g, lb - mb * g.bpm, pen0, npen);
     const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
     const long long mo1 = (long long)mb * g.N;      // member offset of scalar fields
     a.gm += mo;
@@ -355,8 +355,8 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
     // logical block -> member mb and its first pencil; members own contiguous block ranges
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
     const int mb = lb / g.bpm;
-    const int pen0 = (lb - mb * g.bpm) * g.np;
-    const int npen = min(g.np, g.npen_total - pen0);
+    int pen0, npen;
+    block_pencils(g, lb - mb * g.bpm, pen0, npen);
     const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
     const long long mo1 = (long long)mb * g.N;      // member offset of scalar fields
     a.mu += mo;
