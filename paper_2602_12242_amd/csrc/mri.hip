@@ -101,7 +101,8 @@ __global__ void __launch_bounds__(kNT) mri_fast_kernel(const R* __restrict__ v, 
     rbuf += mo;
     const bool vec = (g.nx & 1) == 0;
     // v_out also goes into this thread's LDS line entries for the forward x pass
-#pragma unroll
+    // one slot (cell pair) per iteration; kept rolled to keep the kernel small
+#pragma unroll 1
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e >= npen * g.Lh) continue;

@@ -171,7 +171,8 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
     // the next stage input goes straight into this thread's own LDS line
     // entries (the ones it read the demag field from) for the forward x pass
     const bool fwd = a.want_next && has_demag;
-#pragma unroll
+    // one slot (cell pair) per iteration; kept rolled to keep the kernel small
+#pragma unroll 1
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e >= npen * g.Lh) continue;
@@ -280,7 +281,8 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
     const R b4 = (R)(1.0 / 6.0);
     double hs[3] = {0, 0, 0};
     // mu_4 goes straight into this thread's LDS line entries for the forward x pass
-#pragma unroll
+    // one slot (cell pair) per iteration; kept rolled to keep the kernel small
+#pragma unroll 1
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e >= npen * g.Lh) continue;
@@ -378,7 +380,8 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
     // mu_{s-1} goes straight into this thread's own LDS line entries (read
     // above for K mu_s) for the forward x pass
     const bool fwd = s > 1 && has_demag;
-#pragma unroll
+    // one slot (cell pair) per iteration; kept rolled to keep the kernel small
+#pragma unroll 1
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
         if (e >= npen * g.Lh) continue;
