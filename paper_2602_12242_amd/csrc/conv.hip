@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, 
         const cx<R>* src = X1 + plane * ny * (long long)Sx + kx0;
         const int ncol = min(T, Hx - kx0);
         return [=](int b, int j) -> cx<R> {
-            if (j < ny && b < ncol) return src[mul24(j, Sx) + b];
+            if (j < ny && b < ncol) return src[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b];
             return mk<R>(0, 0);
         };
     };
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, 
         cx<R>* dst = X2 + plane * Py * (long long)Sx + kx0;
         const int ncol = min(T, Hx - kx0);
         auto store = [&](int b, int j, cx<R> v) {
-            if (b < ncol) dst[mul24(j, Sx) + b] = v;
+            if (b < ncol) dst[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b] = v;
         };
         auto next = [&]() {
             if (un < pw.u1)
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, 
         const cx<R>* src = X2 + plane * Py * (long long)Sx + kx0;
         const int ncol = min(T, Hx - kx0);
         return [=](int b, int j) -> cx<R> {
-            if (b < ncol) return src[mul24(j, Sx) + b];
+            if (b < ncol) return src[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b];
             return mk<R>(0, 0);
         };
     };
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, 
         const int ncol = min(T, Hx - kx0);
         // only rows inside the box are written
         auto store = [&](int b, int j, cx<R> v) {
-            if (j < ny && b < ncol) dst[mul24(j, Sx) + b] = v;
+            if (j < ny && b < ncol) dst[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b] = v;
         };
         auto next = [&]() {
             if (un < pw.u1)
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
         const int ncol = min(T, Hx - d.kx0);
         return [=](int b, int j) -> cx<R> {
             const int c = b >> lgT, col = b & (T - 1);
-            if (j < nz && col < ncol) return base[c * comp_stride + mul24(j, plane_stride) + col];
+            if (j < nz && col < ncol) return base[(unsigned)c * (unsigned)comp_stride + umul24((unsigned)j, (unsigned)plane_stride) + (unsigned)col];
             return mk<R>(0, 0);
         };
     };
@@ -244,7 +244,7 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
         const int ncol = min(T, Hx - d.kx0);
         auto store = [&](int b, int j, cx<R> v) {
             const int c = b >> lgT, col = b & (T - 1);
-            if (j < nz && col < ncol) base[c * comp_stride + mul24(j, plane_stride) + col] = v;
+            if (j < nz && col < ncol) base[(unsigned)c * (unsigned)comp_stride + umul24((unsigned)j, (unsigned)plane_stride) + (unsigned)col] = v;
         };
         auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
         auto none_store = [&](int, int, cx<R>) {};

@@ -40,8 +40,8 @@ extern __device__ float2 g_tw32[kTwN];
 extern __device__ double2 g_tw64[kTwN];
 
 template <typename R> __device__ __forceinline__ cx<R> tw_fwd(int k);
-template <> __device__ __forceinline__ float2 tw_fwd<float>(int k) { return g_tw32[k]; }
-template <> __device__ __forceinline__ double2 tw_fwd<double>(int k) { return g_tw64[k]; }
+template <> __device__ __forceinline__ float2 tw_fwd<float>(int k) { return g_tw32[(unsigned)k]; }
+template <> __device__ __forceinline__ double2 tw_fwd<double>(int k) { return g_tw64[(unsigned)k]; }
 // w^k for a transform of direction INV; k indexes the 4096-point table.
 template <typename R, bool INV> __device__ __forceinline__ cx<R> tw(int k) {
     cx<R> w = tw_fwd<R>(k);
@@ -207,6 +207,7 @@ constexpr int kCols = 0;
 constexpr int kLines = 1;
 
 __device__ __forceinline__ int mul24(int a, int b) { return __mul24(a, b); }
+__device__ __forceinline__ unsigned umul24(unsigned a, unsigned b) { return __umul24(a, b); }
 
 // threadIdx.x behind an empty volatile asm statement: index arithmetic derived
 // from it is recomputed in each pass instead of being hoisted out of a tile
@@ -236,17 +237,19 @@ __device__ __forceinline__ void twiddle_apply(cx<R>* v, int k, int twshift) {
     for (int r = 1; r < RAD; ++r) v[r] = cmul<R>(v[r], w[r]);
 }
 
+// Thread slot t -> (sequence b, butterfly j); unsigned arithmetic throughout
+// (no sign fix-ups in shifts and divisions).
 template <int LAYOUT, int NC>
-__device__ __forceinline__ void seq_split(int t, int lgT, int lgnb, int nseq, int& b, int& j) {
+__device__ __forceinline__ void seq_split(unsigned t, int lgT, int lgnb, unsigned nseq, unsigned& b, unsigned& j) {
     if constexpr (LAYOUT == kLines) {
         b = t >> lgnb;
-        j = t & ((1 << lgnb) - 1);
+        j = t & ((1u << lgnb) - 1u);
     } else if constexpr (NC == 1) {
-        b = t & (nseq - 1);
+        b = t & (nseq - 1u);
         j = t >> lgT;
     } else {
-        j = (t >> lgT) / NC;
-        b = t - mul24(j, nseq);
+        j = (t >> lgT) / (unsigned)NC;
+        b = t - umul24(j, nseq);
     }
 }
 
@@ -273,22 +276,22 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
     constexpr int PER = EMAX / RAD > 0 ? EMAX / RAD : 1;
     constexpr int LGR = ilog2c(RAD);
     const int lgnb = lgL - LGR;
-    const int nb = 1 << lgnb;
-    const int total = nb * nseq;
-    const int Ns = 1 << lgNs;
+    const unsigned nb = 1u << lgnb;
+    const unsigned total = nb * (unsigned)nseq;
+    const unsigned Ns = 1u << lgNs;
     const int twshift = kTwLog - LGR - lgNs;
     // uniform strides between the RAD inputs / outputs of one butterfly
-    const int in_stride = LAYOUT == kLines ? nb : (nb * nseq);
-    const int out_stride = LAYOUT == kLines ? Ns : (Ns * nseq);
+    const unsigned in_stride = LAYOUT == kLines ? nb : (nb * (unsigned)nseq);
+    const unsigned out_stride = LAYOUT == kLines ? Ns : (Ns * (unsigned)nseq);
     cx<R> v[PER][RAD];
-    int seqv[PER], pos0[PER], obase[PER];
-    const int tid = tid_opaque();
+    unsigned seqv[PER], pos0[PER], obase[PER];
+    const unsigned tid = (unsigned)tid_opaque();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int t = tid + i * NT;
+        const unsigned t = tid + (unsigned)(i * NT);
         if (t < total) {
-            int b, j;
-            seq_split<LAYOUT, NC>(t, lgT, lgnb, nseq, b, j);
+            unsigned b, j;
+            seq_split<LAYOUT, NC>(t, lgT, lgnb, (unsigned)nseq, b, j);
             seqv[i] = b;
             // with HIN the inputs r >= RAD/2 lie in the zero half (first pass: lgNs = 0)
             constexpr int RIN = HIN ? RAD / 2 : RAD;
@@ -296,32 +299,32 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
 #pragma unroll
                 for (int r = 0; r < RIN; ++r) v[i][r] = in.v[i * RIN + r];
             } else if constexpr (SRC_LDS) {
-                const int ib = LAYOUT == kLines ? (b << lgL) + j : b + mul24(j, nseq);
+                const unsigned ib = LAYOUT == kLines ? (b << lgL) + j : b + umul24(j, (unsigned)nseq);
 #pragma unroll
-                for (int r = 0; r < RIN; ++r) v[i][r] = buf[ib + r * in_stride];
+                for (int r = 0; r < RIN; ++r) v[i][r] = buf[ib + (unsigned)r * in_stride];
             } else {
 #pragma unroll
-                for (int r = 0; r < RIN; ++r) v[i][r] = load(b, j + (r << lgnb));
+                for (int r = 0; r < RIN; ++r) v[i][r] = load((int)b, (int)(j + ((unsigned)r << lgnb)));
             }
 #pragma unroll
             for (int r = RIN; r < RAD; ++r) v[i][r] = mk<R>((R)0, (R)0);
-            const int k = j & (Ns - 1);
+            const unsigned k = j & (Ns - 1u);
             pos0[i] = ((j >> lgNs) << (lgNs + LGR)) + k;
-            obase[i] = LAYOUT == kLines ? (b << lgL) + pos0[i] : b + mul24(pos0[i], nseq);
-            twiddle_apply<R, INV, RAD>(v[i], k, twshift);
+            obase[i] = LAYOUT == kLines ? (b << lgL) + pos0[i] : b + umul24(pos0[i], (unsigned)nseq);
+            twiddle_apply<R, INV, RAD>(v[i], (int)k, twshift);
             dft<R, RAD, INV>(v[i]);
         }
     }
     if constexpr (SRC_LDS && DST_LDS) __syncthreads();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int t = tid + i * NT;
+        const unsigned t = tid + (unsigned)(i * NT);
         if (t < total) {
 #pragma unroll
             // with HOUT the outputs r >= RAD/2 land in the unwanted half (last pass)
             for (int r = 0; r < (HOUT ? RAD / 2 : RAD); ++r) {
-                if constexpr (DST_LDS) buf[obase[i] + r * out_stride] = v[i][r];
-                else store(seqv[i], pos0[i] + r * Ns, v[i][r]);
+                if constexpr (DST_LDS) buf[obase[i] + (unsigned)r * out_stride] = v[i][r];
+                else store((int)seqv[i], (int)(pos0[i] + (unsigned)r * Ns), v[i][r]);
             }
         }
     }
@@ -401,16 +404,16 @@ __device__ __forceinline__ void first_load_rad(FirstIn<R, EMAX, HIN>& in, int lg
     constexpr int RIN = HIN ? RAD / 2 : RAD;
     static_assert(PER * RIN <= FirstIn<R, EMAX, HIN>::N, "first-pass register budget");
     const int lgnb = lgL - LGR;
-    const int total = (1 << lgnb) * nseq;
-    const int tid = tid_opaque();
+    const unsigned total = (1u << lgnb) * (unsigned)nseq;
+    const unsigned tid = (unsigned)tid_opaque();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
-        const int t = tid + i * NT;
+        const unsigned t = tid + (unsigned)(i * NT);
         if (t < total) {
-            int b, j;
-            seq_split<LAYOUT, NC>(t, lgT, lgnb, nseq, b, j);
+            unsigned b, j;
+            seq_split<LAYOUT, NC>(t, lgT, lgnb, (unsigned)nseq, b, j);
 #pragma unroll
-            for (int r = 0; r < RIN; ++r) in.v[i * RIN + r] = load(b, j + (r << lgnb));
+            for (int r = 0; r < RIN; ++r) in.v[i * RIN + r] = load((int)b, (int)(j + ((unsigned)r << lgnb)));
         }
     }
 }
