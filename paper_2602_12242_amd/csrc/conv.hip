@@ -15,6 +15,7 @@
 #include <map>
 #include <mutex>
 #include <tuple>
+#include <type_traits>
 
 #include "magx_internal.hpp"
 
@@ -285,6 +286,159 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     }
 }
 
+// z pass for Pz = 64 (8 x 8 in registers, single precision).  Thread
+// (col, g), col < 32, g < 8, of a 32-column tile holds the elements
+// z = g + 8 r (r < 8) of all three components: a length-8 DFT over r, the
+// twiddles W_64^(g k1), one LDS exchange to (col, k1), a length-8 DFT over g,
+// and it then holds kz = k1 + 8 k2 (k2 < 8) of all three components, so the
+// 3x3 spectral product runs in registers; the inverse retraces the same steps
+// with conjugate twiddles.  Rows z >= nz (nz <= 32) are the zero padding of
+// the forward transform and are not written back.  The tensor spectrum is the
+// tile-major layout of the generic pass with a tile width of 32.
+constexpr int kZ64T = 32;
+
+template <typename R>
+__global__ void __launch_bounds__(kNT) zconv64_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
+                                                      int nz, int Py, int Hx, int Sx, int ntx,
+                                                      int units_per_member, int nunits) {
+    constexpr int T = kZ64T, Hz = 33, H2 = 32;
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* E = reinterpret_cast<cx<R>*>(smem_raw);   // [3][8][8][T]
+    const int tid = threadIdx.x;
+    const int col = tid & (T - 1);
+    const int g = tid >> 5;
+    const unsigned plane_stride = (unsigned)Py * (unsigned)Sx;
+    const unsigned comp_stride = (unsigned)nz * plane_stride;
+    // W_64^(g j), j < 8, from the table (the inverse uses the conjugates)
+    cx<R> w[8];
+    w[0] = mk<R>((R)1, (R)0);
+#pragma unroll
+    for (int j = 1; j < 8; ++j) w[j] = tw_fwd<R>((g * j) << (kTwLog - 6));
+    struct Tile {
+        int mb, kx0, ky, tx, kyo;
+    };
+    const int lbp = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int side = lbp & 1;
+    auto tile_of = [=](int u) {
+        Tile d;
+        d.mb = u / units_per_member;
+        const int r = u - d.mb * units_per_member;
+        const int q = r / ntx;
+        d.tx = r - q * ntx;
+        d.kyo = side ? (q == 0 ? Py >> 1 : q) : q;
+        d.ky = side ? (q == 0 ? Py >> 1 : Py - q) : q;
+        d.kx0 = d.tx * T;
+        return d;
+    };
+    auto base_of = [=](const Tile& d) {
+        return X2 + (long long)d.mb * 3 * comp_stride + (long long)d.ky * Sx + d.kx0;
+    };
+    // Inputs of a tile: rows g + 8 r, r < 4, of the three components.  Every
+    // operation of the pass acts on one column, so a column beyond Hx (read at
+    // the clamped column Hx-1 of the same row) only produces values that are
+    // never stored; rows z >= nz are the zero padding.
+    cx<R> pin[12];
+    auto load_tile = [&](int u) {
+        const Tile d = tile_of(u);
+        const cx<R>* base = base_of(d);
+        const unsigned voff = (unsigned)g * plane_stride + (unsigned)min(col, Hx - 1 - d.kx0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int z = g + 8 * r;
+                const unsigned zoff = (unsigned)min(8 * r, nz - 1 - g) * plane_stride;
+                const cx<R> v = base[(unsigned)c * comp_stride + zoff + voff];
+                pin[c * 4 + r] = z < nz ? v : mk<R>((R)0, (R)0);
+            }
+    };
+    const int npairs = gridDim.x >> 1;
+    const int pr = lbp >> 1;
+    const int t0 = (int)((long long)nunits * pr / npairs);
+    const int t1 = (int)((long long)nunits * (pr + 1) / npairs);
+    if (t0 < t1) load_tile(t0);
+    const R s = -Ms;
+    for (int t = t0; t < t1; ++t) {
+        const Tile d = tile_of(t);
+        const R sy = d.ky <= Py / 2 ? (R)1 : (R)-1;
+        // tensor values of kz = g + 8 k2 (this thread's rows after the exchange),
+        // read at the octant row kzo = kz (k2 < 4) or 64 - kz (k2 >= 4); the
+        // tile's block [6][Hz][T] of the tile-major spectrum is contiguous and
+        // includes the padding columns of the last tile
+        R tv[8][6];
+        {
+            const R* blk = spec + (long long)(d.kyo * ntx + d.tx) * 6 * (Hz * T);
+            const int lo = g * T + col, hi = (64 - g) * T + col;
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) {
+                const int o = k2 < 4 ? lo + 8 * k2 * T : hi - 8 * k2 * T;
+#pragma unroll
+                for (int c6 = 0; c6 < 6; ++c6) tv[k2][c6] = blk[c6 * (Hz * T) + o];
+            }
+        }
+        // forward: DFT over r, twiddles, exchange
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<R> v[8];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = pin[c * 4 + r];
+#pragma unroll
+            for (int r = 4; r < 8; ++r) v[r] = mk<R>((R)0, (R)0);
+            dft8<R, false>(v);
+#pragma unroll
+            for (int k1 = 0; k1 < 8; ++k1) E[((c * 8 + k1) * 8 + g) * T + col] = cmul<R>(v[k1], w[k1]);
+        }
+        __syncthreads();
+        cx<R> X[3][8];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) X[c][q] = E[((c * 8 + g) * 8 + q) * T + col];
+            dft8<R, false>(X[c]);
+        }
+        // spectral product at kz = g + 8 k2
+#pragma unroll
+        for (int k2 = 0; k2 < 8; ++k2) {
+            const int kz = g + 8 * k2;
+            const R sz = kz <= H2 ? (R)1 : (R)-1;
+            const R nxx = tv[k2][0], nyy = tv[k2][1], nzz = tv[k2][2];
+            const R nxy = sy * tv[k2][3], nxz = sz * tv[k2][4], nyz = sy * sz * tv[k2][5];
+            const cx<R> mx = X[0][k2], my = X[1][k2], mz = X[2][k2];
+            X[0][k2] = mk<R>(s * (nxx * mx.x + nxy * my.x + nxz * mz.x), s * (nxx * mx.y + nxy * my.y + nxz * mz.y));
+            X[1][k2] = mk<R>(s * (nxy * mx.x + nyy * my.x + nyz * mz.x), s * (nxy * mx.y + nyy * my.y + nyz * mz.y));
+            X[2][k2] = mk<R>(s * (nxz * mx.x + nyz * my.x + nzz * mz.x), s * (nxz * mx.y + nyz * my.y + nzz * mz.y));
+        }
+        // the next tile's inputs are in flight during the inverse transform
+        if (t + 1 < t1) load_tile(t + 1);
+        // inverse: DFT over k2, conjugate twiddles, exchange back
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dft8<R, true>(X[c]);
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int n2 = 0; n2 < 8; ++n2) E[((c * 8 + n2) * 8 + g) * T + col] = cmul<R>(X[c][n2], cconj<R>(w[n2]));
+        __syncthreads();
+        cx<R>* base = base_of(d);
+        const bool okc = d.kx0 + col < Hx;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<R> v[8];
+#pragma unroll
+            for (int k1 = 0; k1 < 8; ++k1) v[k1] = E[((c * 8 + g) * 8 + k1) * T + col];
+            dft8<R, true>(v);
+            // rows z = g + 8 n1 >= 32 >= nz are never needed
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) {
+                const int z = g + 8 * n1;
+                if (okc && z < nz)
+                    base[(unsigned)c * comp_stride + (unsigned)z * plane_stride + (unsigned)col] = v[n1];
+            }
+        }
+        __syncthreads();   // the next tile's forward exchange rewrites E
+    }
+}
+
 static inline bool em_big(long long elements) { return elements > (long long)kNT * 16; }
 
 // Blocks of a persistent launch: as many as can be resident on the device
@@ -395,8 +549,26 @@ static hipError_t run_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hi
     return hipGetLastError();
 }
 
+static hipError_t run_zconv64(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
+    if (pl.Pz != 64 || pl.tz != kZ64T || pl.nz > 32 || pl.nz < 8) return hipErrorInvalidValue;
+    const int ntx = pl.ntz;
+    const int upm = ntx * (pl.Py / 2);
+    const long long nunits = (long long)upm * pl.nbatch;
+    const size_t lds = (size_t)3 * 64 * kZ64T * sizeof(cx<float>);
+    const int resident = persistent_grid(reinterpret_cast<const void*>(&zconv64_kernel<float>), lds, 1LL << 30);
+    if (resident < 1) return hipErrorInvalidValue;
+    long long grid = 2 * std::min<long long>(nunits, std::max(1, resident / 2));
+    if (grid >= 16) grid -= grid % 16;
+    hipLaunchKernelGGL((zconv64_kernel<float>), dim3((unsigned)grid), dim3(kNT), lds, s, static_cast<cx<float>*>(X2),
+                       static_cast<const float*>(spec), Ms, pl.nz, pl.Py, pl.Hx, pl.Sx, ntx, upm, (int)nunits);
+    return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s) {
+    if constexpr (std::is_same<R, float>::value) {
+        if (pl.zreg) return run_zconv64(pl, X2, spec, Ms, s);
+    }
     return em_big(3LL * pl.Pz * pl.tz) ? run_zconv<R, 32>(pl, X2, spec, Ms, s) : run_zconv<R, 16>(pl, X2, spec, Ms, s);
 }
 

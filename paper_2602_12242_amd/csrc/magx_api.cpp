@@ -128,6 +128,13 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
             const int t = std::atoi(e);
             if (t >= 1 && (t & (t - 1)) == 0 && fits(t, 32)) tz = t;
         }
+        // single precision with Pz = 64: the register-resident z pass, 32 columns per tile
+        static const bool zreg_on = [] {
+            const char* e = std::getenv("MAGX_ZREG");
+            return !(e && std::atoi(e) == 0);
+        }();
+        p.zreg = (zreg_on && dt == MAGX_F32 && p.Pz == 64) ? 1 : 0;
+        if (p.zreg) tz = 32;
         p.tz = tz;
         p.ntz = (p.Hx + tz - 1) / tz;
         if ((long long)p.Hy * p.ntz * 6 * p.Hz * tz >= (1LL << 31)) return MAGX_ESIZE;

@@ -57,10 +57,12 @@ def test_sizes_of_workloads():
     s = magx.magx_sizes((512, 512, 32), (2.5e-9,) * 3, magx.F32)
     N = 512 * 512 * 32
     assert s["field_bytes"] == 3 * N * 4
-    assert s["spectrum_bytes"] == 6 * 33 * 513 * 528 * 4
+    # [Hy][ntz][6][Hz][tz]: single precision with Pz = 64 takes 32-column
+    # tiles (17 for Hx = 513), double precision 16-column tiles (33)
+    assert s["spectrum_bytes"] == 6 * 33 * 513 * (17 * 32) * 4
     assert s["tape_bytes_per_step"] == 28 * N * 4
     s64 = magx.magx_sizes((512, 512, 32), (2.5e-9,) * 3, magx.F64)
-    assert s64["spectrum_bytes"] == 2 * s["spectrum_bytes"]
+    assert s64["spectrum_bytes"] == 6 * 33 * 513 * (33 * 16) * 8
     # the large workload fits
     s = magx.magx_sizes((1024, 1024, 64), (3e-9,) * 3, magx.F32)
     assert s["workspace_bytes"] < 40e9

@@ -42,6 +42,13 @@ CASES = {
              dict(Ms=8e5, alpha=0.1, Hbias=(0, 0, 2e5), terms=1 | 16)),
     "tiles": ((96, 70, 9), (2e-9, 2e-9, 3e-9),
               dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, alpha=0.1, Hbias=(1e3, 2e3, -5e3), terms=ALL)),
+    # Pz = 64: in single precision the register-resident z pass (32-column
+    # tiles, a ragged last tile of one column); nz = 17 is its shortest input
+    "thick": ((70, 9, 20), (2e-9, 2e-9, 1e-9),
+              dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, eK=(0.6, 0.0, 0.8), alpha=0.1,
+                   Hbias=(1e3, -2e3, 5e3), terms=ALL)),
+    "slab17": ((24, 5, 17), (2.5e-9, 2e-9, 1.5e-9),
+               dict(Ms=8e5, A=1.3e-11, alpha=0.2, Hbias=(0, 3e3, 1e4), terms=1 | 2 | 16)),
     # Pz = 1024: the longest z transform, one column per z tile
     "tall": ((3, 2, 300), (2e-9, 2e-9, 1e-9),
              dict(Ms=8e5, A=1.3e-11, alpha=0.1, Hbias=(0, 0, 1e4), terms=1 | 2 | 16)),
@@ -96,7 +103,7 @@ def _dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=t)
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "film", "column", "tiles"])
+@pytest.mark.parametrize("name", ["tiny_all", "film", "column", "tiles", "thick"])
 def test_tensor_spectrum_matches_oracle(name):
     n, d, _ = CASES[name]
     g, spec, P = _oracle_setup(name)
@@ -138,7 +145,7 @@ def test_llg_rhs_matches_oracle(dtype):
     assert _err(k.cpu().numpy(), ref) <= (1e-14 if dtype == 1 else 1e-6)
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "film", "line", "cell", "tiles"])
+@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "film", "line", "cell", "tiles", "thick"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_one_rk4_step_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -175,7 +182,7 @@ def test_several_steps_f64_and_norm(renorm):
         assert np.abs(np.sqrt(np.sum(out ** 2, axis=0)) - 1).max() < 1e-15
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "film", "tiles"])
+@pytest.mark.parametrize("name", ["tiny_all", "film", "tiles", "thick"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_energy_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -191,7 +198,7 @@ def test_energy_matches_oracle(name, dtype):
     assert abs(e[5] - ref["total"]) <= (1e-11 if dtype == 1 else 2e-5) * scale
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles"])
+@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_heff_backward_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
