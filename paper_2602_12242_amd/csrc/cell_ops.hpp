@@ -324,52 +324,92 @@ __device__ __forceinline__ void pen_coords(const PG& g, int pen, int& y, int& z)
     y = pen - z * g.ny;
 }
 
+// Row of X1/Y1 holding component c of pencil p (32-bit element offset: the
+// spectral arrays of a whole batch stay below 2^31 elements).
+__device__ __forceinline__ unsigned x_row(const PG& g, int mb, int c, int pen) {
+    int y, z;
+    z = fdiv(pen, g.div_ny);
+    y = pen - z * g.ny;
+    return (((unsigned)(mb * 3 + c) * (unsigned)g.nz + (unsigned)z) * (unsigned)g.ny + (unsigned)y) * (unsigned)g.Sx;
+}
+
+// The half-length real-FFT split and merge steps pair bin k with its mirror
+// Lh - k: both come from the same two values and the same twiddle
+// W^k = exp(-2 pi i k / Px), since W^(Lh-k) = -conj(W^k).  Item t < Lq
+// (Lq = max(Lh/2, 1)) of a line takes k = t and Lh - t; t = 0 also takes
+// k = Lh/2 (its own mirror).
+
 // Inverse x pass: Y1 rows -> real lines; afterwards the real value of cell x
-// of line l is buf[l*Lh + x/2].x (x even) or .y (x odd).
+// of line l is buf[l*Lh + x/2].x (x even) or .y (x odd).  Split step of the
+// half-length inverse, Z[k] = (X[k] + X*[Lh-k]) + i (X[k] - X*[Lh-k]) w^-k
+// (w^-k = conj(W^k)), into LDS; then the inverse FFT of every line in LDS.
 template <typename R, bool BIG>
 __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int mb, int pen0, int npen) {
     const int Lh = g.Lh;
+    const int lgq = g.lgLh > 0 ? g.lgLh - 1 : 0;
     const int twsh = kTwLog - g.lgPx;
-    // split step of the half-length inverse, computed while the first FFT
-    // pass reads Y1: Z[k] = (X[k] + X*[Lh-k]) + i (X[k] - X*[Lh-k]) w^-k
-    auto load = [&](int line, int k) -> cx<R> {
-        const int p = line / 3, c = line - 3 * p;
-        int y, z;
-        pen_coords<R>(g, pen0 + p, y, z);
-        const cx<R>* row = Y1 + ((((mb * 3 + c) * g.nz + z) * g.ny + y) * g.Sx);
-        const cx<R> a = row[k];
-        const cx<R> b = cconj<R>(row[Lh - k]);
-        const cx<R> A = cadd<R>(a, b);
-        const cx<R> B = cmul<R>(csub<R>(a, b), cconj<R>(tw_fwd<R>(k << twsh)));
+    auto split = [](cx<R> a, cx<R> b, cx<R> wc) {   // a = X[k], b = X[Lh-k], wc = conj(W^k)
+        const cx<R> bc = cconj<R>(b);
+        const cx<R> A = cadd<R>(a, bc);
+        const cx<R> B = cmul<R>(csub<R>(a, bc), wc);
         return mk<R>(A.x - B.y, A.y + B.x);
     };
+    for (int e = threadIdx.x; e < (npen * 3) << lgq; e += kNT) {
+        const int line = e >> lgq, t = e & ((1 << lgq) - 1);
+        const int p = line / 3, c = line - 3 * p;
+        const cx<R>* row = Y1 + x_row(g, mb, c, pen0 + p);
+        cx<R>* out = buf + line * Lh;
+        const cx<R> a = row[t], b = row[Lh - t];
+        if (t == 0) {
+            out[0] = split(a, b, mk<R>((R)1, (R)0));
+            if (Lh > 1) {
+                const cx<R> h = row[Lh >> 1];
+                out[Lh >> 1] = split(h, h, mk<R>((R)0, (R)1));     // conj(W^(Lh/2)) = i
+            }
+        } else {
+            const cx<R> wc = cconj<R>(tw_fwd<R>(t << twsh));
+            out[t] = split(a, b, wc);
+            out[Lh - t] = split(b, a, mk<R>(-wc.x, wc.y));         // conj(W^(Lh-t)) = -W^t
+        }
+    }
+    __syncthreads();
+    auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
     auto none_store = [&](int, int, cx<R>) {};
-    fft_io<R, true, pemax<BIG>(), false, true, kLines, 1, false, true>(buf, g.lgLh, 0, npen * 3, load, none_store);
+    fft_io<R, true, pemax<BIG>(), true, true, kLines, 1, false, true>(buf, g.lgLh, 0, npen * 3, none_load, none_store);
 }
 
 // Forward x pass: buf holds packed lines z[n] = x[2n] + i x[2n+1]; writes the
-// Hx-column half spectrum of every line to X1.
+// Hx-column half spectrum of every line to X1.  Merge step: with P = Z[k],
+// Q = Z[Lh-k], E = (P + Q*)/2, O = (P - Q*)/(2i) and T = W^k O,
+// X[k] = E + T and X[Lh-k] = (E - T)*.
 template <typename R, bool BIG>
 __device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int mb, int pen0, int npen) {
     const int Lh = g.Lh;
+    const int lgq = g.lgLh > 0 ? g.lgLh - 1 : 0;
     const int twsh = kTwLog - g.lgPx;
     auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
     auto none_store = [&](int, int, cx<R>) {};
     __syncthreads();
     fft_io<R, false, pemax<BIG>(), true, true, kLines, 1, true, false>(buf, g.lgLh, 0, npen * 3, none_load, none_store);
     const R half = (R)0.5;
-    for (int e = threadIdx.x; e < npen * 3 * g.Hx; e += kNT) {
-        const int line = fdiv(e, g.div_hx), k = e - line * g.Hx;
+    for (int e = threadIdx.x; e < (npen * 3) << lgq; e += kNT) {
+        const int line = e >> lgq, t = e & ((1 << lgq) - 1);
         const int p = line / 3, c = line - 3 * p;
-        int y, z;
-        pen_coords<R>(g, pen0 + p, y, z);
-        const cx<R> Zk = buf[line * Lh + (k & (Lh - 1))];
-        const cx<R> Zm = cconj<R>(buf[line * Lh + ((Lh - k) & (Lh - 1))]);
-        const cx<R> E = cscale<R>(cadd<R>(Zk, Zm), half);
-        const cx<R> D = csub<R>(Zk, Zm);
-        const cx<R> O = mk<R>(half * D.y, -half * D.x);       // (Zk - Zm) / (2i)
-        const cx<R> X = cadd<R>(E, cmul<R>(tw_fwd<R>(k << twsh), O));
-        X1[(((mb * 3 + c) * g.nz + z) * g.ny + y) * g.Sx + k] = X;
+        cx<R>* row = X1 + x_row(g, mb, c, pen0 + p);
+        const cx<R>* in = buf + line * Lh;
+        if (t == 0) {
+            const cx<R> P = in[0];
+            row[0] = mk<R>(P.x + P.y, (R)0);
+            row[Lh] = mk<R>(P.x - P.y, (R)0);
+            if (Lh > 1) row[Lh >> 1] = cconj<R>(in[Lh >> 1]);   // W^(Lh/2) = -i
+        } else {
+            const cx<R> P = in[t], Q = in[Lh - t];
+            const cx<R> E = mk<R>(half * (P.x + Q.x), half * (P.y - Q.y));
+            const cx<R> O = mk<R>(half * (P.y + Q.y), half * (Q.x - P.x));
+            const cx<R> T = cmul<R>(tw_fwd<R>(t << twsh), O);
+            row[t] = cadd<R>(E, T);
+            row[Lh - t] = mk<R>(E.x - T.x, T.y - E.y);
+        }
     }
 }
 
