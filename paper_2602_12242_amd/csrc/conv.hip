@@ -445,6 +445,8 @@ static inline bool em_big(long long elements) { return elements > (long long)kNT
 // (occupancy of this kernel at this LDS size, times the CU count), at most
 // one per tile.  Cached per device, kernel and LDS size.
 static int persistent_grid(const void* kernel, size_t lds, long long ntiles, int nt = kNT) {
+    if (lds > 65536 && hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return -1;
     static std::mutex mu;
     static std::map<std::tuple<int, const void*, size_t>, int> cache;
     int dev = 0;
@@ -517,15 +519,20 @@ static bool y_wide(const Plan& pl) {
     return nt != 256;
 }
 
+// Tiles of more than 256 x 32 elements (beyond 64 KiB of LDS): 512 threads of 32.
+static bool y_huge(const Plan& pl) { return (long long)pl.Py * pl.ty > (long long)kNT * 32; }
+
 template <typename R>
 hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
     if (!em_big((long long)pl.Py * pl.ty)) return run_yfwd<R, 16, kNT>(pl, X1, X2, s);
+    if (y_huge(pl)) return run_yfwd<R, 32, 512>(pl, X1, X2, s);
     return y_wide(pl) ? run_yfwd<R, 16, 512>(pl, X1, X2, s) : run_yfwd<R, 32, kNT>(pl, X1, X2, s);
 }
 
 template <typename R>
 hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
     if (!em_big((long long)pl.Py * pl.ty)) return run_yinv<R, 16, kNT>(pl, X2, Y1, s);
+    if (y_huge(pl)) return run_yinv<R, 32, 512>(pl, X2, Y1, s);
     return y_wide(pl) ? run_yinv<R, 16, 512>(pl, X2, Y1, s) : run_yinv<R, 32, kNT>(pl, X2, Y1, s);
 }
 

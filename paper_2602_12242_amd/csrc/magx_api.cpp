@@ -105,11 +105,14 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
         return MAGX_ESIZE;
     p.ncell = (long long)p.nx * p.ny * p.nz;
     if (3LL * nbatch * p.ncell >= (1LL << 31) || nbatch > 65535) return MAGX_ESIZE;
-    p.ty = std::min(16, pow2_floor(lds_cplx / p.Py));
+    // y tile: Py*ty complex in LDS; single precision takes up to 128 KiB (one
+    // block of 512 threads per CU, 16 columns = whole 128-byte row segments)
+    const int y_cplx = dt == MAGX_F32 ? 2 * lds_cplx : lds_cplx;
+    p.ty = std::min(16, pow2_floor(y_cplx / p.Py));
     // tuning override of the y tile width (power of two within the LDS budget)
     if (const char* e = std::getenv("MAGX_TILE_Y")) {
         const int t = std::atoi(e);
-        if (t >= 1 && (t & (t - 1)) == 0 && (long long)t * p.Py <= lds_cplx) p.ty = t;
+        if (t >= 1 && (t & (t - 1)) == 0 && (long long)t * p.Py <= y_cplx) p.ty = t;
     }
     // z tile: data 3*Pz*tz complex in LDS (at most 64 KiB), at most 16 FFT
     // elements per thread when possible (32 at most), and at most 4 tensor

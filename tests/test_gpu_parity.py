@@ -49,6 +49,12 @@ CASES = {
                    Hbias=(1e3, -2e3, 5e3), terms=ALL)),
     "slab17": ((24, 5, 17), (2.5e-9, 2e-9, 1.5e-9),
                dict(Ms=8e5, A=1.3e-11, alpha=0.2, Hbias=(0, 3e3, 1e4), terms=1 | 2 | 16)),
+    # Py = 1024 and 4096: in single precision the y tiles of 128 KiB (512
+    # threads, 16 and 4 columns, three passes for 4096)
+    "long_y": ((5, 300, 2), (2e-9, 2e-9, 2e-9),
+               dict(Ms=8e5, A=1.3e-11, D=1e-3, alpha=0.1, Hbias=(0, 1e4, 0), terms=1 | 2 | 4 | 16)),
+    "longest_y": ((3, 1100, 2), (2e-9, 1e-9, 2e-9),
+                  dict(Ms=8e5, A=1.3e-11, alpha=0.1, terms=1 | 2)),
     # Pz = 1024: the longest z transform, one column per z tile
     "tall": ((3, 2, 300), (2e-9, 2e-9, 1e-9),
              dict(Ms=8e5, A=1.3e-11, alpha=0.1, Hbias=(0, 0, 1e4), terms=1 | 2 | 16)),
@@ -145,7 +151,7 @@ def test_llg_rhs_matches_oracle(dtype):
     assert _err(k.cpu().numpy(), ref) <= (1e-14 if dtype == 1 else 1e-6)
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "film", "line", "cell", "tiles", "thick"])
+@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "film", "line", "cell", "tiles", "thick", "long_y"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_one_rk4_step_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
