@@ -29,6 +29,31 @@ struct PG {
 inline size_t pencil_lds(const Plan& pl) { return (size_t)3 * pl.np * pl.Lh * pl.esize * 2; }
 inline bool pencil_big(const Plan& pl) { return pl.np * pl.Lh > 1024; }
 
+// Compile-time line geometry: for a power-of-two line nx = Lh = 2^LG (so
+// Px = 2 nx, Hx = Lh + 1, Sx = Lh + 16) the kernels are instantiated with the
+// sizes as constants, which turns the FFT strides and row offsets into
+// immediates; LG = 0 keeps them runtime values.
+constexpr int kPencilLgMin = 7, kPencilLgMax = 10;
+
+inline int pencil_lg(const Plan& pl) {
+    if (pl.nx != pl.Lh || pl.lgLh < kPencilLgMin || pl.lgLh > kPencilLgMax || pl.Sx != pl.Lh + 16 ||
+        pl.np * pl.Lh > 1024)
+        return 0;
+    return pl.lgLh;
+}
+
+template <int LG>
+__device__ __forceinline__ void pg_fix(PG& g) {
+    if constexpr (LG > 0) {
+        g.lgLh = LG;
+        g.Lh = 1 << LG;
+        g.lgPx = LG + 1;
+        g.nx = 1 << LG;
+        g.Hx = (1 << LG) + 1;
+        g.Sx = (1 << LG) + 16;
+    }
+}
+
 inline PG make_pg(const Plan& pl) {
     PG g;
     g.nx = pl.nx; g.ny = pl.ny; g.nz = pl.nz;

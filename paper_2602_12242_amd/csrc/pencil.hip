@@ -25,9 +25,10 @@ namespace magx {
 
 // ---- kernels -------------------------------------------------------------------
 
-template <typename R, bool BIG>
+template <typename R, bool BIG, int LG>
 __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R>* __restrict__ X1, PG g,
                                                    const R* __restrict__ msp) {
+    pg_fix<LG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     // logical block -> member mb and its first pencil; members own contiguous block ranges
@@ -60,11 +61,12 @@ __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R
 }
 
 // mode: 0 -> write H (with bias if with_bias); 1 -> energy partials (m.H_term)
-template <typename R, bool BIG>
+template <typename R, bool BIG, int LG>
 __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1, const R* __restrict__ f,
                                                     R* __restrict__ H, PG g, Phys<R> ph, int has_demag,
                                                     int with_bias, int energy, int sum_input,
                                                     double* __restrict__ partials) {
+    pg_fix<LG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
@@ -137,9 +139,10 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
     }
 }
 
-template <typename R, bool BIG>
+template <typename R, bool BIG, int LG>
 __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, PG g,
                                                     Phys<R> ph, StageArgs<R> a, int has_demag) {
+    pg_fix<LG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     // logical block -> member mb and its first pencil; members own contiguous block ranges
@@ -256,9 +259,10 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
     r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 
-template <typename R, bool BIG>
+template <typename R, bool BIG, int LG>
 __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG g, Phys<R> ph, StartArgs<R> a,
                                                      int has_demag, double* __restrict__ partials) {
+    pg_fix<LG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
@@ -347,10 +351,11 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
     r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 
-template <typename R, bool BIG>
+template <typename R, bool BIG, int LG>
 __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1, PG g,
                                                      Phys<R> ph, BackArgs<R> a, int has_demag,
                                                      double* __restrict__ partials) {
+    pg_fix<LG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
@@ -549,12 +554,28 @@ __global__ void copy_kernel(const R* __restrict__ src, R* __restrict__ dst, long
 
 // ---- launchers -----------------------------------------------------------------
 
+// Pencil kernel launch: the power-of-two line lengths 2^7 ... 2^10 with
+// compile-time geometry, every other size with runtime geometry.
+#define MAGX_PENCIL_LAUNCH(KERNEL, ...)                                                                 \
+    do {                                                                                                \
+        const dim3 grid_((unsigned)pl.pencil_blocks), block_(kNT);                                      \
+        const size_t lds_ = pencil_lds(pl);                                                             \
+        switch (pencil_lg(pl)) {                                                                        \
+            case 7: hipLaunchKernelGGL((KERNEL<R, false, 7>), grid_, block_, lds_, s, __VA_ARGS__); break;  \
+            case 8: hipLaunchKernelGGL((KERNEL<R, false, 8>), grid_, block_, lds_, s, __VA_ARGS__); break;  \
+            case 9: hipLaunchKernelGGL((KERNEL<R, false, 9>), grid_, block_, lds_, s, __VA_ARGS__); break;  \
+            case 10: hipLaunchKernelGGL((KERNEL<R, false, 10>), grid_, block_, lds_, s, __VA_ARGS__); break; \
+            default:                                                                                    \
+                if (pencil_big(pl))                                                                     \
+                    hipLaunchKernelGGL((KERNEL<R, true, 0>), grid_, block_, lds_, s, __VA_ARGS__);      \
+                else                                                                                    \
+                    hipLaunchKernelGGL((KERNEL<R, false, 0>), grid_, block_, lds_, s, __VA_ARGS__);     \
+        }                                                                                               \
+    } while (0)
+
 template <typename R>
 hipError_t launch_xfwd(const Plan& pl, const R* f, void* X1, const R* msp, hipStream_t s) {
-    if (pencil_big(pl)) hipLaunchKernelGGL((xfwd_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s, f,
-                       static_cast<cx<R>*>(X1), make_pg(pl), msp);
-    else hipLaunchKernelGGL((xfwd_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s, f,
-                       static_cast<cx<R>*>(X1), make_pg(pl), msp);
+    MAGX_PENCIL_LAUNCH(xfwd_kernel, f, static_cast<cx<R>*>(X1), make_pg(pl), msp);
     return hipGetLastError();
 }
 
@@ -562,12 +583,7 @@ template <typename R>
 hipError_t launch_field(const Plan& pl, const Phys<R>& ph, const void* Y1, const R* f, R* H, int with_bias,
                         int energy, int sum_input, double* partials, hipStream_t s) {
     const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
-    if (pencil_big(pl)) hipLaunchKernelGGL((field_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
-                       static_cast<const cx<R>*>(Y1), f, H, make_pg(pl), ph, has_demag, with_bias, energy,
-                       sum_input, partials);
-    else hipLaunchKernelGGL((field_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
-                       static_cast<const cx<R>*>(Y1), f, H, make_pg(pl), ph, has_demag, with_bias, energy,
-                       sum_input, partials);
+    MAGX_PENCIL_LAUNCH(field_kernel, static_cast<const cx<R>*>(Y1), f, H, make_pg(pl), ph, has_demag, with_bias, energy, sum_input, partials);
     return hipGetLastError();
 }
 
@@ -575,10 +591,7 @@ template <typename R>
 hipError_t launch_stage(const Plan& pl, const Phys<R>& ph, const void* Y1, void* X1, const StageArgs<R>& a,
                         hipStream_t s) {
     const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
-    if (pencil_big(pl)) hipLaunchKernelGGL((stage_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
-                       static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag);
-    else hipLaunchKernelGGL((stage_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
-                       static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag);
+    MAGX_PENCIL_LAUNCH(stage_kernel, static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag);
     return hipGetLastError();
 }
 
@@ -586,10 +599,7 @@ template <typename R>
 hipError_t launch_bstart(const Plan& pl, const Phys<R>& ph, void* X1, const StartArgs<R>& a, double* partials,
                          hipStream_t s) {
     const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
-    if (pencil_big(pl)) hipLaunchKernelGGL((bstart_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
-                       static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag, partials);
-    else hipLaunchKernelGGL((bstart_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
-                       static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag, partials);
+    MAGX_PENCIL_LAUNCH(bstart_kernel, static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag, partials);
     return hipGetLastError();
 }
 
@@ -597,12 +607,7 @@ template <typename R>
 hipError_t launch_bstage(const Plan& pl, const Phys<R>& ph, const void* Y1, void* X1, const BackArgs<R>& a,
                          double* partials, hipStream_t s) {
     const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
-    if (pencil_big(pl)) hipLaunchKernelGGL((bstage_kernel<R, true>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
-                       static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag,
-                       partials);
-    else hipLaunchKernelGGL((bstage_kernel<R, false>), dim3(pl.pencil_blocks), dim3(kNT), pencil_lds(pl), s,
-                       static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag,
-                       partials);
+    MAGX_PENCIL_LAUNCH(bstage_kernel, static_cast<const cx<R>*>(Y1), static_cast<cx<R>*>(X1), make_pg(pl), ph, a, has_demag, partials);
     return hipGetLastError();
 }
 

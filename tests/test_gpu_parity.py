@@ -55,6 +55,13 @@ CASES = {
                dict(Ms=8e5, A=1.3e-11, D=1e-3, alpha=0.1, Hbias=(0, 1e4, 0), terms=1 | 2 | 4 | 16)),
     "longest_y": ((3, 1100, 2), (2e-9, 1e-9, 2e-9),
                   dict(Ms=8e5, A=1.3e-11, alpha=0.1, terms=1 | 2)),
+    # power-of-two lines (nx = 256, 1024): pencil kernels with compile-time
+    # line geometry (as are the 128-cell film and the 512-cell workloads)
+    "pow2_256": ((256, 3, 2), (2e-9, 2e-9, 2e-9),
+                 dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, eK=(0, 0, 1), alpha=0.1, Hbias=(1e3, 0, 2e3),
+                      terms=ALL)),
+    "pow2_1024": ((1024, 2, 1), (2e-9, 2e-9, 2e-9),
+                  dict(Ms=8e5, A=1.3e-11, D=1e-3, alpha=0.05, Hbias=(0, 0, 1e4), terms=ALL)),
     # Pz = 1024: the longest z transform, one column per z tile
     "tall": ((3, 2, 300), (2e-9, 2e-9, 1e-9),
              dict(Ms=8e5, A=1.3e-11, alpha=0.1, Hbias=(0, 0, 1e4), terms=1 | 2 | 16)),
@@ -151,7 +158,8 @@ def test_llg_rhs_matches_oracle(dtype):
     assert _err(k.cpu().numpy(), ref) <= (1e-14 if dtype == 1 else 1e-6)
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "film", "line", "cell", "tiles", "thick", "long_y"])
+@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "film", "line", "cell", "tiles", "thick", "long_y",
+                                  "pow2_256", "pow2_1024"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_one_rk4_step_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -188,7 +196,7 @@ def test_several_steps_f64_and_norm(renorm):
         assert np.abs(np.sqrt(np.sum(out ** 2, axis=0)) - 1).max() < 1e-15
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "film", "tiles", "thick"])
+@pytest.mark.parametrize("name", ["tiny_all", "film", "tiles", "thick", "pow2_256"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_energy_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -204,7 +212,7 @@ def test_energy_matches_oracle(name, dtype):
     assert abs(e[5] - ref["total"]) <= (1e-11 if dtype == 1 else 2e-5) * scale
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick"])
+@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "pow2_256"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_heff_backward_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -220,7 +228,7 @@ def test_heff_backward_matches_oracle(name, dtype):
 
 
 @pytest.mark.parametrize("renorm", [0, 1, 2])
-@pytest.mark.parametrize("name", ["tiny_all", "tiles"])
+@pytest.mark.parametrize("name", ["tiny_all", "tiles", "pow2_256"])
 def test_step_backward_matches_oracle(name, renorm):
     n, d, mat = CASES[name]
     mat = dict(mat, renorm=renorm)
