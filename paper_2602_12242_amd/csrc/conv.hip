@@ -59,9 +59,28 @@ struct PairWalk {
     __device__ int tile(int u) const { return (u / ntxp) * ntx + 2 * (u % ntxp) + side; }
 };
 
-template <typename R, int EM, int NT>
+// Compile-time geometry of the y passes for square power-of-two grids in
+// single precision, nx = ny = 2^(LG-1) (Px = Py = 2^LG): every size of the
+// pass (row stride, tile width, tile count) becomes a constant, so the FFT
+// strides and row offsets are immediates.  LG = 0 keeps runtime sizes.
+constexpr int ytile_lg(int LG) { return LG >= 10 ? 14 - LG : 4; }   // ty = min(16, 2^14 / Py)
+
+template <int LG>
+__device__ __forceinline__ void ygeom_fix(int& ny, int& lgPy, int& Hx, int& Sx, int& lgT, int& ntx) {
+    if constexpr (LG > 0) {
+        ny = 1 << (LG - 1);
+        lgPy = LG;
+        Hx = (1 << (LG - 1)) + 1;
+        Sx = (1 << (LG - 1)) + 16;
+        lgT = ytile_lg(LG);
+        ntx = (Hx + (1 << lgT) - 1) >> lgT;
+    }
+}
+
+template <typename R, int EM, int NT, int LG>
 __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
                                                   int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
+    ygeom_fix<LG>(ny, lgPy, Hx, Sx, lgT, ntx);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
@@ -107,9 +126,10 @@ __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, 
     }
 }
 
-template <typename R, int EM, int NT>
+template <typename R, int EM, int NT, int LG>
 __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
                                                   int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
+    ygeom_fix<LG>(ny, lgPy, Hx, Sx, lgT, ntx);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
@@ -478,32 +498,32 @@ static int pair_grid(int resident, long long nunits) {
     return (int)g;
 }
 
-template <typename R, int EM, int NT>
+template <typename R, int EM, int NT, int LG = 0>
 static hipError_t run_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
     const int lgT = ilog2(pl.ty);
     const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
     const int ntiles = ntx * 3 * pl.nz * pl.nbatch;
     const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
-    const int grid = pair_grid(persistent_grid(reinterpret_cast<const void*>(&yfwd_kernel<R, EM, NT>), lds,
+    const int grid = pair_grid(persistent_grid(reinterpret_cast<const void*>(&yfwd_kernel<R, EM, NT, LG>), lds,
                                                1LL << 30, NT),
                                (long long)(ntiles / ntx) * ((ntx + 1) / 2));
     if (grid < 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((yfwd_kernel<R, EM, NT>), dim3(grid), dim3(NT), lds, s, static_cast<const cx<R>*>(X1),
+    hipLaunchKernelGGL((yfwd_kernel<R, EM, NT, LG>), dim3(grid), dim3(NT), lds, s, static_cast<const cx<R>*>(X1),
                        static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx, ntiles);
     return hipGetLastError();
 }
 
-template <typename R, int EM, int NT>
+template <typename R, int EM, int NT, int LG = 0>
 static hipError_t run_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
     const int lgT = ilog2(pl.ty);
     const int ntx = (pl.Hx + pl.ty - 1) / pl.ty;
     const int ntiles = ntx * 3 * pl.nz * pl.nbatch;
     const size_t lds = (size_t)pl.Py * pl.ty * sizeof(cx<R>);
-    const int grid = pair_grid(persistent_grid(reinterpret_cast<const void*>(&yinv_kernel<R, EM, NT>), lds,
+    const int grid = pair_grid(persistent_grid(reinterpret_cast<const void*>(&yinv_kernel<R, EM, NT, LG>), lds,
                                                1LL << 30, NT),
                                (long long)(ntiles / ntx) * ((ntx + 1) / 2));
     if (grid < 2) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((yinv_kernel<R, EM, NT>), dim3(grid), dim3(NT), lds, s, static_cast<const cx<R>*>(X2),
+    hipLaunchKernelGGL((yinv_kernel<R, EM, NT, LG>), dim3(grid), dim3(NT), lds, s, static_cast<const cx<R>*>(X2),
                        static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx, ntiles);
     return hipGetLastError();
 }
@@ -522,8 +542,25 @@ static bool y_wide(const Plan& pl) {
 // Tiles of more than 256 x 32 elements (beyond 64 KiB of LDS): 512 threads of 32.
 static bool y_huge(const Plan& pl) { return (long long)pl.Py * pl.ty > (long long)kNT * 32; }
 
+// LG of the compile-time y geometry that matches the plan, 0 if none.
+static int y_lg(const Plan& pl) {
+    if (pl.dtype != MAGX_F32 || pl.Px != pl.Py || 2 * pl.nx != pl.Px || 2 * pl.ny != pl.Py) return 0;
+    if (pl.lgPy < 8 || pl.lgPy > 11 || y_wide(pl)) return 0;
+    if (pl.ty != (1 << ytile_lg(pl.lgPy)) || pl.Sx != pl.Px / 2 + 16) return 0;
+    return pl.lgPy;
+}
+
 template <typename R>
 hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
+    if constexpr (std::is_same<R, float>::value) {
+        switch (y_lg(pl)) {
+            case 8: return run_yfwd<R, 16, kNT, 8>(pl, X1, X2, s);
+            case 9: return run_yfwd<R, 32, kNT, 9>(pl, X1, X2, s);
+            case 10: return run_yfwd<R, 32, 512, 10>(pl, X1, X2, s);
+            case 11: return run_yfwd<R, 32, 512, 11>(pl, X1, X2, s);
+            default: break;
+        }
+    }
     if (!em_big((long long)pl.Py * pl.ty)) return run_yfwd<R, 16, kNT>(pl, X1, X2, s);
     if (y_huge(pl)) return run_yfwd<R, 32, 512>(pl, X1, X2, s);
     return y_wide(pl) ? run_yfwd<R, 16, 512>(pl, X1, X2, s) : run_yfwd<R, 32, kNT>(pl, X1, X2, s);
@@ -531,6 +568,15 @@ hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) 
 
 template <typename R>
 hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
+    if constexpr (std::is_same<R, float>::value) {
+        switch (y_lg(pl)) {
+            case 8: return run_yinv<R, 16, kNT, 8>(pl, X2, Y1, s);
+            case 9: return run_yinv<R, 32, kNT, 9>(pl, X2, Y1, s);
+            case 10: return run_yinv<R, 32, 512, 10>(pl, X2, Y1, s);
+            case 11: return run_yinv<R, 32, 512, 11>(pl, X2, Y1, s);
+            default: break;
+        }
+    }
     if (!em_big((long long)pl.Py * pl.ty)) return run_yinv<R, 16, kNT>(pl, X2, Y1, s);
     if (y_huge(pl)) return run_yinv<R, 32, 512>(pl, X2, Y1, s);
     return y_wide(pl) ? run_yinv<R, 16, 512>(pl, X2, Y1, s) : run_yinv<R, 32, kNT>(pl, X2, Y1, s);

@@ -62,6 +62,10 @@ CASES = {
                       terms=ALL)),
     "pow2_1024": ((1024, 2, 1), (2e-9, 2e-9, 2e-9),
                   dict(Ms=8e5, A=1.3e-11, D=1e-3, alpha=0.05, Hbias=(0, 0, 1e4), terms=ALL)),
+    # square power-of-two plane (nx = ny = 128): y passes with compile-time
+    # geometry in single precision (as are the 256-, 512- and 1024-cell workloads)
+    "sq128": ((128, 128, 2), (2e-9, 2e-9, 2e-9),
+              dict(Ms=8e5, A=1.3e-11, D=1e-3, alpha=0.1, Hbias=(2e3, 0, 0), terms=ALL)),
     # Pz = 1024: the longest z transform, one column per z tile
     "tall": ((3, 2, 300), (2e-9, 2e-9, 1e-9),
              dict(Ms=8e5, A=1.3e-11, alpha=0.1, Hbias=(0, 0, 1e4), terms=1 | 2 | 16)),
