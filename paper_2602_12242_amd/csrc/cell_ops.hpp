@@ -114,7 +114,8 @@ __device__ __forceinline__ void load_pair(const R* __restrict__ f, long long N, 
             b[c] = v.y;
         } else {
             a[c] = p[0];
-            b[c] = two ? p[1] : (R)0;
+            const R v1 = p[two ? 1 : 0];   // unconditional load: no wait behind a branch
+            b[c] = two ? v1 : (R)0;
         }
     }
 }
@@ -158,7 +159,8 @@ __device__ __forceinline__ void load_s_pair(const R* __restrict__ s, long long i
         o[1] = v.y;
     } else {
         o[0] = s[id];
-        o[1] = two ? s[id + 1] : (R)0;
+        const R v1 = s[id + (two ? 1 : 0)];
+        o[1] = two ? v1 : (R)0;
     }
 }
 
@@ -189,48 +191,65 @@ __device__ __forceinline__ void local_field_pair(const R* __restrict__ f, const 
     if (ph.terms & (MAGX_EXCH | MAGX_DMI)) {
         const R kdx = ph.kap * ph.dx, kdy = ph.kap * ph.dy;
         R xl[3], xr[3], yp[2][3], ym[2][3], zp[2][3], zm[2][3];
-        // neighbour availability: in the grid and (with a profile) in the magnet
-        bool okxl = x0 > 0, okxr;
-        bool okyp[2], okym[2], okzp[2], okzm[2];
+        // Neighbour availability: in the grid and (with a profile) in the
+        // magnet.  Every neighbour is loaded, at the cell itself where it lies
+        // outside the grid (so the address is valid), and replaced by its ghost
+        // value afterwards: no load sits behind a branch, so all of them are in
+        // flight together.
         const int xr_off = two ? 2 : 1;
-        okxr = x0 + xr_off < g.nx;
         const long long pz = (long long)g.nx * g.ny;
+        const bool gxl = x0 > 0, gxr = x0 + xr_off < g.nx;
+        const bool gyp = y + 1 < g.ny, gym = y > 0, gzp = z + 1 < g.nz, gzm = z > 0;
+        const long long il = gxl ? id - 1 : id, ir = gxr ? id + xr_off : id;
+        const long long iyp = gyp ? id + g.nx : id, iym = gym ? id - g.nx : id;
+        const long long izp = gzp ? id + pz : id, izm = gzm ? id - pz : id;
+        R xlv[3], xrv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            xlv[c] = f[c * N + il];
+            xrv[c] = f[c * N + ir];
+        }
+        load_pair(f, N, iyp, vec, two, yp[0], yp[1]);
+        load_pair(f, N, iym, vec, two, ym[0], ym[1]);
+        load_pair(f, N, izp, vec, two, zp[0], zp[1]);
+        load_pair(f, N, izm, vec, two, zm[0], zm[1]);
+        bool okxl = gxl, okxr = gxr;
+        bool okyp[2], okym[2], okzp[2], okzm[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            okyp[q] = y + 1 < g.ny;
-            okym[q] = y > 0;
-            okzp[q] = z + 1 < g.nz;
-            okzm[q] = z > 0;
+            okyp[q] = gyp;
+            okym[q] = gym;
+            okzp[q] = gzp;
+            okzm[q] = gzm;
         }
         if (sp) {
-            if (okxl) okxl = sp[id - 1] > (R)0;
-            if (okxr) okxr = sp[id + xr_off] > (R)0;
-            R t[2];
-            if (y + 1 < g.ny) { load_s_pair(sp, id + g.nx, vec, two, t); okyp[0] = t[0] > (R)0; okyp[1] = t[1] > (R)0; }
-            if (y > 0) { load_s_pair(sp, id - g.nx, vec, two, t); okym[0] = t[0] > (R)0; okym[1] = t[1] > (R)0; }
-            if (z + 1 < g.nz) { load_s_pair(sp, id + pz, vec, two, t); okzp[0] = t[0] > (R)0; okzp[1] = t[1] > (R)0; }
-            if (z > 0) { load_s_pair(sp, id - pz, vec, two, t); okzm[0] = t[0] > (R)0; okzm[1] = t[1] > (R)0; }
+            const R sl = sp[il], sr = sp[ir];
+            R t0[2], t1[2], t2[2], t3[2];
+            load_s_pair(sp, iyp, vec, two, t0);
+            load_s_pair(sp, iym, vec, two, t1);
+            load_s_pair(sp, izp, vec, two, t2);
+            load_s_pair(sp, izm, vec, two, t3);
+            okxl = okxl && sl > (R)0;
+            okxr = okxr && sr > (R)0;
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                okyp[q] = okyp[q] && t0[q] > (R)0;
+                okym[q] = okym[q] && t1[q] > (R)0;
+                okzp[q] = okzp[q] && t2[q] > (R)0;
+                okzm[q] = okzm[q] && t3[q] > (R)0;
+            }
         }
         // outer x neighbours of the pair: cell x0 - 1 and cell x0 + 2 (or x0 + 1 if alone)
-        R last[3];
+        R last[3], gl[3], gr[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) last[c] = two ? m[1][c] : m[0][c];
-        if (okxl) {
+        ghost_xm<R>(m[0], kdx, gl);
+        ghost_xp<R>(last, kdx, gr);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) xl[c] = f[c * N + id - 1];
-        } else {
-            ghost_xm<R>(m[0], kdx, xl);
+        for (int c = 0; c < 3; ++c) {
+            xl[c] = okxl ? xlv[c] : gl[c];
+            xr[c] = okxr ? xrv[c] : gr[c];
         }
-        if (okxr) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) xr[c] = f[c * N + id + xr_off];
-        } else {
-            ghost_xp<R>(last, kdx, xr);
-        }
-        if (y + 1 < g.ny) load_pair(f, N, id + g.nx, vec, two, yp[0], yp[1]);
-        if (y > 0) load_pair(f, N, id - g.nx, vec, two, ym[0], ym[1]);
-        if (z + 1 < g.nz) load_pair(f, N, id + pz, vec, two, zp[0], zp[1]);
-        if (z > 0) load_pair(f, N, id - pz, vec, two, zm[0], zm[1]);
         // the two cells of the pair see each other unless one is outside the magnet
         const bool in0 = sw[0] > (R)0, in1 = sw[1] > (R)0;
 #pragma unroll
@@ -349,6 +368,10 @@ __device__ __forceinline__ void pen_coords(const PG& g, int pen, int& y, int& z)
     y = pen - z * g.ny;
 }
 
+// Split/merge items per thread and chunk (3 np Lh/2 <= 1536 items per block
+// for np Lh <= 1024).
+constexpr int kXIt = 6;
+
 // Row of X1/Y1 holding component c of pencil p (32-bit element offset: the
 // spectral arrays of a whole batch stay below 2^31 elements).
 __device__ __forceinline__ unsigned x_row(const PG& g, int mb, int c, int pen) {
@@ -379,22 +402,39 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int mb, int 
         const cx<R> B = cmul<R>(csub<R>(a, bc), wc);
         return mk<R>(A.x - B.y, A.y + B.x);
     };
-    for (int e = threadIdx.x; e < (npen * 3) << lgq; e += kNT) {
-        const int line = e >> lgq, t = e & ((1 << lgq) - 1);
-        const int p = line / 3, c = line - 3 * p;
-        const cx<R>* row = Y1 + x_row(g, mb, c, pen0 + p);
-        cx<R>* out = buf + line * Lh;
-        const cx<R> a = row[t], b = row[Lh - t];
-        if (t == 0) {
-            out[0] = split(a, b, mk<R>((R)1, (R)0));
-            if (Lh > 1) {
-                const cx<R> h = row[Lh >> 1];
-                out[Lh >> 1] = split(h, h, mk<R>((R)0, (R)1));     // conj(W^(Lh/2)) = i
+    // items in chunks of kXIt per thread: all loads of a chunk are issued
+    // before any is used (no load behind a branch or a loop-carried wait)
+    const int count = (npen * 3) << lgq;
+    for (int base = 0; base < count; base += kXIt * kNT) {
+        cx<R> A[kXIt], B[kXIt], C[kXIt], W[kXIt];
+        const int wave0 = base + ((int)threadIdx.x & ~63);
+#pragma unroll
+        for (int i = 0; i < kXIt; ++i) {
+            const int e = min(base + (int)threadIdx.x + i * kNT, count - 1);
+            const int line = e >> lgq, t = e & ((1 << lgq) - 1);
+            const int p = line / 3, c = line - 3 * p;
+            const cx<R>* row = Y1 + x_row(g, mb, c, pen0 + p);
+            A[i] = row[t];
+            B[i] = row[Lh - t];
+            W[i] = tw_fwd<R>(t << twsh);
+            C[i] = mk<R>((R)0, (R)0);
+            // X[Lh/2] for item 0 of a line, loaded only by waves holding such an item
+            if (lgq < 6 || ((wave0 + i * kNT) & ((1 << lgq) - 1)) == 0) C[i] = row[t == 0 ? (Lh >> 1) : t];
+        }
+#pragma unroll
+        for (int i = 0; i < kXIt; ++i) {
+            const int e = base + (int)threadIdx.x + i * kNT;
+            if (e >= count) break;
+            const int line = e >> lgq, t = e & ((1 << lgq) - 1);
+            cx<R>* out = buf + line * Lh;
+            if (t == 0) {
+                out[0] = split(A[i], B[i], mk<R>((R)1, (R)0));
+                if (Lh > 1) out[Lh >> 1] = split(C[i], C[i], mk<R>((R)0, (R)1));   // conj(W^(Lh/2)) = i
+            } else {
+                const cx<R> wc = cconj<R>(W[i]);
+                out[t] = split(A[i], B[i], wc);
+                out[Lh - t] = split(B[i], A[i], mk<R>(-wc.x, wc.y));            // conj(W^(Lh-t)) = -W^t
             }
-        } else {
-            const cx<R> wc = cconj<R>(tw_fwd<R>(t << twsh));
-            out[t] = split(a, b, wc);
-            out[Lh - t] = split(b, a, mk<R>(-wc.x, wc.y));         // conj(W^(Lh-t)) = -W^t
         }
     }
     __syncthreads();
@@ -417,23 +457,35 @@ __device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int mb, int pen0, 
     __syncthreads();
     fft_io<R, false, pemax<BIG>(), true, true, kLines, 1, true, false>(buf, g.lgLh, 0, npen * 3, none_load, none_store);
     const R half = (R)0.5;
-    for (int e = threadIdx.x; e < (npen * 3) << lgq; e += kNT) {
-        const int line = e >> lgq, t = e & ((1 << lgq) - 1);
-        const int p = line / 3, c = line - 3 * p;
-        cx<R>* row = X1 + x_row(g, mb, c, pen0 + p);
-        const cx<R>* in = buf + line * Lh;
-        if (t == 0) {
-            const cx<R> P = in[0];
-            row[0] = mk<R>(P.x + P.y, (R)0);
-            row[Lh] = mk<R>(P.x - P.y, (R)0);
-            if (Lh > 1) row[Lh >> 1] = cconj<R>(in[Lh >> 1]);   // W^(Lh/2) = -i
-        } else {
-            const cx<R> P = in[t], Q = in[Lh - t];
-            const cx<R> E = mk<R>(half * (P.x + Q.x), half * (P.y - Q.y));
-            const cx<R> O = mk<R>(half * (P.y + Q.y), half * (Q.x - P.x));
-            const cx<R> T = cmul<R>(tw_fwd<R>(t << twsh), O);
-            row[t] = cadd<R>(E, T);
-            row[Lh - t] = mk<R>(E.x - T.x, T.y - E.y);
+    const int count = (npen * 3) << lgq;
+    for (int base = 0; base < count; base += kXIt * kNT) {
+        cx<R> W[kXIt];
+#pragma unroll
+        for (int i = 0; i < kXIt; ++i) {
+            const int e = min(base + (int)threadIdx.x + i * kNT, count - 1);
+            W[i] = tw_fwd<R>((e & ((1 << lgq) - 1)) << twsh);
+        }
+#pragma unroll
+        for (int i = 0; i < kXIt; ++i) {
+            const int e = base + (int)threadIdx.x + i * kNT;
+            if (e >= count) break;
+            const int line = e >> lgq, t = e & ((1 << lgq) - 1);
+            const int p = line / 3, c = line - 3 * p;
+            cx<R>* row = X1 + x_row(g, mb, c, pen0 + p);
+            const cx<R>* in = buf + line * Lh;
+            if (t == 0) {
+                const cx<R> P = in[0];
+                row[0] = mk<R>(P.x + P.y, (R)0);
+                row[Lh] = mk<R>(P.x - P.y, (R)0);
+                if (Lh > 1) row[Lh >> 1] = cconj<R>(in[Lh >> 1]);   // W^(Lh/2) = -i
+            } else {
+                const cx<R> P = in[t], Q = in[Lh - t];
+                const cx<R> E = mk<R>(half * (P.x + Q.x), half * (P.y - Q.y));
+                const cx<R> O = mk<R>(half * (P.y + Q.y), half * (Q.x - P.x));
+                const cx<R> T = cmul<R>(W[i], O);
+                row[t] = cadd<R>(E, T);
+                row[Lh - t] = mk<R>(E.x - T.x, T.y - E.y);
+            }
         }
     }
 }

@@ -192,6 +192,12 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
         const long long id = ((long long)z * g.ny + y) * g.nx + x0;
+        // RK4 registers first, so their loads are in flight with the stencil's
+        R k[2][3], mn[2][3], acc[2][3], xn[2][3], nrm[2];
+        if (s > 1) {
+            load_pair(a.mn, g.N, id, vec, two, mn[0], mn[1]);
+            load_pair(a.acc, g.N, id, vec, two, acc[0], acc[1]);
+        }
         R ys[2][3], H[2][3], ex[2], dm[2], an[2], sw[2];
         local_field_pair<R>(a.yin, g, x0, y, z, vec, two, ph, ys, H, ex, dm, an, false, sw);
 #pragma unroll
@@ -206,7 +212,6 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
         }
         if (a.tapeH) store_pair(a.tapeH, g.N, id, vec, two, H[0], H[1]);
         if (a.tapeYin) store_pair(a.tapeYin, g.N, id, vec, two, ys[0], ys[1]);
-        R k[2][3], mn[2][3], acc[2][3], xn[2][3], nrm[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) llg_rhs<R>(ys[q], H[q], ph.a, ph.alpha, k[q]);
         if (s <= 1) {
@@ -214,10 +219,7 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
             for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) mn[q][c] = ys[q][c];
-        } else {
-            load_pair(a.mn, g.N, id, vec, two, mn[0], mn[1]);
         }
-        if (s > 1) load_pair(a.acc, g.N, id, vec, two, acc[0], acc[1]);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
 #pragma unroll
