@@ -217,7 +217,7 @@ def pmc_summarize(fetch_csv, write_csv, command):
     total = 0.0
     for label, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
         rows = _pmc_rows(path, counter)
-        copy = [v * 1024.0 for k, v in rows if "copy_kernel" in k]
+        copy = [v * 1024.0 for k, v in rows if "magx::copy_kernel" in k]
         dom = [v * 1024.0 for k, v in rows if re.search(r"magx::" + DOMINANT + r"\w*_kernel", k)]
         if not copy or not dom:
             raise SystemExit(f"{path}: no {counter} rows for copy_kernel / {DOMINANT}_kernel")
