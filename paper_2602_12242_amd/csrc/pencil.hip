@@ -312,7 +312,8 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
             load_pair(a.y5, g.N, id, vec, two, y5[0], y5[1]);
             R nx5[2];
             nx5[0] = a.nx5[id];
-            nx5[1] = two ? a.nx5[id + 1] : (R)1;
+            const R n1 = a.nx5[id + (two ? 1 : 0)];
+            nx5[1] = two ? n1 : (R)1;
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
                 const R pl = dot3(y5[q], lam[q]);
@@ -435,7 +436,8 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
             if (norm) {
                 R nxs[2];
                 nxs[0] = a.nxs[id];
-                nxs[1] = two ? a.nxs[id + 1] : (R)1;
+                const R n1 = a.nxs[id + (two ? 1 : 0)];
+                nxs[1] = two ? n1 : (R)1;
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
                     const R py = dot3(ys[q], yb[q]);
