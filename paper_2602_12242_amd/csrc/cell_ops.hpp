@@ -402,6 +402,7 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int mb, int 
         const cx<R> B = cmul<R>(csub<R>(a, bc), wc);
         return mk<R>(A.x - B.y, A.y + B.x);
     };
+    tw_lds_fill<R>();   // pass twiddles, read after the barrier below
     // items in chunks of kXIt per thread: all loads of a chunk are issued
     // before any is used (no load behind a branch or a loop-carried wait)
     const int count = (npen * 3) << lgq;
@@ -440,7 +441,8 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int mb, int 
     __syncthreads();
     auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
     auto none_store = [&](int, int, cx<R>) {};
-    fft_io<R, true, pemax<BIG>(), true, true, kLines, 1, false, true>(buf, g.lgLh, 0, npen * 3, none_load, none_store);
+    fft_io<R, true, pemax<BIG>(), true, true, kLines, 1, false, true, lgmax<pemax<BIG>()>(), kNT, true>(
+        buf, g.lgLh, 0, npen * 3, none_load, none_store);
 }
 
 // Forward x pass: buf holds packed lines z[n] = x[2n] + i x[2n+1]; writes the
@@ -454,8 +456,10 @@ __device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int mb, int pen0, 
     const int twsh = kTwLog - g.lgPx;
     auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
     auto none_store = [&](int, int, cx<R>) {};
+    tw_lds_fill<R>();   // pass twiddles (same values if c2r_lines filled them)
     __syncthreads();
-    fft_io<R, false, pemax<BIG>(), true, true, kLines, 1, true, false>(buf, g.lgLh, 0, npen * 3, none_load, none_store);
+    fft_io<R, false, pemax<BIG>(), true, true, kLines, 1, true, false, lgmax<pemax<BIG>()>(), kNT, true>(
+        buf, g.lgLh, 0, npen * 3, none_load, none_store);
     const R half = (R)0.5;
     const int count = (npen * 3) << lgq;
     for (int base = 0; base < count; base += kXIt * kNT) {

@@ -81,6 +81,7 @@ template <typename R, int EM, int NT, int LG>
 __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
                                                   int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
     ygeom_fix<LG>(ny, lgPy, Hx, Sx, lgT, ntx);
+    tw_lds_fill<R>();   // read by the second pass, after the first barrier
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
@@ -120,7 +121,7 @@ __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, 
             if (un < pw.u1)
                 first_load<R, EM, kCols, 1, true, lgmax<EM>(), NT>(in, lgPy, lgT, T, loader(pw.tile(un)));
         };
-        fft_reg<R, false, EM, false, kCols, 1, true, false, lgmax<EM>(), NT>(buf, lgPy, lgT, T, in, next, store);
+        fft_reg<R, false, EM, false, kCols, 1, true, false, lgmax<EM>(), NT, true>(buf, lgPy, lgT, T, in, next, store);
         __syncthreads();   // the last pass read LDS; the next tile's first pass writes it
         u = un;
     }
@@ -130,6 +131,7 @@ template <typename R, int EM, int NT, int LG>
 __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
                                                   int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
     ygeom_fix<LG>(ny, lgPy, Hx, Sx, lgT, ntx);
+    tw_lds_fill<R>();   // read by the second pass, after the first barrier
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
@@ -165,7 +167,7 @@ __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, 
             if (un < pw.u1)
                 first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(in, lgPy, lgT, T, loader(pw.tile(un)));
         };
-        fft_reg<R, true, EM, false, kCols, 1, false, true, lgmax<EM>(), NT>(buf, lgPy, lgT, T, in, next, store);
+        fft_reg<R, true, EM, false, kCols, 1, false, true, lgmax<EM>(), NT, true>(buf, lgPy, lgT, T, in, next, store);
         __syncthreads();
         u = un;
     }
@@ -187,6 +189,7 @@ template <typename R, int EM>
 __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
                                                     int nz, int lgPz, int Py, int Hx, int Hz, int Sx, int lgT,
                                                     int ntx, int units_per_member, int nunits) {
+    tw_lds_fill<R>();   // read from the second pass on, after the first barrier
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
@@ -272,7 +275,7 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
         auto next = [&]() {
             if (t + 1 < t1) first_load<R, EM, kCols, 3, true, 3>(in, lgPz, lgT, T3, loader(t + 1));
         };
-        fft_reg<R, false, EM, true, kCols, 3, true, false, 3>(buf, lgPz, lgT, T3, in, next, none_store);
+        fft_reg<R, false, EM, true, kCols, 3, true, false, 3, kNT, true>(buf, lgPz, lgT, T3, in, next, none_store);
         // 3x3 symmetric product with the real spectrum: H_a = -Ms sum_b N_ab M_b.
         // Item (kzo, col) serves kz = kzo and its mirror Pz - kzo, where the
         // components odd in z (xz, yz) change sign.
@@ -301,7 +304,7 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
         }
         if (t + 1 < t1) tensor_load(t + 1);
         __syncthreads();
-        fft_io<R, true, EM, true, false, kCols, 3, false, true, 3>(buf, lgPz, lgT, T3, none_load, store);
+        fft_io<R, true, EM, true, false, kCols, 3, false, true, 3, kNT, true>(buf, lgPz, lgT, T3, none_load, store);
         __syncthreads();   // LDS is rewritten by the next tile
     }
 }

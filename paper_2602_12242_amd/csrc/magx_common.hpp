@@ -48,6 +48,29 @@ template <typename R, bool INV> __device__ __forceinline__ cx<R> tw(int k) {
     return INV ? cconj<R>(w) : w;
 }
 
+// Two-level copy of the twiddle table in LDS for the FFT passes of a block:
+// W^k = W^(64 (k >> 6)) W^(k & 63) (W = exp(-2 pi i / 4096)), 128 entries.
+// A pass twiddle then costs two LDS reads and a complex product instead of a
+// global (L2) load.  Every kernel that asks the passes for it (TWL) fills it
+// with tw_lds_fill before its first barrier.
+template <typename R> __device__ __forceinline__ cx<R>* tw_lds() {
+    __shared__ cx<R> t[128];
+    return t;
+}
+template <typename R> __device__ __forceinline__ void tw_lds_fill() {
+    cx<R>* t = tw_lds<R>();
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) t[i] = tw_fwd<R>(i < 64 ? i : (i - 64) << 6);
+}
+template <typename R, bool INV, bool TWL> __device__ __forceinline__ cx<R> tw_pass(int k) {
+    if constexpr (TWL) {
+        const cx<R>* t = tw_lds<R>();
+        const cx<R> w = cmul<R>(t[64 + (k >> 6)], t[k & 63]);
+        return INV ? cconj<R>(w) : w;
+    } else {
+        return tw<R, INV>(k);
+    }
+}
+
 // ---- small DFTs in registers --------------------------------------------------
 template <typename R, bool INV> __device__ __forceinline__ void dft2(cx<R>* v) {
     cx<R> a = v[0], b = v[1];
@@ -221,12 +244,12 @@ __device__ __forceinline__ int tid_opaque() {
 // v[r] *= w^(r k), r = 1..RAD-1, for the pass twiddle w: w^k, w^2k, w^4k, ...
 // come from the table and every other power is a product of those (at most
 // log2(RAD) - 1 products deep).
-template <typename R, bool INV, int RAD>
+template <typename R, bool INV, int RAD, bool TWL = false>
 __device__ __forceinline__ void twiddle_apply(cx<R>* v, int k, int twshift) {
     if (!k) return;
     cx<R> w[RAD];
 #pragma unroll
-    for (int p = 1; p < RAD; p <<= 1) w[p] = tw<R, INV>((p * k) << twshift);
+    for (int p = 1; p < RAD; p <<= 1) w[p] = tw_pass<R, INV, TWL>((p * k) << twshift);
 #pragma unroll
     for (int r = 3; r < RAD; ++r) {
         if ((r & (r - 1)) == 0) continue;
@@ -269,7 +292,7 @@ struct FirstIn {
 };
 
 template <typename R, int RAD, bool INV, int EMAX, int SRC, bool DST_LDS, int LAYOUT, int NC, bool HIN,
-          bool HOUT, int NT, class Load, class Store, class In>
+          bool HOUT, int NT, bool TWL, class Load, class Store, class In>
 __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lgL, int lgNs, int lgT, int nseq,
                                                  Load& load, Store& store, In& in) {
     constexpr bool SRC_LDS = SRC == kSrcLds;
@@ -311,7 +334,7 @@ __device__ __forceinline__ void stockham_io_pass(cx<R>* __restrict__ buf, int lg
             const unsigned k = j & (Ns - 1u);
             pos0[i] = ((j >> lgNs) << (lgNs + LGR)) + k;
             obase[i] = LAYOUT == kLines ? (b << lgL) + pos0[i] : b + umul24(pos0[i], (unsigned)nseq);
-            twiddle_apply<R, INV, RAD>(v[i], (int)k, twshift);
+            twiddle_apply<R, INV, RAD, TWL>(v[i], (int)k, twshift);
             dft<R, RAD, INV>(v[i]);
         }
     }
@@ -348,7 +371,7 @@ template <int EMAX> constexpr int lgmax() { return EMAX >= 32 ? 5 : (EMAX >= 16 
     }
 
 template <typename R, bool INV, int EMAX, bool SRC_LDS, bool DST_LDS, int LAYOUT, int NC, bool HALF_IN = false,
-          bool HALF_OUT = false, int LGM = lgmax<EMAX>(), int NT = kNT, class Load, class Store>
+          bool HALF_OUT = false, int LGM = lgmax<EMAX>(), int NT = kNT, bool TWL = false, class Load, class Store>
 __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT, int nseq, Load load, Store store) {
     if (lgL == 0) {   // length 1: the transform is the identity
         for (int b = threadIdx.x; b < nseq; b += NT) {
@@ -372,10 +395,10 @@ __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT
         const bool last = left == g;
 #define MAGX_BODY(RADIX)                                                                                          \
     if (last)                                                                                                     \
-        stockham_io_pass<R, RADIX, INV, EMAX, SRC_LDS ? kSrcLds : kSrcFn, DST_LDS, LAYOUT, NC, HALF_IN, HALF_OUT, NT>(  \
+        stockham_io_pass<R, RADIX, INV, EMAX, SRC_LDS ? kSrcLds : kSrcFn, DST_LDS, LAYOUT, NC, HALF_IN, HALF_OUT, NT, TWL>(  \
             buf, lgL, lgNs, lgT, nseq, load, store, noin);                                                        \
     else                                                                                                          \
-        stockham_io_pass<R, RADIX, INV, EMAX, SRC_LDS ? kSrcLds : kSrcFn, true, LAYOUT, NC, HALF_IN, false, NT>(      \
+        stockham_io_pass<R, RADIX, INV, EMAX, SRC_LDS ? kSrcLds : kSrcFn, true, LAYOUT, NC, HALF_IN, false, NT, TWL>(      \
             buf, lgL, lgNs, lgT, nseq, load, store, noin);
         MAGX_RADIX_SWITCH(g, LGM)
 #undef MAGX_BODY
@@ -385,10 +408,10 @@ __device__ __forceinline__ void fft_io(cx<R>* __restrict__ buf, int lgL, int lgT
     while (left > 0) {
         constexpr int RADIX = 1 << LGM;
         if (left == LGM)
-            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, DST_LDS, LAYOUT, NC, false, HALF_OUT, NT>(
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, DST_LDS, LAYOUT, NC, false, HALF_OUT, NT, TWL>(
                 buf, lgL, lgNs, lgT, nseq, load, store, noin);
         else
-            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, true, LAYOUT, NC, false, false, NT>(
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, true, LAYOUT, NC, false, false, NT, TWL>(
                 buf, lgL, lgNs, lgT, nseq, load, store, noin);
         lgNs += LGM;
         left -= LGM;
@@ -431,7 +454,7 @@ __device__ __forceinline__ void first_load(FirstIn<R, EMAX, HIN>& in, int lgL, i
 // after_first() runs once the first pass has consumed them, typically to
 // issue the next tile's first_load.  Requires lgL >= 1.
 template <typename R, bool INV, int EMAX, bool DST_LDS, int LAYOUT, int NC, bool HALF_IN, bool HALF_OUT,
-          int LGM = lgmax<EMAX>(), int NT = kNT, class After, class Store>
+          int LGM = lgmax<EMAX>(), int NT = kNT, bool TWL = false, class After, class Store>
 __device__ __forceinline__ void fft_reg(cx<R>* __restrict__ buf, int lgL, int lgT, int nseq,
                                         FirstIn<R, EMAX, HALF_IN>& in, After after_first, Store store) {
     static_assert(LGM >= 3 && LGM <= lgmax<EMAX>(), "pass radix beyond the register budget");
@@ -444,10 +467,10 @@ __device__ __forceinline__ void fft_reg(cx<R>* __restrict__ buf, int lgL, int lg
         const bool last = left == g;
 #define MAGX_BODY(RADIX)                                                                                     \
     if (last)                                                                                                \
-        stockham_io_pass<R, RADIX, INV, EMAX, kSrcReg, DST_LDS, LAYOUT, NC, HALF_IN, HALF_OUT, NT>(              \
+        stockham_io_pass<R, RADIX, INV, EMAX, kSrcReg, DST_LDS, LAYOUT, NC, HALF_IN, HALF_OUT, NT, TWL>(              \
             buf, lgL, lgNs, lgT, nseq, none_load, store, in);                                                \
     else                                                                                                     \
-        stockham_io_pass<R, RADIX, INV, EMAX, kSrcReg, true, LAYOUT, NC, HALF_IN, false, NT>(buf, lgL, lgNs, lgT, \
+        stockham_io_pass<R, RADIX, INV, EMAX, kSrcReg, true, LAYOUT, NC, HALF_IN, false, NT, TWL>(buf, lgL, lgNs, lgT, \
                                                                                          nseq, none_load,    \
                                                                                          store, in);
         MAGX_RADIX_SWITCH(g, LGM)
@@ -459,10 +482,10 @@ __device__ __forceinline__ void fft_reg(cx<R>* __restrict__ buf, int lgL, int lg
     while (left > 0) {
         constexpr int RADIX = 1 << LGM;
         if (left == LGM)
-            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, DST_LDS, LAYOUT, NC, false, HALF_OUT, NT>(
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, DST_LDS, LAYOUT, NC, false, HALF_OUT, NT, TWL>(
                 buf, lgL, lgNs, lgT, nseq, none_load, store, noin);
         else
-            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, true, LAYOUT, NC, false, false, NT>(
+            stockham_io_pass<R, RADIX, INV, EMAX, kSrcLds, true, LAYOUT, NC, false, false, NT, TWL>(
                 buf, lgL, lgNs, lgT, nseq, none_load, store, noin);
         lgNs += LGM;
         left -= LGM;
