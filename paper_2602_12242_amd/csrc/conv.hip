@@ -468,8 +468,6 @@ static inline bool em_big(long long elements) { return elements > (long long)kNT
 // (occupancy of this kernel at this LDS size, times the CU count), at most
 // one per tile.  Cached per device, kernel and LDS size.
 static int persistent_grid(const void* kernel, size_t lds, long long ntiles, int nt = kNT) {
-    if (lds > 65536 && hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return -1;
     static std::mutex mu;
     static std::map<std::tuple<int, const void*, size_t>, int> cache;
     int dev = 0;
@@ -483,6 +481,10 @@ static int persistent_grid(const void* kernel, size_t lds, long long ntiles, int
             resident = it->second;
         } else {
             int cus = 0, per_cu = 0;
+            // more than 64 KiB of dynamic LDS has to be allowed per kernel first
+            if (lds > 65536 &&
+                hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+                return -1;
             if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return -1;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, lds) != hipSuccess) return -1;
             resident = std::max(1, per_cu) * std::max(1, cus);
