@@ -318,18 +318,17 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
 // with conjugate twiddles.  Rows z >= nz (nz <= 32) are the zero padding of
 // the forward transform and are not written back.  The tensor spectrum is the
 // tile-major layout of the generic pass with a tile width of 32.
-constexpr int kZ64T = 32;
 
-template <typename R>
-__global__ void __launch_bounds__(kNT) zconv64_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
-                                                      int nz, int Py, int Hx, int Sx, int ntx,
-                                                      int units_per_member, int nunits) {
-    constexpr int T = kZ64T, Hz = 33, H2 = 32;
+template <typename R, int T>
+__global__ void __launch_bounds__(8 * T) zconv64_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
+                                                        int nz, int Py, int Hx, int Sx, int ntx,
+                                                        int units_per_member, int nunits) {
+    constexpr int Hz = 33, H2 = 32;
     extern __shared__ unsigned char smem_raw[];
     cx<R>* E = reinterpret_cast<cx<R>*>(smem_raw);   // [3][8][8][T]
     const int tid = threadIdx.x;
     const int col = tid & (T - 1);
-    const int g = tid >> 5;
+    const int g = tid / T;
     const unsigned plane_stride = (unsigned)Py * (unsigned)Sx;
     const unsigned comp_stride = (unsigned)nz * plane_stride;
     // W_64^(g j), j < 8, from the table (the inverse uses the conjugates)
@@ -607,25 +606,28 @@ static hipError_t run_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hi
     return hipGetLastError();
 }
 
+template <int T>
 static hipError_t run_zconv64(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
-    if (pl.Pz != 64 || pl.tz != kZ64T || pl.nz > 32 || pl.nz < 8) return hipErrorInvalidValue;
+    if (pl.Pz != 64 || pl.tz != T || pl.nz > 32 || pl.nz < 8) return hipErrorInvalidValue;
     const int ntx = pl.ntz;
     const int upm = ntx * (pl.Py / 2);
     const long long nunits = (long long)upm * pl.nbatch;
-    const size_t lds = (size_t)3 * 64 * kZ64T * sizeof(cx<float>);
-    const int resident = persistent_grid(reinterpret_cast<const void*>(&zconv64_kernel<float>), lds, 1LL << 30);
+    const size_t lds = (size_t)3 * 64 * T * sizeof(cx<float>);
+    const int resident =
+        persistent_grid(reinterpret_cast<const void*>(&zconv64_kernel<float, T>), lds, 1LL << 30, 8 * T);
     if (resident < 1) return hipErrorInvalidValue;
     long long grid = 2 * std::min<long long>(nunits, std::max(1, resident / 2));
     if (grid >= 16) grid -= grid % 16;
-    hipLaunchKernelGGL((zconv64_kernel<float>), dim3((unsigned)grid), dim3(kNT), lds, s, static_cast<cx<float>*>(X2),
-                       static_cast<const float*>(spec), Ms, pl.nz, pl.Py, pl.Hx, pl.Sx, ntx, upm, (int)nunits);
+    hipLaunchKernelGGL((zconv64_kernel<float, T>), dim3((unsigned)grid), dim3(8 * T), lds, s,
+                       static_cast<cx<float>*>(X2), static_cast<const float*>(spec), Ms, pl.nz, pl.Py, pl.Hx, pl.Sx,
+                       ntx, upm, (int)nunits);
     return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s) {
     if constexpr (std::is_same<R, float>::value) {
-        if (pl.zreg) return run_zconv64(pl, X2, spec, Ms, s);
+        if (pl.zreg) return pl.tz == 16 ? run_zconv64<16>(pl, X2, spec, Ms, s) : run_zconv64<32>(pl, X2, spec, Ms, s);
     }
     return em_big(3LL * pl.Pz * pl.tz) ? run_zconv<R, 32>(pl, X2, spec, Ms, s) : run_zconv<R, 16>(pl, X2, spec, Ms, s);
 }

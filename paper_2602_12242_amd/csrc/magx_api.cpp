@@ -136,8 +136,12 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
             const char* e = std::getenv("MAGX_ZREG");
             return !(e && std::atoi(e) == 0);
         }();
+        static const int zreg_t = [] {
+            const char* e = std::getenv("MAGX_ZREG_T");
+            return (e && std::atoi(e) == 16) ? 16 : 32;
+        }();
         p.zreg = (zreg_on && dt == MAGX_F32 && p.Pz == 64) ? 1 : 0;
-        if (p.zreg) tz = 32;
+        if (p.zreg) tz = zreg_t;
         p.tz = tz;
         p.ntz = (p.Hx + tz - 1) / tz;
         if ((long long)p.Hy * p.ntz * 6 * p.Hz * tz >= (1LL << 31)) return MAGX_ESIZE;
