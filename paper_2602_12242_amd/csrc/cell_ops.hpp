@@ -19,6 +19,10 @@ template <bool BIG> constexpr int maxslot() { return BIG ? 8 : 4; }
 
 struct PG {
     int nx, ny, nz, Lh, lgLh, Hx, Sx, lgPx, np, npen_total;   // npen_total: pencils of one member
+    // log2 of the cell-pair slots per line, max(Lh/2, 1): the cells fill the
+    // lower half of a packed line (x < nx <= Px/2); the upper half is the zero
+    // padding, which the forward pass never reads and nothing writes
+    int lgLq;
     int bpm;                                                 // blocks per member
     int zmajor;                                              // block order: z fastest (see block_pencils)
     long long N;                                             // cells of one member
@@ -46,6 +50,7 @@ template <int LG>
 __device__ __forceinline__ void pg_fix(PG& g) {
     if constexpr (LG > 0) {
         g.lgLh = LG;
+        g.lgLq = LG - 1;
         g.Lh = 1 << LG;
         g.lgPx = LG + 1;
         g.nx = 1 << LG;
@@ -58,6 +63,7 @@ inline PG make_pg(const Plan& pl) {
     PG g;
     g.nx = pl.nx; g.ny = pl.ny; g.nz = pl.nz;
     g.Lh = pl.Lh; g.lgLh = pl.lgLh; g.Hx = pl.Hx; g.Sx = pl.Sx; g.lgPx = pl.lgPx;
+    g.lgLq = pl.lgLh > 0 ? pl.lgLh - 1 : 0;
     g.np = pl.np; g.npen_total = pl.ny * pl.nz; g.bpm = pl.blocks_per_member; g.N = pl.ncell;
     g.div_ny = make_fastdiv(pl.ny);
     g.div_hx = make_fastdiv(pl.Hx);

@@ -41,8 +41,8 @@ __global__ void __launch_bounds__(kNT) mri_slow_kernel(const cx<R>* __restrict__
     for (int c = 0; c < 3; ++c) hbv[c] = ph.hbm ? ph.hbm[mb * 3 + c] : ph.hb[c];
     const bool vec = (g.nx & 1) == 0;
     if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, mb, pen0, npen);
-    for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+    for (int e = threadIdx.x; e < npen << g.lgLq; e += kNT) {
+        const int p = e >> g.lgLq, n = e & ((1 << g.lgLq) - 1);
         const int x0 = 2 * n;
         if (x0 >= g.nx) continue;
         const bool two = x0 + 1 < g.nx;
@@ -105,8 +105,8 @@ __global__ void __launch_bounds__(kNT) mri_fast_kernel(const R* __restrict__ v, 
 #pragma unroll 1
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
-        if (e >= npen * g.Lh) continue;
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        if (e >= npen << g.lgLq) continue;
+        const int p = e >> g.lgLq, n = e & ((1 << g.lgLq) - 1);
         const int x0 = 2 * n;
         if (x0 >= g.nx) {
             if (fwd) {

@@ -38,8 +38,8 @@ __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R
     block_pencils(g, lb - mb * g.bpm, pen0, npen);
     const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
     f += mo;
-    for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+    for (int e = threadIdx.x; e < npen << g.lgLq; e += kNT) {
+        const int p = e >> g.lgLq, n = e & ((1 << g.lgLq) - 1);
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
         const long long row = ((long long)z * g.ny + y) * g.nx;
@@ -84,8 +84,8 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
     const bool vec = (g.nx & 1) == 0;
     if (has_demag) c2r_lines<R, BIG>(buf, Y1, g, mb, pen0, npen);
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int e = threadIdx.x; e < npen * g.Lh; e += kNT) {
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+    for (int e = threadIdx.x; e < npen << g.lgLq; e += kNT) {
+        const int p = e >> g.lgLq, n = e & ((1 << g.lgLq) - 1);
         const int x0 = 2 * n;
         if (x0 >= g.nx) continue;
         const bool two = x0 + 1 < g.nx;
@@ -178,8 +178,8 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
 #pragma unroll 1
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
-        if (e >= npen * g.Lh) continue;
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        if (e >= npen << g.lgLq) continue;
+        const int p = e >> g.lgLq, n = e & ((1 << g.lgLq) - 1);
         const int x0 = 2 * n;
         if (x0 >= g.nx) {
             if (fwd) {
@@ -291,8 +291,8 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
 #pragma unroll 1
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
-        if (e >= npen * g.Lh) continue;
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        if (e >= npen << g.lgLq) continue;
+        const int p = e >> g.lgLq, n = e & ((1 << g.lgLq) - 1);
         const int x0 = 2 * n;
         if (x0 >= g.nx) {
             if (has_demag) {
@@ -392,8 +392,8 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
 #pragma unroll 1
     for (int i = 0; i < maxslot<BIG>(); ++i) {
         const int e = threadIdx.x + i * kNT;
-        if (e >= npen * g.Lh) continue;
-        const int p = e >> g.lgLh, n = e & (g.Lh - 1);
+        if (e >= npen << g.lgLq) continue;
+        const int p = e >> g.lgLq, n = e & ((1 << g.lgLq) - 1);
         const int x0 = 2 * n;
         if (x0 >= g.nx) {
             if (fwd) {
