@@ -8,8 +8,10 @@
 //           are zero padding), then the pointwise product with the real
 //           symmetric tensor spectrum, H_a = -Ms sum_b N_ab M_b (tensor values
 //           held in registers), then the inverse z FFT; only rows z < nz are
-//           written back (in place).
+//           written back (in place).  Single precision with Pz = 64 has a
+//           register-resident variant (zconv64).
 //  * yinv : inverse y FFT; only rows y < ny (inside the box) are written.
+// FFT pass twiddles come from a two-level LDS table filled by each block.
 #include <algorithm>
 #include <cstdlib>
 #include <map>
@@ -310,14 +312,15 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
 }
 
 // z pass for Pz = 64 (8 x 8 in registers, single precision).  Thread
-// (col, g), col < 32, g < 8, of a 32-column tile holds the elements
-// z = g + 8 r (r < 8) of all three components: a length-8 DFT over r, the
-// twiddles W_64^(g k1), one LDS exchange to (col, k1), a length-8 DFT over g,
-// and it then holds kz = k1 + 8 k2 (k2 < 8) of all three components, so the
-// 3x3 spectral product runs in registers; the inverse retraces the same steps
-// with conjugate twiddles.  Rows z >= nz (nz <= 32) are the zero padding of
-// the forward transform and are not written back.  The tensor spectrum is the
-// tile-major layout of the generic pass with a tile width of 32.
+// (col, g), col < T, g < 8, of a T-column tile (8 T threads; T = 32 by
+// default) holds the elements z = g + 8 r (r < 8) of all three components: a
+// length-8 DFT over r, the twiddles W_64^(g k1), one LDS exchange to
+// (col, k1), a length-8 DFT over g, and it then holds kz = k1 + 8 k2 (k2 < 8)
+// of all three components, so the 3x3 spectral product runs in registers; the
+// inverse retraces the same steps with conjugate twiddles.  Rows z >= nz
+// (nz <= 32) are the zero padding of the forward transform and are not written
+// back.  The tensor spectrum is the tile-major layout of the generic pass with
+// a tile width of T.
 
 template <typename R, int T>
 __global__ void __launch_bounds__(8 * T) zconv64_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
@@ -532,8 +535,9 @@ static hipError_t run_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t
     return hipGetLastError();
 }
 
-// Tiles of more than 256 x 16 elements: 256 threads of 32 elements (two
-// radix-32 passes for Py = 1024), or with MAGX_Y_THREADS=512 512 threads of 16.
+// Tiles of 256 x 16 < Py * ty <= 256 x 32 elements (64 KiB in single
+// precision): 256 threads of 32 elements, or with MAGX_Y_THREADS=512 512
+// threads of 16.
 static bool y_wide(const Plan& pl) {
     static const int nt = [] {
         const char* e = std::getenv("MAGX_Y_THREADS");
@@ -543,7 +547,8 @@ static bool y_wide(const Plan& pl) {
     return nt != 256;
 }
 
-// Tiles of more than 256 x 32 elements (beyond 64 KiB of LDS): 512 threads of 32.
+// Tiles of more than 256 x 32 elements (up to 128 KiB of LDS, one block per
+// CU): 512 threads of 32 elements (two radix-32 passes for Py = 1024).
 static bool y_huge(const Plan& pl) { return (long long)pl.Py * pl.ty > (long long)kNT * 32; }
 
 // LG of the compile-time y geometry that matches the plan, 0 if none.
