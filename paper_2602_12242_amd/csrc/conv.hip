@@ -61,20 +61,25 @@ struct PairWalk {
     __device__ int tile(int u) const { return (u / ntxp) * ntx + 2 * (u % ntxp) + side; }
 };
 
-// Compile-time geometry of the y passes for square power-of-two grids in
-// single precision, nx = ny = 2^(LG-1) (Px = Py = 2^LG): every size of the
-// pass (row stride, tile width, tile count) becomes a constant, so the FFT
-// strides and row offsets are immediates.  LG = 0 keeps runtime sizes.
-constexpr int ytile_lg(int LG) { return LG >= 10 ? 14 - LG : 4; }   // ty = min(16, 2^14 / Py)
+// Compile-time geometry of the y passes for square power-of-two grids,
+// nx = ny = 2^(LG-1) (Px = Py = 2^LG): every size of the pass (row stride,
+// tile width, tile count) becomes a constant, so the FFT strides and row
+// offsets are immediates.  LG = 0 keeps runtime sizes.  The tile width is the
+// plan's, ty = min(16, budget / Py) with a budget of 2^14 complex values in
+// single and 2^12 in double precision.
+template <typename R> constexpr int ytile_lg(int LG) {
+    constexpr int lgb = sizeof(R) == 4 ? 14 : 12;
+    return LG >= lgb - 4 ? lgb - LG : 4;
+}
 
-template <int LG>
+template <typename R, int LG>
 __device__ __forceinline__ void ygeom_fix(int& ny, int& lgPy, int& Hx, int& Sx, int& lgT, int& ntx) {
     if constexpr (LG > 0) {
         ny = 1 << (LG - 1);
         lgPy = LG;
         Hx = (1 << (LG - 1)) + 1;
         Sx = (1 << (LG - 1)) + 16;
-        lgT = ytile_lg(LG);
+        lgT = ytile_lg<R>(LG);
         ntx = (Hx + (1 << lgT) - 1) >> lgT;
     }
 }
@@ -82,7 +87,7 @@ __device__ __forceinline__ void ygeom_fix(int& ny, int& lgPy, int& Hx, int& Sx, 
 template <typename R, int EM, int NT, int LG>
 __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
                                                   int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
-    ygeom_fix<LG>(ny, lgPy, Hx, Sx, lgT, ntx);
+    ygeom_fix<R, LG>(ny, lgPy, Hx, Sx, lgT, ntx);
     tw_lds_fill<R>();   // read by the second pass, after the first barrier
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
@@ -132,7 +137,7 @@ __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, 
 template <typename R, int EM, int NT, int LG>
 __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
                                                   int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
-    ygeom_fix<LG>(ny, lgPy, Hx, Sx, lgT, ntx);
+    ygeom_fix<R, LG>(ny, lgPy, Hx, Sx, lgT, ntx);
     tw_lds_fill<R>();   // read by the second pass, after the first barrier
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
@@ -552,21 +557,31 @@ static bool y_wide(const Plan& pl) {
 static bool y_huge(const Plan& pl) { return (long long)pl.Py * pl.ty > (long long)kNT * 32; }
 
 // LG of the compile-time y geometry that matches the plan, 0 if none.
+template <typename R>
 static int y_lg(const Plan& pl) {
-    if (pl.dtype != MAGX_F32 || pl.Px != pl.Py || 2 * pl.nx != pl.Px || 2 * pl.ny != pl.Py) return 0;
+    if (pl.Px != pl.Py || 2 * pl.nx != pl.Px || 2 * pl.ny != pl.Py) return 0;
     if (pl.lgPy < 8 || pl.lgPy > 11 || y_wide(pl)) return 0;
-    if (pl.ty != (1 << ytile_lg(pl.lgPy)) || pl.Sx != pl.Px / 2 + 16) return 0;
+    if (pl.ty != (1 << ytile_lg<R>(pl.lgPy)) || pl.Sx != pl.Px / 2 + 16) return 0;
     return pl.lgPy;
 }
 
 template <typename R>
 hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
     if constexpr (std::is_same<R, float>::value) {
-        switch (y_lg(pl)) {
+        switch (y_lg<R>(pl)) {
             case 8: return run_yfwd<R, 16, kNT, 8>(pl, X1, X2, s);
             case 9: return run_yfwd<R, 32, kNT, 9>(pl, X1, X2, s);
             case 10: return run_yfwd<R, 32, 512, 10>(pl, X1, X2, s);
             case 11: return run_yfwd<R, 32, 512, 11>(pl, X1, X2, s);
+            default: break;
+        }
+    } else {
+        // double precision: tiles of 2^12 values, 256 threads of 16
+        switch (y_lg<R>(pl)) {
+            case 8: return run_yfwd<R, 16, kNT, 8>(pl, X1, X2, s);
+            case 9: return run_yfwd<R, 16, kNT, 9>(pl, X1, X2, s);
+            case 10: return run_yfwd<R, 16, kNT, 10>(pl, X1, X2, s);
+            case 11: return run_yfwd<R, 16, kNT, 11>(pl, X1, X2, s);
             default: break;
         }
     }
@@ -578,11 +593,19 @@ hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) 
 template <typename R>
 hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
     if constexpr (std::is_same<R, float>::value) {
-        switch (y_lg(pl)) {
+        switch (y_lg<R>(pl)) {
             case 8: return run_yinv<R, 16, kNT, 8>(pl, X2, Y1, s);
             case 9: return run_yinv<R, 32, kNT, 9>(pl, X2, Y1, s);
             case 10: return run_yinv<R, 32, 512, 10>(pl, X2, Y1, s);
             case 11: return run_yinv<R, 32, 512, 11>(pl, X2, Y1, s);
+            default: break;
+        }
+    } else {
+        switch (y_lg<R>(pl)) {
+            case 8: return run_yinv<R, 16, kNT, 8>(pl, X2, Y1, s);
+            case 9: return run_yinv<R, 16, kNT, 9>(pl, X2, Y1, s);
+            case 10: return run_yinv<R, 16, kNT, 10>(pl, X2, Y1, s);
+            case 11: return run_yinv<R, 16, kNT, 11>(pl, X2, Y1, s);
             default: break;
         }
     }
