@@ -29,6 +29,14 @@ CASES = {
                         terms=ALL)),
     "tiles": ((96, 70, 9), (2e-9, 2e-9, 3e-9),
               dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, alpha=0.1, Hbias=(1e3, 2e3, -5e3), terms=ALL)),
+    # Pz = 64: the register-resident z pass (single precision) walks units of
+    # every member
+    "thick": ((40, 9, 20), (2e-9, 2e-9, 1e-9),
+              dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, eK=(0.6, 0.0, 0.8), alpha=0.1, Hbias=(1e3, -2e3, 5e3),
+                   terms=ALL)),
+    # square power-of-two plane: compile-time pencil and y geometry
+    "sq128": ((128, 128, 2), (2e-9, 2e-9, 2e-9),
+              dict(Ms=8e5, A=1.3e-11, D=1e-3, alpha=0.1, Hbias=(2e3, 0, 1e3), terms=ALL)),
 }
 B = 3
 
@@ -109,7 +117,7 @@ def test_batched_member_matches_oracle(name):
         assert err <= 1e-11, (b, err)
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles"])
+@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "sq128"])
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_batched_steps_and_reverse_equal_single(name, dtype):
     n, d, mat, single, batch, pb = _setup(name, dtype)
