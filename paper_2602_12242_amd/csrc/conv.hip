@@ -8,8 +8,8 @@
 //           are zero padding), then the pointwise product with the real
 //           symmetric tensor spectrum, H_a = -Ms sum_b N_ab M_b (tensor values
 //           held in registers), then the inverse z FFT; only rows z < nz are
-//           written back (in place).  Single precision with Pz = 64 has a
-//           register-resident variant (zconv64).
+//           written back (in place).  Single precision with Pz = 8 ... 64
+//           has a register-resident variant (zconvr).
 //  * yinv : inverse y FFT; only rows y < ny (inside the box) are written.
 // FFT pass twiddles come from a two-level LDS table filled by each block.
 #include <algorithm>
@@ -316,34 +316,42 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
     }
 }
 
-// z pass for Pz = 64 (8 x 8 in registers, single precision).  Thread
-// (col, g), col < T, g < 8, of a T-column tile (8 T threads; T = 32 by
-// default) holds the elements z = g + 8 r (r < 8) of all three components: a
-// length-8 DFT over r, the twiddles W_64^(g k1), one LDS exchange to
-// (col, k1), a length-8 DFT over g, and it then holds kz = k1 + 8 k2 (k2 < 8)
-// of all three components, so the 3x3 spectral product runs in registers; the
-// inverse retraces the same steps with conjugate twiddles.  Rows z >= nz
-// (nz <= 32) are the zero padding of the forward transform and are not written
-// back.  The tensor spectrum is the tile-major layout of the generic pass with
-// a tile width of T.
-
-template <typename R, int T>
-__global__ void __launch_bounds__(8 * T) zconv64_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
-                                                        int nz, int Py, int Hx, int Sx, int ntx,
-                                                        int units_per_member, int nunits) {
-    constexpr int Hz = 33, H2 = 32;
+// Register-resident z pass for Pz = 8 G, G = 1, 2, 4, 8 (single precision).
+// Thread (col, g), col < T, g < G, of a T-column tile (G T threads) holds
+// the elements z = g + G r (r < 8) of all three components.  Forward: a
+// length-8 DFT over r, the twiddles W_Pz^(g k1), one LDS exchange, and
+// length-G DFTs over g: the thread then owns k1 = g + G j (j < 8/G) and
+// kz = k1 + 8 k2 (k2 < G) of all three components, eight values each, so the
+// 3x3 spectral product runs in registers.  The inverse retraces the steps with
+// conjugate twiddles.  Rows z >= nz (nz <= Pz/2, so r < 4) are the zero
+// padding and are not written back.  The tensor spectrum is the tile-major
+// layout of the generic pass with a tile width of T.  G = 8 is the 8 x 8
+// split of Pz = 64; G = 1 needs no exchange.
+template <typename R, int T, int G>
+__global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
+                                                       int nz, int Py, int Hx, int Sx, int ntx,
+                                                       int units_per_member, int nunits) {
+    constexpr int PZ = 8 * G, H2 = PZ / 2, Hz = H2 + 1, J = 8 / G;
+    constexpr int LGPZ = ilog2c(PZ);
     extern __shared__ unsigned char smem_raw[];
-    cx<R>* E = reinterpret_cast<cx<R>*>(smem_raw);   // [3][8][8][T]
+    cx<R>* E = reinterpret_cast<cx<R>*>(smem_raw);   // [3][8][G][T]
     const int tid = threadIdx.x;
     const int col = tid & (T - 1);
     const int g = tid / T;
     const unsigned plane_stride = (unsigned)Py * (unsigned)Sx;
     const unsigned comp_stride = (unsigned)nz * plane_stride;
-    // W_64^(g j), j < 8, from the table (the inverse uses the conjugates)
-    cx<R> w[8];
-    w[0] = mk<R>((R)1, (R)0);
+    // w1[k1] = W_Pz^(g k1) (forward pass over r); w2[j][q] = W_Pz^(q (g + G j))
+    // (the twiddles between the length-G DFTs of the items k1 = g + G j);
+    // the inverse uses the conjugates
+    // (for G = 8, J = 1 and w2[0] = w1)
+    cx<R> w1[8], w2[J][G];
 #pragma unroll
-    for (int j = 1; j < 8; ++j) w[j] = tw_fwd<R>((g * j) << (kTwLog - 6));
+    for (int k1 = 0; k1 < 8; ++k1) w1[k1] = tw_fwd<R>(((g * k1) & (PZ - 1)) << (kTwLog - LGPZ));
+#pragma unroll
+    for (int jj = 0; jj < J; ++jj)
+#pragma unroll
+        for (int q = 0; q < G; ++q)
+            w2[jj][q] = G == 8 ? w1[q] : tw_fwd<R>(((q * (g + G * jj)) & (PZ - 1)) << (kTwLog - LGPZ));
     struct Tile {
         int mb, kx0, ky, tx, kyo;
     };
@@ -363,7 +371,7 @@ __global__ void __launch_bounds__(8 * T) zconv64_kernel(cx<R>* __restrict__ X2, 
     auto base_of = [=](const Tile& d) {
         return X2 + (long long)d.mb * 3 * comp_stride + (long long)d.ky * Sx + d.kx0;
     };
-    // Inputs of a tile: rows g + 8 r, r < 4, of the three components.  Every
+    // Inputs of a tile: rows g + G r, r < 4, of the three components.  Every
     // operation of the pass acts on one column, so a column beyond Hx (read at
     // the clamped column Hx-1 of the same row) only produces values that are
     // never stored; rows z >= nz are the zero padding.
@@ -376,8 +384,8 @@ __global__ void __launch_bounds__(8 * T) zconv64_kernel(cx<R>* __restrict__ X2, 
         for (int c = 0; c < 3; ++c)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int z = g + 8 * r;
-                const unsigned zoff = (unsigned)min(8 * r, nz - 1 - g) * plane_stride;
+                const int z = g + G * r;
+                const unsigned zoff = (unsigned)min(G * r, nz - 1 - g) * plane_stride;
                 const cx<R> v = base[(unsigned)c * comp_stride + zoff + voff];
                 pin[c * 4 + r] = z < nz ? v : mk<R>((R)0, (R)0);
             }
@@ -391,20 +399,26 @@ __global__ void __launch_bounds__(8 * T) zconv64_kernel(cx<R>* __restrict__ X2, 
     for (int t = t0; t < t1; ++t) {
         const Tile d = tile_of(t);
         const R sy = d.ky <= Py / 2 ? (R)1 : (R)-1;
-        // tensor values of kz = g + 8 k2 (this thread's rows after the exchange),
-        // read at the octant row kzo = kz (k2 < 4) or 64 - kz (k2 >= 4); the
-        // tile's block [6][Hz][T] of the tile-major spectrum is contiguous and
-        // includes the padding columns of the last tile
+        // tensor values of this thread's kz = g + G j + 8 k2, read at the
+        // octant row kzo = min(kz, Pz - kz); the tile's block [6][Hz][T] of the
+        // tile-major spectrum is contiguous and includes the padding columns of
+        // the last tile
         R tv[8][6];
         {
             const R* blk = spec + (long long)(d.kyo * ntx + d.tx) * 6 * (Hz * T);
-            const int lo = g * T + col, hi = (64 - g) * T + col;
+            // with g < G, kz <= H2 holds for all g when G j + 8 k2 + G - 1 <= H2
+            // and for none when G j + 8 k2 > H2 (decided at compile time)
+            const int lo = g * T + col, hi = (PZ - g) * T + col;
 #pragma unroll
-            for (int k2 = 0; k2 < 8; ++k2) {
-                const int o = k2 < 4 ? lo + 8 * k2 * T : hi - 8 * k2 * T;
+            for (int jj = 0; jj < J; ++jj)
 #pragma unroll
-                for (int c6 = 0; c6 < 6; ++c6) tv[k2][c6] = blk[c6 * (Hz * T) + o];
-            }
+                for (int k2 = 0; k2 < G; ++k2) {
+                    const int k0 = G * jj + 8 * k2;
+                    const int olo = lo + k0 * T, ohi = hi - k0 * T;
+                    const int o = k0 + G - 1 <= H2 ? olo : (k0 > H2 ? ohi : (g + k0 <= H2 ? olo : ohi));
+#pragma unroll
+                    for (int c6 = 0; c6 < 6; ++c6) tv[jj * G + k2][c6] = blk[c6 * (Hz * T) + o];
+                }
         }
         // forward: DFT over r, twiddles, exchange
 #pragma unroll
@@ -416,51 +430,62 @@ __global__ void __launch_bounds__(8 * T) zconv64_kernel(cx<R>* __restrict__ X2, 
             for (int r = 4; r < 8; ++r) v[r] = mk<R>((R)0, (R)0);
             dft8<R, false>(v);
 #pragma unroll
-            for (int k1 = 0; k1 < 8; ++k1) E[((c * 8 + k1) * 8 + g) * T + col] = cmul<R>(v[k1], w[k1]);
+            for (int k1 = 0; k1 < 8; ++k1) E[((c * 8 + k1) * G + g) * T + col] = cmul<R>(v[k1], w1[k1]);
         }
-        __syncthreads();
+        if constexpr (G > 1) __syncthreads();
+        // length-G DFTs over g: X[c][j G + k2] is the spectrum at kz = g + G j + 8 k2
         cx<R> X[3][8];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-#pragma unroll
-            for (int q = 0; q < 8; ++q) X[c][q] = E[((c * 8 + g) * 8 + q) * T + col];
-            dft8<R, false>(X[c]);
-        }
-        // spectral product at kz = g + 8 k2
-#pragma unroll
-        for (int k2 = 0; k2 < 8; ++k2) {
-            const int kz = g + 8 * k2;
-            const R sz = kz <= H2 ? (R)1 : (R)-1;
-            const R nxx = tv[k2][0], nyy = tv[k2][1], nzz = tv[k2][2];
-            const R nxy = sy * tv[k2][3], nxz = sz * tv[k2][4], nyz = sy * sz * tv[k2][5];
-            const cx<R> mx = X[0][k2], my = X[1][k2], mz = X[2][k2];
-            X[0][k2] = mk<R>(s * (nxx * mx.x + nxy * my.x + nxz * mz.x), s * (nxx * mx.y + nxy * my.y + nxz * mz.y));
-            X[1][k2] = mk<R>(s * (nxy * mx.x + nyy * my.x + nyz * mz.x), s * (nxy * mx.y + nyy * my.y + nyz * mz.y));
-            X[2][k2] = mk<R>(s * (nxz * mx.x + nyz * my.x + nzz * mz.x), s * (nxz * mx.y + nyz * my.y + nzz * mz.y));
-        }
-        // the next tile's inputs are in flight during the inverse transform
-        if (t + 1 < t1) load_tile(t + 1);
-        // inverse: DFT over k2, conjugate twiddles, exchange back
-#pragma unroll
-        for (int c = 0; c < 3; ++c) dft8<R, true>(X[c]);
-        __syncthreads();
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
-            for (int n2 = 0; n2 < 8; ++n2) E[((c * 8 + n2) * 8 + g) * T + col] = cmul<R>(X[c][n2], cconj<R>(w[n2]));
-        __syncthreads();
+            for (int jj = 0; jj < J; ++jj) {
+                const int k1 = g + G * jj;
+#pragma unroll
+                for (int q = 0; q < G; ++q) X[c][jj * G + q] = E[((c * 8 + k1) * G + q) * T + col];
+                if constexpr (G > 1) dft<R, G, false>(&X[c][jj * G]);
+            }
+        // spectral product
+#pragma unroll
+        for (int jj = 0; jj < J; ++jj)
+#pragma unroll
+            for (int k2 = 0; k2 < G; ++k2) {
+                const int e = jj * G + k2;
+                const int kz = g + G * jj + 8 * k2;
+                const R sz = kz <= H2 ? (R)1 : (R)-1;
+                const R nxx = tv[e][0], nyy = tv[e][1], nzz = tv[e][2];
+                const R nxy = sy * tv[e][3], nxz = sz * tv[e][4], nyz = sy * sz * tv[e][5];
+                const cx<R> mx = X[0][e], my = X[1][e], mz = X[2][e];
+                X[0][e] = mk<R>(s * (nxx * mx.x + nxy * my.x + nxz * mz.x), s * (nxx * mx.y + nxy * my.y + nxz * mz.y));
+                X[1][e] = mk<R>(s * (nxy * mx.x + nyy * my.x + nyz * mz.x), s * (nxy * mx.y + nyy * my.y + nyz * mz.y));
+                X[2][e] = mk<R>(s * (nxz * mx.x + nyz * my.x + nzz * mz.x), s * (nxz * mx.y + nyz * my.y + nzz * mz.y));
+            }
+        // the next tile's inputs are in flight during the inverse transform
+        if (t + 1 < t1) load_tile(t + 1);
+        // inverse: length-G DFTs over k2, conjugate twiddles, exchange back
+        if constexpr (G > 1) __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int jj = 0; jj < J; ++jj) {
+                const int k1 = g + G * jj;
+                if constexpr (G > 1) dft<R, G, true>(&X[c][jj * G]);
+#pragma unroll
+                for (int q = 0; q < G; ++q)
+                    E[((c * 8 + k1) * G + q) * T + col] = cmul<R>(X[c][jj * G + q], cconj<R>(w2[jj][q]));
+            }
+        if constexpr (G > 1) __syncthreads();
         cx<R>* base = base_of(d);
         const bool okc = d.kx0 + col < Hx;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             cx<R> v[8];
 #pragma unroll
-            for (int k1 = 0; k1 < 8; ++k1) v[k1] = E[((c * 8 + g) * 8 + k1) * T + col];
+            for (int k1 = 0; k1 < 8; ++k1) v[k1] = E[((c * 8 + k1) * G + g) * T + col];
             dft8<R, true>(v);
-            // rows z = g + 8 n1 >= 32 >= nz are never needed
+            // rows z = g + G n1 >= Pz/2 >= nz are never needed
 #pragma unroll
             for (int n1 = 0; n1 < 4; ++n1) {
-                const int z = g + 8 * n1;
+                const int z = g + G * n1;
                 if (okc && z < nz)
                     base[(unsigned)c * comp_stride + (unsigned)z * plane_stride + (unsigned)col] = v[n1];
             }
@@ -634,28 +659,39 @@ static hipError_t run_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hi
     return hipGetLastError();
 }
 
-template <int T>
-static hipError_t run_zconv64(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
-    if (pl.Pz != 64 || pl.tz != T || pl.nz > 32 || pl.nz < 8) return hipErrorInvalidValue;
+template <int T, int G>
+static hipError_t run_zconvr(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
+    if (pl.Pz != 8 * G || pl.tz != T || 2 * pl.nz > pl.Pz || 4 * pl.nz <= pl.Pz) return hipErrorInvalidValue;
     const int ntx = pl.ntz;
     const int upm = ntx * (pl.Py / 2);
     const long long nunits = (long long)upm * pl.nbatch;
-    const size_t lds = (size_t)3 * 64 * T * sizeof(cx<float>);
+    const size_t lds = (size_t)3 * 8 * G * T * sizeof(cx<float>);
     const int resident =
-        persistent_grid(reinterpret_cast<const void*>(&zconv64_kernel<float, T>), lds, 1LL << 30, 8 * T);
-    if (resident < 1) return hipErrorInvalidValue;
+        persistent_grid(reinterpret_cast<const void*>(&zconvr_kernel<float, T, G>), lds, 1LL << 30, G * T);
+    if (resident < 2) return hipErrorInvalidValue;
     long long grid = 2 * std::min<long long>(nunits, std::max(1, resident / 2));
     if (grid >= 16) grid -= grid % 16;
-    hipLaunchKernelGGL((zconv64_kernel<float, T>), dim3((unsigned)grid), dim3(8 * T), lds, s,
+    hipLaunchKernelGGL((zconvr_kernel<float, T, G>), dim3((unsigned)grid), dim3(G * T), lds, s,
                        static_cast<cx<float>*>(X2), static_cast<const float*>(spec), Ms, pl.nz, pl.Py, pl.Hx, pl.Sx,
                        ntx, upm, (int)nunits);
     return hipGetLastError();
 }
 
+static hipError_t run_zreg(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
+    if (pl.tz == 16) return pl.Pz == 64 ? run_zconvr<16, 8>(pl, X2, spec, Ms, s) : hipErrorInvalidValue;
+    switch (pl.Pz) {
+        case 8: return run_zconvr<64, 1>(pl, X2, spec, Ms, s);
+        case 16: return run_zconvr<32, 2>(pl, X2, spec, Ms, s);
+        case 32: return run_zconvr<32, 4>(pl, X2, spec, Ms, s);
+        case 64: return run_zconvr<32, 8>(pl, X2, spec, Ms, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename R>
 hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s) {
     if constexpr (std::is_same<R, float>::value) {
-        if (pl.zreg) return pl.tz == 16 ? run_zconv64<16>(pl, X2, spec, Ms, s) : run_zconv64<32>(pl, X2, spec, Ms, s);
+        if (pl.zreg) return run_zreg(pl, X2, spec, Ms, s);
     }
     return em_big(3LL * pl.Pz * pl.tz) ? run_zconv<R, 32>(pl, X2, spec, Ms, s) : run_zconv<R, 16>(pl, X2, spec, Ms, s);
 }

@@ -131,7 +131,8 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
             const int t = std::atoi(e);
             if (t >= 1 && (t & (t - 1)) == 0 && fits(t, 32)) tz = t;
         }
-        // single precision with Pz = 64: the register-resident z pass, 32 columns per tile
+        // single precision with Pz = 8 ... 64: the register-resident z pass (Pz/8 T threads per
+        // T-column tile; T = 32, 64 for Pz = 8, 16 selectable for Pz = 64)
         static const bool zreg_on = [] {
             const char* e = std::getenv("MAGX_ZREG");
             return !(e && std::atoi(e) == 0);
@@ -140,8 +141,8 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
             const char* e = std::getenv("MAGX_ZREG_T");
             return (e && std::atoi(e) == 16) ? 16 : 32;
         }();
-        p.zreg = (zreg_on && dt == MAGX_F32 && p.Pz == 64) ? 1 : 0;
-        if (p.zreg) tz = zreg_t;
+        p.zreg = (zreg_on && dt == MAGX_F32 && p.Pz >= 8 && p.Pz <= 64) ? 1 : 0;
+        if (p.zreg) tz = p.Pz == 64 ? zreg_t : (p.Pz == 8 ? 64 : 32);   // at least 64 threads per block
         p.tz = tz;
         p.ntz = (p.Hx + tz - 1) / tz;
         if ((long long)p.Hy * p.ntz * 6 * p.Hz * tz >= (1LL << 31)) return MAGX_ESIZE;

@@ -35,7 +35,7 @@ struct Plan {
     // column tiles of the y and z passes, pencils per block of the x passes
     int ty, tz, np;
     int ntz;                    // column tiles of the z pass (and of the tensor spectrum)
-    int zreg;                   // z pass held in registers (single precision, Pz = 64, tz = 32)
+    int zreg;                   // z pass held in registers (single precision, Pz = 8 ... 64)
     int pencil_blocks;
     // workspace layout (bytes)
     size_t off_x1, off_x2, off_f[5], off_part, ws_bytes;
