@@ -250,8 +250,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this build runs on one GPU only; the multi-GPU decomposition is a design "
-              "(see the sharding notes), so --gpus must be 1", file=sys.stderr)
+        print("bench.py: magx runs on one GPU; the decomposition over several GPUs (z slabs with two "
+              "all-to-all exchanges per H_eff) is designed but not implemented, so --gpus must be 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
