@@ -66,6 +66,12 @@ CASES = {
     # geometry in single precision (as are the 256-, 512- and 1024-cell workloads)
     "sq128": ((128, 128, 2), (2e-9, 2e-9, 2e-9),
               dict(Ms=8e5, A=1.3e-11, D=1e-3, alpha=0.1, Hbias=(2e3, 0, 0), terms=ALL)),
+    # register-resident z pass on degenerate planes: one cell across (Px = Py
+    # = 2, a single column and one row pair) and a single row (Py = 2)
+    "stack20": ((1, 1, 20), (2e-9, 2e-9, 1e-9),
+                dict(Ms=8e5, A=1.3e-11, alpha=0.1, Hbias=(0, 0, 1e4), terms=1 | 2 | 16)),
+    "row9": ((3, 1, 9), (2e-9, 2e-9, 2e-9),
+             dict(Ms=8e5, A=1.3e-11, D=1e-3, Ku=5e5, eK=(0, 0, 1), alpha=0.1, terms=ALL)),
     # Pz = 1024: the longest z transform, one column per z tile
     "tall": ((3, 2, 300), (2e-9, 2e-9, 1e-9),
              dict(Ms=8e5, A=1.3e-11, alpha=0.1, Hbias=(0, 0, 1e4), terms=1 | 2 | 16)),
