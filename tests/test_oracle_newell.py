@@ -194,3 +194,128 @@ def test_spectrum_is_real_and_even():
         flip_z = sp[(-np.arange(6)) % 6, :, :]
         assert np.allclose(flip_y, py * sp, atol=1e-12)
         assert np.allclose(flip_z, pz * sp, atol=1e-12)
+
+
+# ---- off-diagonal components, pinned without Newell's g -------------------------------
+
+def _triangle_fold(rho2, zc, c):
+    # int_{zc-c}^{zc+c} (c - |w - zc|) / sqrt(rho2 + w^2) dw for rho2 > 0: the
+    # shared in-plane direction of two perpendicular faces, whose coordinate
+    # difference w has the triangle density (c - |w - zc|) (elementary
+    # antiderivatives asinh(w / rho) and sqrt(rho2 + w^2))
+    rho = math.sqrt(rho2)
+    A = lambda w: math.asinh(w / rho)  # noqa: E731
+    B = lambda w: math.sqrt(rho2 + w * w)  # noqa: E731
+    lo, hi = zc - c, zc + c
+    return ((c - zc) * (A(zc) - A(lo)) + (B(zc) - B(lo))
+            + (c + zc) * (A(hi) - A(zc)) - (B(hi) - B(zc)))
+
+
+def _surface_offdiag(a, b, R, d):
+    # N_ab (a != b) = 1/(4 pi V) sum over the a-faces of the target cell (normal
+    # sign t) and the b-faces of the source cell (normal sign s) of
+    # t s int int dS dS' / |x - x'| -- the surface-charge form of the
+    # cell-averaged tensor (Section II-B, Eq. (3)).  The two faces are
+    # perpendicular: the difference along a (u) and along b (v) are uniform,
+    # the one along the third axis is folded analytically, (u, v) adaptively.
+    c = 3 - a - b
+    tot = 0.0
+    for t in (1, -1):
+        for s in (1, -1):
+            ua = R[a] + t * d[a] / 2
+            vb = R[b] - s * d[b] / 2
+            ulo, uhi = ua - d[a] / 2, ua + d[a] / 2
+            vlo, vhi = vb - d[b] / 2, vb + d[b] / 2
+
+            def f(v, u):
+                r2 = u * u + v * v
+                return _triangle_fold(r2, R[c], d[c]) if r2 > 0 else 0.0
+            pu = [0.0] if ulo < 0.0 < uhi else []
+            pv = [0.0] if vlo < 0.0 < vhi else []
+            val, _ = integrate.nquad(f, [[vlo, vhi], [ulo, uhi]],
+                                     opts=[{"points": pv, "epsabs": 1e-14, "epsrel": 1e-12, "limit": 200},
+                                           {"points": pu, "epsabs": 1e-14, "epsrel": 1e-12, "limit": 200}])
+            tot += t * s * val
+    return tot / (4 * math.pi * d[0] * d[1] * d[2])
+
+
+_OFFDIAG = {(0, 1): 3, (0, 2): 4, (1, 2): 5}
+
+
+@pytest.mark.parametrize("d", [(1.2, 1.0, 0.8), (1.0, 1.0, 1.0), (3.90625, 3.90625, 3.0)])
+@pytest.mark.parametrize("o", [(1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1), (2, 1, 0), (1, 2, 1), (2, 2, 1),
+                               (-1, 2, 1), (1, -1, -2)])
+def test_offdiagonal_matches_independent_surface_integral(o, d):
+    # P5 for N_xy, N_xz, N_yz: edge- and corner-touching neighbours and 2-cell
+    # offsets, every sign pattern the parity rules of the tensor distinguish.
+    # Both orders (a-faces against b-faces and b against a) are evaluated: the
+    # tensor is symmetric.
+    R = [o[i] * d[i] for i in range(3)]
+    got = newell.tensor(*R, *d)
+    for (a, b), ci in _OFFDIAG.items():
+        ref_ab = _surface_offdiag(a, b, R, d)
+        ref_ba = _surface_offdiag(b, a, R, d)
+        assert abs(ref_ab - ref_ba) < 1e-12
+        assert abs(got[ci] - ref_ab) < 1e-8 * max(abs(ref_ab), 1e-3), (o, (a, b), got[ci], ref_ab)
+
+
+def _volume_gauss(R, d, nsub=2, q=6):
+    # N(R) = -1/(4 pi V) int_target int_source d_a d_b (1/|x - y|) dy dx by a
+    # product Gauss-Legendre rule over both cells (nsub panels of q nodes per
+    # axis and cell); valid where the cells are apart, so the kernel is smooth
+    t, w = np.polynomial.legendre.leggauss(q)
+    nodes, wts = [], []
+    for i in range(3):
+        h = d[i] / nsub
+        xs = np.concatenate([-d[i] / 2 + (k + 0.5) * h + 0.5 * h * t for k in range(nsub)])
+        nodes.append(xs)
+        wts.append(np.tile(0.5 * h * w, nsub))
+    X = np.stack(np.meshgrid(*nodes, indexing="ij"), -1).reshape(-1, 3)
+    W = np.einsum("i,j,k->ijk", *wts).ravel()
+    acc = np.zeros(6)
+    for p in range(X.shape[0]):                      # target node x = R + X[p]
+        r = (np.asarray(R) + X[p])[None, :] - X     # x - y for every source node y
+        r2 = (r * r).sum(1)
+        inv5 = W / (r2 * r2 * np.sqrt(r2))
+        K = [(3 * r[:, 0] ** 2 - r2) @ inv5, (3 * r[:, 1] ** 2 - r2) @ inv5, (3 * r[:, 2] ** 2 - r2) @ inv5,
+             (3 * r[:, 0] * r[:, 1]) @ inv5, (3 * r[:, 0] * r[:, 2]) @ inv5, (3 * r[:, 1] * r[:, 2]) @ inv5]
+        acc += W[p] * np.array(K)
+    V = d[0] * d[1] * d[2]
+    return -acc / (4 * math.pi * V)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("o,d", [((2, 1, 0), (1.0, 1.0, 1.0)), ((2, 1, 1), (1.0, 1.0, 1.0)),
+                                 ((0, 2, 1), (1.0, 1.0, 1.0)), ((3, -2, 1), (1.2, 1.0, 0.8)),
+                                 ((1, 3, -2), (1.2, 1.0, 0.8)), ((4, 1, 0), (3.90625, 3.90625, 3.0)),
+                                 ((2, 2, 2), (1.0, 0.5, 0.75))])
+def test_all_components_match_volume_quadrature(o, d):
+    # The defining double volume integral of Eq. (3) by brute-force product
+    # quadrature (no f, g, triangle densities or near/far split), at offsets
+    # where the cells do not touch (r = 2 ... 4.5 cells): every component.
+    R = [o[i] * d[i] for i in range(3)]
+    got = newell.tensor(*R, *d)
+    ref = _volume_gauss(R, d)
+    assert np.abs(got - ref).max() < 1e-10 * np.abs(ref).max(), (o, d, got, ref)
+
+
+@pytest.mark.parametrize("o", [(1, 1, 0), (1, 0, 1), (2, 1, 1), (-1, 2, 1), (0, 0, 0)])
+def test_tensor_is_additive_over_subcells(o):
+    # A 2 x 2 x 2 cell is the union of eight half-size cells: its tensor at
+    # offset R is the target-average of the source sum over the subcells,
+    # N_big(R) = (1/8) sum_i sum_j N_small(R + s_i - s_j).  Off-centre offsets
+    # make all three off-diagonal components non-zero and take the small-cell
+    # tensor through every argument pattern of f and g.
+    D = (1.2, 1.0, 0.8)
+    d = tuple(v / 2 for v in D)
+    R = np.array([o[i] * D[i] for i in range(3)])
+    subs = [np.array([(i - 0.5) * d[0], (j - 0.5) * d[1], (k - 0.5) * d[2]])
+            for i in (0, 1) for j in (0, 1) for k in (0, 1)]
+    acc = np.zeros(6)
+    for si in subs:
+        for sj in subs:
+            acc += newell.tensor(*(R + si - sj), *d)
+    acc /= 8.0
+    big = newell.tensor(*R, *D)
+    # rounding of the closed forms' differences: ~1e-15 absolute at these offsets
+    assert np.abs(acc - big).max() < 1e-11 * max(np.abs(big).max(), 1e-3), (o, acc, big)
