@@ -57,7 +57,7 @@ extern "C" {
 #define MAGX_EDTYPE     -3   /* unknown element type */
 #define MAGX_EWORKSPACE -4   /* reserved: buffer sizes are the caller's contract (see magx_sizes) */
 #define MAGX_EHIP       -5   /* a HIP call failed */
-#define MAGX_ENONFINITE -6   /* reserved: non-finite state */
+#define MAGX_ENONFINITE -6   /* magx_status: a checked call produced a NaN or infinite value */
 #define MAGX_ESTATE     -7   /* reverse mode or checkpointed rollout asked for while a bias schedule is set */
 
 /* ---- field terms (bit mask), Eq. (2) -------------------------------------- */
@@ -86,7 +86,13 @@ typedef struct {
  *   terms  bit mask of MAGX_* field terms
  *   renorm 0: never renormalise; 1: renormalise the new state only;
  *          2: renormalise every RK stage input and the new state (default)
- *   check_finite  reserved, must be 0 or 1 */
+ *   check_finite  0 or 1.  With 1, the call clears a flag word at the start of
+ *          its workspace and every kernel that writes a field, a state or a
+ *          gradient sets it when one of its outputs is NaN or infinite
+ *          (renormalisation keeps |m| = 1, so a non-finite value means the
+ *          step size or the input was unusable); magx_status reads it.  The
+ *          computation itself is unchanged.  magx_llg_rhs (no workspace)
+ *          ignores the flag. */
 typedef struct {
     double Ms, A, D, Ku;
     double eK[3];
@@ -249,6 +255,17 @@ int magx_rollout_backward(magx_ctx* ctx, const void* ckpt_store, const magx_para
  * as -(mu0 Ms/2) m.H_demag. */
 int magx_energy(magx_ctx* ctx, const void* m, const magx_params* p, void* e_out,
                 void* ws, void* stream);
+
+/* Outcome of the last call on ctx made with check_finite = 1: waits for the
+ * stream of that call, then returns MAGX_ENONFINITE if one of its kernels met
+ * a NaN or infinite output, MAGX_OK if none did (or if no call on ctx has
+ * asked for the check yet), MAGX_EHIP if the wait or the read failed, and
+ * MAGX_EINVAL for a NULL ctx.  The workspace of that call must still be
+ * allocated.  A checked call clears the flag at its start, so the outcome
+ * belongs to that call alone; a checkpointed rollout counts as one call.
+ * Non-finite values propagate through every later step and stage, so
+ * checking the last call of a sequence covers the sequence. */
+int magx_status(magx_ctx* ctx);
 
 /* Number of effective-field evaluations (FFT convolutions of a state)
  * enqueued through this context so far. */

@@ -333,6 +333,23 @@ __device__ __forceinline__ void local_field_pair(const R* __restrict__ f, const 
     }
 }
 
+// Non-finite detection (calls made with check_finite): true if any of the
+// n values is NaN or infinite; note_nonfinite sets the flag word with one
+// atomic from the first lane of every wave that met such a value (called by
+// all active lanes of the wave).
+template <typename R, int n>
+__device__ __forceinline__ bool any_nonfinite(const R* v) {
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < n; ++i) bad = bad || !isfinite(v[i]);
+    return bad;
+}
+
+__device__ __forceinline__ void note_nonfinite(unsigned* flag, bool bad) {
+    const unsigned long long b = __ballot(bad);
+    if (b != 0ull && __lane_id() == (unsigned)(__ffsll((long long)b) - 1)) atomicOr(flag, 1u);
+}
+
 template <typename R>
 __device__ __forceinline__ void cross3(const R a[3], const R b[3], R o[3]) {
     o[0] = a[1] * b[2] - a[2] * b[1];

@@ -13,7 +13,6 @@
 //  * yinv : inverse y FFT; only rows y < ny (inside the box) are written.
 // FFT pass twiddles come from a two-level LDS table filled by each block.
 #include <algorithm>
-#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -565,18 +564,6 @@ static hipError_t run_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t
     return hipGetLastError();
 }
 
-// Tiles of 256 x 16 < Py * ty <= 256 x 32 elements (64 KiB in single
-// precision): 256 threads of 32 elements, or with MAGX_Y_THREADS=512 512
-// threads of 16.
-static bool y_wide(const Plan& pl) {
-    static const int nt = [] {
-        const char* e = std::getenv("MAGX_Y_THREADS");
-        return e ? std::atoi(e) : 256;
-    }();
-    (void)pl;
-    return nt != 256;
-}
-
 // Tiles of more than 256 x 32 elements (up to 128 KiB of LDS, one block per
 // CU): 512 threads of 32 elements (two radix-32 passes for Py = 1024).
 static bool y_huge(const Plan& pl) { return (long long)pl.Py * pl.ty > (long long)kNT * 32; }
@@ -585,7 +572,7 @@ static bool y_huge(const Plan& pl) { return (long long)pl.Py * pl.ty > (long lon
 template <typename R>
 static int y_lg(const Plan& pl) {
     if (pl.Px != pl.Py || 2 * pl.nx != pl.Px || 2 * pl.ny != pl.Py) return 0;
-    if (pl.lgPy < 8 || pl.lgPy > 11 || y_wide(pl)) return 0;
+    if (pl.lgPy < 8 || pl.lgPy > 11) return 0;
     if (pl.ty != (1 << ytile_lg<R>(pl.lgPy)) || pl.Sx != pl.Px / 2 + 16) return 0;
     return pl.lgPy;
 }
@@ -610,9 +597,11 @@ hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) 
             default: break;
         }
     }
+    // tiles of up to 256 x 16 elements: 256 threads of 16; up to 256 x 32
+    // (64 KiB in single precision): 256 threads of 32
     if (!em_big((long long)pl.Py * pl.ty)) return run_yfwd<R, 16, kNT>(pl, X1, X2, s);
     if (y_huge(pl)) return run_yfwd<R, 32, 512>(pl, X1, X2, s);
-    return y_wide(pl) ? run_yfwd<R, 16, 512>(pl, X1, X2, s) : run_yfwd<R, 32, kNT>(pl, X1, X2, s);
+    return run_yfwd<R, 32, kNT>(pl, X1, X2, s);
 }
 
 template <typename R>
@@ -636,7 +625,7 @@ hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) 
     }
     if (!em_big((long long)pl.Py * pl.ty)) return run_yinv<R, 16, kNT>(pl, X2, Y1, s);
     if (y_huge(pl)) return run_yinv<R, 32, 512>(pl, X2, Y1, s);
-    return y_wide(pl) ? run_yinv<R, 16, 512>(pl, X2, Y1, s) : run_yinv<R, 32, kNT>(pl, X2, Y1, s);
+    return run_yinv<R, 32, kNT>(pl, X2, Y1, s);
 }
 
 template <typename R, int EM>
@@ -678,7 +667,6 @@ static hipError_t run_zconvr(const Plan& pl, void* X2, const void* spec, float M
 }
 
 static hipError_t run_zreg(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
-    if (pl.tz == 16) return pl.Pz == 64 ? run_zconvr<16, 8>(pl, X2, spec, Ms, s) : hipErrorInvalidValue;
     switch (pl.Pz) {
         case 8: return run_zconvr<64, 1>(pl, X2, spec, Ms, s);
         case 16: return run_zconvr<32, 2>(pl, X2, spec, Ms, s);

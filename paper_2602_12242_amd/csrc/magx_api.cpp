@@ -3,7 +3,6 @@
 // HIP kernels of tensor.hip, conv.hip and pencil.hip.
 #include <algorithm>
 #include <cmath>
-#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -24,6 +23,12 @@ struct magx_ctx {
     double time;
     long long heff_count;
     int device;
+    // non-finite check: flag word of the last call made with check_finite = 1
+    // (in that call's workspace) and its stream; chk_hold keeps the flag of
+    // a compound call (checkpointed rollout) armed across its inner calls
+    unsigned* chk_flag;
+    hipStream_t chk_stream;
+    int chk_hold;
     // launch timing of one kernel family (diagnostics)
     int prof_kind;
     size_t prof_used;
@@ -109,11 +114,6 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
     // block of 512 threads per CU, 16 columns = whole 128-byte row segments)
     const int y_cplx = dt == MAGX_F32 ? 2 * lds_cplx : lds_cplx;
     p.ty = std::min(16, pow2_floor(y_cplx / p.Py));
-    // tuning override of the y tile width (power of two within the LDS budget)
-    if (const char* e = std::getenv("MAGX_TILE_Y")) {
-        const int t = std::atoi(e);
-        if (t >= 1 && (t & (t - 1)) == 0 && (long long)t * p.Py <= y_cplx) p.ty = t;
-    }
     // z tile: data 3*Pz*tz complex in LDS (at most 64 KiB), at most 16 FFT
     // elements per thread when possible (32 at most), and at most 4 tensor
     // items (kz <= Pz/2, column) per thread: (Pz/2+1)*tz <= 4*256
@@ -126,46 +126,28 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
         int tz = 64;
         while (tz > 1 && !fits(tz, 16)) tz >>= 1;
         if (!fits(tz, 32)) return MAGX_ESIZE;
-        // tuning override of the z tile width (power of two within the budgets)
-        if (const char* e = std::getenv("MAGX_TILE_Z")) {
-            const int t = std::atoi(e);
-            if (t >= 1 && (t & (t - 1)) == 0 && fits(t, 32)) tz = t;
-        }
         // single precision with Pz = 8 ... 64: the register-resident z pass (Pz/8 T threads per
-        // T-column tile; T = 32, 64 for Pz = 8, 16 selectable for Pz = 64)
-        static const bool zreg_on = [] {
-            const char* e = std::getenv("MAGX_ZREG");
-            return !(e && std::atoi(e) == 0);
-        }();
-        static const int zreg_t = [] {
-            const char* e = std::getenv("MAGX_ZREG_T");
-            return (e && std::atoi(e) == 16) ? 16 : 32;
-        }();
-        p.zreg = (zreg_on && dt == MAGX_F32 && p.Pz >= 8 && p.Pz <= 64) ? 1 : 0;
-        if (p.zreg) tz = p.Pz == 64 ? zreg_t : (p.Pz == 8 ? 64 : 32);   // at least 64 threads per block
+        // T-column tile; T = 32, and 64 for Pz = 8 so a block has at least 64 threads)
+        p.zreg = (dt == MAGX_F32 && p.Pz >= 8 && p.Pz <= 64) ? 1 : 0;
+        if (p.zreg) tz = p.Pz == 8 ? 64 : 32;
         p.tz = tz;
         p.ntz = (p.Hx + tz - 1) / tz;
         if ((long long)p.Hy * p.ntz * 6 * p.Hz * tz >= (1LL << 31)) return MAGX_ESIZE;
     }
     p.np = std::max(1, 1024 / p.Lh);
-    // tuning override of the pencils per block (within the register budget)
-    if (const char* e = std::getenv("MAGX_PENCILS")) {
-        const int t = std::atoi(e);
-        if (t >= 1 && t <= p.np) p.np = t;
-    }
     const int npen = p.ny * p.nz;
     if (p.np > npen) p.np = npen;
     // pencil blocks never straddle two members (the last one of a member may be
     // ragged); with ny >= np and nz > 1 a block holds np rows of one plane and
     // blocks run through z fastest
     p.pencil_zmajor = (p.ny >= p.np && p.nz > 1) ? 1 : 0;
-    if (const char* e = std::getenv("MAGX_PENCIL_ORDER")) p.pencil_zmajor = (std::atoi(e) == 1 && p.nz > 1) ? 1 : 0;
     p.blocks_per_member = p.pencil_zmajor ? p.nz * ((p.ny + p.np - 1) / p.np) : (npen + p.np - 1) / p.np;
     p.pencil_blocks = nbatch * p.blocks_per_member;
     const size_t es = (size_t)p.esize;
     const long long N = p.ncell * nbatch;
     p.field_bytes = (size_t)3 * N * es;
     size_t off = 0;
+    p.off_flag = off; off = 256;
     p.off_x1 = off; off = align256(off + (size_t)3 * nbatch * p.nz * p.ny * p.Sx * 2 * es);
     p.off_x2 = off; off = align256(off + (size_t)3 * nbatch * p.nz * p.Py * p.Sx * 2 * es);
     for (int i = 0; i < 5; ++i) { p.off_f[i] = off; off = align256(off + p.field_bytes); }
@@ -277,6 +259,39 @@ static int ensure_twiddles(hipStream_t s, int* device) {
 
 static inline char* bptr(void* p, size_t off) { return static_cast<char*>(p) + off; }
 
+// Non-finite check of a call made with check_finite = 1: the flag word at the
+// start of its workspace is cleared on the call's stream (by a kernel) and
+// handed to the kernels, which set it on a NaN or infinite output; magx_status
+// reads the flag of the last such call.  Inside a compound call (chk_hold) the
+// flag armed at its start is kept.
+template <typename R>
+static int arm_finite_check(magx_ctx* c, const magx_params* p, void* ws, hipStream_t s, Phys<R>& ph) {
+    ph.nf = nullptr;
+    if (!p->check_finite) return MAGX_OK;
+    unsigned* flag = reinterpret_cast<unsigned*>(bptr(ws, c->pl.off_flag));
+    if (!(c->chk_hold && c->chk_flag == flag)) {
+        if (launch_fill_zero(reinterpret_cast<double*>(flag), 1, s) != hipSuccess) return MAGX_EHIP;
+        c->chk_flag = flag;
+        c->chk_stream = s;
+    }
+    ph.nf = flag;
+    return MAGX_OK;
+}
+
+// Arms the check once for a compound call and holds it until destruction.
+struct CheckHold {
+    magx_ctx* c;
+    int prev;
+    CheckHold(magx_ctx* ctx) : c(ctx), prev(ctx->chk_hold) {}
+    int arm(const magx_params* p, void* ws, hipStream_t s) {
+        Phys<float> tmp{};
+        const int rc = arm_finite_check<float>(c, p, ws, s, tmp);
+        c->chk_hold = 1;
+        return rc;
+    }
+    ~CheckHold() { c->chk_hold = prev; }
+};
+
 // Convolution passes on X1 (input, overwritten with Y1) using X2.
 template <typename R>
 static int conv_passes(magx_ctx* c, void* ws, R Ms, hipStream_t s) {
@@ -304,6 +319,8 @@ static int do_heff(magx_ctx* c, const R* m, const magx_params* p, R* H, void* ws
                    double* e_out) {
     const Plan& pl = c->pl;
     Phys<R> ph = phys_at<R>(c, p, c->time);
+    int rc0 = arm_finite_check<R>(c, p, ws, s, ph);
+    if (rc0) return rc0;
     void* X1 = bptr(ws, pl.off_x1);
     double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
     if (p->terms & MAGX_DEMAG) {
@@ -346,6 +363,8 @@ static int do_step(magx_ctx* c, R* m, const magx_params* p, double dt, int nstep
                    hipStream_t s) {
     const Plan& pl = c->pl;
     Phys<R> ph = make_phys<R>(pl, p, c->hbias_members, c->ms_profile);
+    int rc0 = arm_finite_check<R>(c, p, ws, s, ph);
+    if (rc0) return rc0;
     const bool timed = !c->sched_t.empty();
     static const double kC[4] = {0.0, 0.5, 0.5, 1.0};   // stage times of classical RK4
     const bool demag = (p->terms & MAGX_DEMAG) != 0;
@@ -378,7 +397,8 @@ static int do_step(magx_ctx* c, R* m, const magx_params* p, double dt, int nstep
             a.dt = (R)dt;
             a.want_next = !(n == nsteps - 1 && st == 4);
             ProfScope ps(c, kProfStage, s);
-            const Phys<R> phs = timed ? phys_at<R>(c, p, c->time + (n + kC[st - 1]) * dt) : ph;
+            Phys<R> phs = timed ? phys_at<R>(c, p, c->time + (n + kC[st - 1]) * dt) : ph;
+            phs.nf = ph.nf;
             if (launch_stage<R>(pl, phs, X1, X1, a, s) != hipSuccess) return MAGX_EHIP;
         }
     }
@@ -399,6 +419,9 @@ static int do_step_euler(magx_ctx* c, R* m, const magx_params* p, double dt, int
     R* W = reinterpret_cast<R*>(bptr(ws, pl.off_f[1]));
     R* cur = m;
     R* oth = W;
+    Phys<R> ph0 = make_phys<R>(pl, p, c->hbias_members, c->ms_profile);
+    int rc0 = arm_finite_check<R>(c, p, ws, s, ph0);
+    if (rc0) return rc0;
     if (demag) {
         ProfScope ps(c, kProfXfwd, s);
         if (launch_xfwd<R>(pl, cur, X1, static_cast<const R*>(c->ms_profile), s) != hipSuccess) return MAGX_EHIP;
@@ -418,7 +441,8 @@ static int do_step_euler(magx_ctx* c, R* m, const magx_params* p, double dt, int
         a.stage = 0;
         a.dt = (R)dt;
         a.want_next = n < nsteps - 1;
-        const Phys<R> ph = phys_at<R>(c, p, c->time + n * dt);
+        Phys<R> ph = phys_at<R>(c, p, c->time + n * dt);
+        ph.nf = ph0.nf;
         ProfScope ps(c, kProfStage, s);
         if (launch_stage<R>(pl, ph, X1, X1, a, s) != hipSuccess) return MAGX_EHIP;
         std::swap(cur, oth);
@@ -433,6 +457,8 @@ static int do_step_backward(magx_ctx* c, const R* tape, int nsteps, const magx_p
                             R* gHbias, void* ws, hipStream_t s, bool fresh = true, bool finish = true) {
     const Plan& pl = c->pl;
     Phys<R> ph = make_phys<R>(pl, p, c->hbias_members, c->ms_profile);
+    int rc0 = arm_finite_check<R>(c, p, ws, s, ph);
+    if (rc0) return rc0;
     const bool demag = (p->terms & MAGX_DEMAG) != 0;
     void* X1 = bptr(ws, pl.off_x1);
     R* xi5 = reinterpret_cast<R*>(bptr(ws, pl.off_f[0]));
@@ -491,6 +517,8 @@ static int do_heff_backward(magx_ctx* c, const R* gH, const magx_params* p, R* g
                             hipStream_t s) {
     const Plan& pl = c->pl;
     Phys<R> ph = make_phys<R>(pl, p, c->hbias_members, c->ms_profile);
+    int rc0 = arm_finite_check<R>(c, p, ws, s, ph);
+    if (rc0) return rc0;
     void* X1 = bptr(ws, pl.off_x1);
     double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
     if (launch_fill_zero(part, (long long)pl.pencil_blocks * 8, s) != hipSuccess) return MAGX_EHIP;
@@ -538,7 +566,9 @@ static int do_step_mri(magx_ctx* c, R* m, const magx_params* p, double dt, doubl
                        hipStream_t s) {
     static const KnothWolke kw;
     const Plan& pl = c->pl;
-    const Phys<R> ph = make_phys<R>(pl, p, c->hbias_members, c->ms_profile);
+    Phys<R> ph = make_phys<R>(pl, p, c->hbias_members, c->ms_profile);
+    int rc0 = arm_finite_check<R>(c, p, ws, s, ph);
+    if (rc0) return rc0;
     Phys<R> pfast = ph, pslow = ph;     // both keep the ghost rule of the full field
     pfast.terms = ph.terms & MAGX_EXCH;
     pslow.terms = ph.terms & ~MAGX_EXCH;
@@ -578,6 +608,7 @@ static int do_step_mri(magx_ctx* c, R* m, const magx_params* p, double dt, doubl
             if (timed) {
                 pslow_t = phys_at<R>(c, p, c->time + (n + kw.c[i]) * dt);
                 pslow_t.terms = ph.terms & ~MAGX_EXCH;
+                pslow_t.nf = ph.nf;
             }
             if (launch_mri_slow<R>(pl, pslow_t, X1, cur, demag ? 1 : 0, Sout, Sa, Sb, (R)kw.w[i][0],
                                    (R)kw.w[i][1], (R)kw.w[i][i], rf, s) != hipSuccess)
@@ -647,6 +678,9 @@ int magx_tensor_init_batched(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, 
     c->device = dev;
     c->prof_kind = 0;
     c->prof_used = 0;
+    c->chk_flag = nullptr;
+    c->chk_stream = nullptr;
+    c->chk_hold = 0;
     *ctx = c;
     return MAGX_OK;
 }
@@ -803,6 +837,9 @@ int magx_rollout_forward(magx_ctx* ctx, void* m, const magx_params* p, double dt
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t fb = ctx->pl.field_bytes;
     const long long n3 = 3 * ctx->pl.ncell * ctx->pl.nbatch;
+    CheckHold hold(ctx);
+    rc = hold.arm(p, ws, s);
+    if (rc) return rc;
     for (int n0 = 0, seg = 0; n0 < nsteps; n0 += ckpt, ++seg) {
         void* slot = bptr(ckpt_store, (size_t)seg * fb);
         hipError_t e = ctx->pl.dtype == MAGX_F32
@@ -825,6 +862,9 @@ int magx_rollout_backward(magx_ctx* ctx, const void* ckpt_store, const magx_para
     if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
     const Plan& pl = ctx->pl;
+    CheckHold hold(ctx);
+    rc = hold.arm(p, ws, s);
+    if (rc) return rc;
     double* part = reinterpret_cast<double*>(bptr(ws, pl.off_part));
     if (launch_fill_zero(part, (long long)pl.pencil_blocks * 8, s) != hipSuccess) return MAGX_EHIP;
     hipError_t e;
@@ -858,6 +898,15 @@ int magx_rollout_backward(magx_ctx* ctx, const void* ckpt_store, const magx_para
 }
 
 long long magx_heff_count(const magx_ctx* ctx) { return ctx ? ctx->heff_count : -1; }
+
+int magx_status(magx_ctx* ctx) {
+    if (!ctx) return MAGX_EINVAL;
+    if (!ctx->chk_flag) return MAGX_OK;
+    if (hipStreamSynchronize(ctx->chk_stream) != hipSuccess) return MAGX_EHIP;
+    unsigned v = 0;
+    if (hipMemcpy(&v, ctx->chk_flag, sizeof v, hipMemcpyDeviceToHost) != hipSuccess) return MAGX_EHIP;
+    return v ? MAGX_ENONFINITE : MAGX_OK;
+}
 
 int magx_spectrum_layout(const magx_ctx* ctx, int dims[5]) {
     if (!ctx || !dims) return MAGX_EINVAL;

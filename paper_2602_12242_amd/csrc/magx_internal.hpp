@@ -37,8 +37,9 @@ struct Plan {
     int ntz;                    // column tiles of the z pass (and of the tensor spectrum)
     int zreg;                   // z pass held in registers (single precision, Pz = 8 ... 64)
     int pencil_blocks;
-    // workspace layout (bytes)
-    size_t off_x1, off_x2, off_f[5], off_part, ws_bytes;
+    // workspace layout (bytes): the non-finite flag word first, then X1, X2,
+    // five fields and the per-block partials
+    size_t off_flag, off_x1, off_x2, off_f[5], off_part, ws_bytes;
     size_t field_bytes;
     size_t tape_step_bytes, tape_extra_bytes;
     size_t spectrum_bytes, scratch_bytes;
@@ -65,6 +66,8 @@ struct Phys {
     R dx, dy;             // ghost offsets
     unsigned terms;
     int renorm;
+    unsigned* nf;         // non-finite flag (device word, set to 1 by any wave that meets a
+                          // non-finite output), or null when the call does not check
 };
 
 hipError_t launch_twiddle_init(hipStream_t s);

@@ -76,6 +76,7 @@ __global__ void __launch_bounds__(kNT) mri_slow_kernel(const cx<R>* __restrict__
 #pragma unroll
             for (int c = 0; c < 3; ++c) { r[0][c] += wb * b0[c]; r[1][c] += wb * b1[c]; }
         }
+        if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(r[0]) || (two && any_nonfinite<R, 3>(r[1])));
         if (S_out) store_pair(S_out, g.N, id, vec, two, S[0], S[1]);
         store_pair(r_out, g.N, id, vec, two, r[0], r[1]);
     }
@@ -141,6 +142,7 @@ __global__ void __launch_bounds__(kNT) mri_fast_kernel(const R* __restrict__ v, 
                 }
             }
         }
+        if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(xn[0]) || (two && any_nonfinite<R, 3>(xn[1])));
         store_pair(qbuf, g.N, id, vec, two, q[0], q[1]);
         store_pair(vout, g.N, id, vec, two, xn[0], xn[1]);
         if (fwd) {

@@ -124,8 +124,12 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
                 }
             }
         }
-        if (!energy) store_pair(H, g.N, id, vec, two, out[0], out[1]);
+        if (!energy) {
+            if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(out[0]) || (two && any_nonfinite<R, 3>(out[1])));
+            store_pair(H, g.N, id, vec, two, out[0], out[1]);
+        }
     }
+    if (energy && ph.nf) note_nonfinite(ph.nf, !isfinite(acc[0] + acc[1] + acc[2] + acc[3] + acc[4]));
     if (energy) {
         for (int v = 0; v < 6; ++v) {
             const double sm = block_sum(acc[v], red);
@@ -243,6 +247,9 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
                 }
             }
         }
+        if (ph.nf)
+            note_nonfinite(ph.nf, any_nonfinite<R, 3>(xn[0]) || any_nonfinite<R, 3>(H[0]) ||
+                                      (two && (any_nonfinite<R, 3>(xn[1]) || any_nonfinite<R, 3>(H[1]))));
         if (s >= 1 && s < 4) store_pair(a.acc, g.N, id, vec, two, acc[0], acc[1]);
         if (a.tapeNx) {
             if (vec) *reinterpret_cast<cx<R>*>(a.tapeNx + id) = mk<R>(nrm[0], nrm[1]);
@@ -333,6 +340,7 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
             for (int c = 0; c < 3; ++c) kap[q][c] = b4 * a.dt * xi[q][c];
             rhs_mu<R>(y4[q], kap[q], ph.a, ph.alpha, mu[q]);
         }
+        if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(xi[0]) || (two && any_nonfinite<R, 3>(xi[1])));
         store_pair(a.xi5, g.N, id, vec, two, xi[0], xi[1]);
         store_pair(a.gm, g.N, id, vec, two, xi[0], xi[1]);
         store_pair(a.kap, g.N, id, vec, two, kap[0], kap[1]);
@@ -462,6 +470,7 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
                 }
                 rhs_mu<R>(yp[q], kp[q], ph.a, ph.alpha, mup[q]);
             }
+            if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(lam[0]) || (two && any_nonfinite<R, 3>(lam[1])));
             store_pair(a.gm, g.N, id, vec, two, lam[0], lam[1]);
             store_pair(a.kap, g.N, id, vec, two, kp[0], kp[1]);
             store_pair(a.muout, g.N, id, vec, two, mup[0], mup[1]);
@@ -476,6 +485,7 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
             for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int c = 0; c < 3; ++c) lam[q][c] += yb[q][c];
+            if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(lam[0]) || (two && any_nonfinite<R, 3>(lam[1])));
             store_pair(a.gm, g.N, id, vec, two, lam[0], lam[1]);
         }
     }

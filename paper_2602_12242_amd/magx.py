@@ -56,7 +56,7 @@ EXPORTS = ("magx_sizes", "magx_sizes_batched", "magx_tensor_init", "magx_tensor_
            "magx_set_member_bias", "magx_ctx_batch", "magx_set_ms_profile", "magx_heff", "magx_llg_rhs", "magx_step", "magx_step_mri",
            "magx_step_euler", "magx_set_bias_schedule", "magx_get_time",
            "magx_heff_backward", "magx_step_backward", "magx_rollout_forward", "magx_rollout_backward",
-           "magx_energy", "magx_heff_count", "magx_ctx_info", "magx_spectrum_layout", "magx_profile_start",
+           "magx_energy", "magx_status", "magx_heff_count", "magx_ctx_info", "magx_spectrum_layout", "magx_profile_start",
            "magx_profile_stop", "magx_strerror", "magx_destroy")
 
 _lib = None
@@ -92,6 +92,7 @@ def load(path=LIB_PATH):
         "magx_rollout_forward": (i, [vp, vp, P(magx_params), d, i, i, vp, vp, vp]),
         "magx_rollout_backward": (i, [vp, vp, P(magx_params), d, i, i, vp, vp, vp, vp, vp, vp]),
         "magx_energy": (i, [vp, vp, P(magx_params), vp, vp, vp]),
+        "magx_status": (i, [vp]),
         "magx_heff_count": (ctypes.c_longlong, [vp]),
         "magx_ctx_info": (i, [vp, P(magx_grid), P(ctypes.c_int)]),
         "magx_spectrum_layout": (i, [vp, P(ctypes.c_int)]),
@@ -234,6 +235,14 @@ class Context:
                 raise ValueError(f"s: expected contiguous {self.tdtype} {shape} on {self.device}")
         _check(self.lib.magx_set_ms_profile(self.h, _ptr(s)), "magx_set_ms_profile")
         self.ms_profile = s
+
+    def status(self):
+        """magx_status: waits for the last call made with check_finite=1 and
+        returns 0 or MAGX_ENONFINITE (-6); raises on any other error."""
+        rc = int(self.lib.magx_status(self.h))
+        if rc not in (0, -6):
+            _check(rc, "magx_status")
+        return rc
 
     @property
     def heff_count(self):
