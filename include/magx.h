@@ -55,7 +55,8 @@ extern "C" {
                                 >= 2n exceeds the FFT passes' limits: Py <= 4096; Px <= 4096 (float)
                                 or 2048 (double); Pz <= 1024 */
 #define MAGX_EDTYPE     -3   /* unknown element type */
-#define MAGX_EWORKSPACE -4   /* reserved: buffer sizes are the caller's contract (see magx_sizes) */
+#define MAGX_EWORKSPACE -4   /* magx_step_static: the grid needs more than its fixed workspace;
+                                elsewhere buffer sizes are the caller's contract (see magx_sizes) */
 #define MAGX_EHIP       -5   /* a HIP call failed */
 #define MAGX_ENONFINITE -6   /* magx_status: a checked call produced a NaN or infinite value */
 #define MAGX_ESTATE     -7   /* reverse mode or checkpointed rollout asked for while a bias schedule is set */
@@ -179,6 +180,21 @@ int magx_llg_rhs(magx_ctx* ctx, const void* m, const void* H,
  * field and pre-normalisation length is recorded for magx_step_backward. */
 int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps,
               void* tape, void* ws, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): magx_step
+ * without a tape and without a caller workspace.  Its workspace is a 64 MiB
+ * array in device memory that the library holds on each GPU it runs on until
+ * the process ends (enough for a single-precision 256 x 256 x 8 grid or a
+ * double-precision 256 x 128 x 8 one); MAGX_EWORKSPACE if the context's grid
+ * and batch need more, checked before any HIP call.  Nothing is allocated:
+ * no hipMalloc, hipFree or allocating library routine.  All calls on one GPU
+ * share that array: calls that overlap on one GPU (concurrent streams or host
+ * threads) race and must be serialised by the caller; each call writes every
+ * part of it before reading it.  With check_finite the flag word is in that
+ * array too, so magx_status must be called before the next call on the GPU
+ * that uses it. */
+int magx_step_static(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps, void* stream);
 
 /* Advances m (device, in place) by nsteps forward Euler steps
  * m <- m + dt R(m) (the integrator of the paper's scaling runs, Section IV),

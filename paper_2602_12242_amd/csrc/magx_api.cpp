@@ -259,6 +259,32 @@ static int ensure_twiddles(hipStream_t s, int* device) {
 
 static inline char* bptr(void* p, size_t off) { return static_cast<char*>(p) + off; }
 
+// Workspace of magx_step_static: a file-scope device array (each GPU the
+// library runs on holds its own copy until the process ends).  Its name is a
+// host-side stand-in in host code; the device address comes from
+// hipGetSymbolAddress, taken once per device with that device current (at
+// context creation) and kept in g_static_ws.
+constexpr size_t kStaticWsBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+static std::mutex g_static_mutex;
+static void* g_static_ws[64];
+
+static int ensure_static_ws(int dev) {
+    if (dev < 0 || dev >= 64) return MAGX_EHIP;
+    std::lock_guard<std::mutex> lk(g_static_mutex);
+    if (g_static_ws[dev]) return MAGX_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MAGX_EHIP;
+    g_static_ws[dev] = ptr;
+    return MAGX_OK;
+}
+
+static void* static_ws(int dev) {
+    if (dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_static_mutex);
+    return g_static_ws[dev];
+}
+
 // Non-finite check of a call made with check_finite = 1: the flag word at the
 // start of its workspace is cleared on the call's stream (by a kernel) and
 // handed to the kernels, which set it on a NaN or infinite output; magx_status
@@ -666,6 +692,8 @@ int magx_tensor_init_batched(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, 
     int dev = 0;
     rc = ensure_twiddles(s, &dev);
     if (rc) return rc;
+    rc = ensure_static_ws(dev);
+    if (rc) return rc;
     if (build_tensor_spectrum(pl, spectrum, scratch, s) != hipSuccess) return MAGX_EHIP;
     magx_ctx* c = new (std::nothrow) magx_ctx;
     if (!c) return MAGX_EINVAL;
@@ -750,6 +778,22 @@ int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nstep
     if (ctx->pl.dtype == MAGX_F32)
         return do_step<float>(ctx, static_cast<float*>(m), p, dt, nsteps, static_cast<float*>(tape), ws, s);
     return do_step<double>(ctx, static_cast<double*>(m), p, dt, nsteps, static_cast<double*>(tape), ws, s);
+}
+
+int magx_step_static(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps, void* stream) {
+    if (!ctx || !m || nsteps < 0 || !std::isfinite(dt)) return MAGX_EINVAL;
+    int rc = check_params(p);
+    if (rc) return rc;
+    // RK4 without a tape uses the flag word, X1, X2 and three fields: the
+    // workspace prefix up to the fourth field
+    if (ctx->pl.off_f[3] > kStaticWsBytes) return MAGX_EWORKSPACE;
+    void* ws = static_ws(ctx->device);
+    if (!ws) return MAGX_EHIP;
+    if (nsteps == 0) return MAGX_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (ctx->pl.dtype == MAGX_F32)
+        return do_step<float>(ctx, static_cast<float*>(m), p, dt, nsteps, nullptr, ws, s);
+    return do_step<double>(ctx, static_cast<double*>(m), p, dt, nsteps, nullptr, ws, s);
 }
 
 int magx_step_euler(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps, void* ws, void* stream) {

@@ -53,7 +53,7 @@ class magx_size_info(ctypes.Structure):
 
 
 EXPORTS = ("magx_sizes", "magx_sizes_batched", "magx_tensor_init", "magx_tensor_init_batched",
-           "magx_set_member_bias", "magx_ctx_batch", "magx_set_ms_profile", "magx_heff", "magx_llg_rhs", "magx_step", "magx_step_mri",
+           "magx_set_member_bias", "magx_ctx_batch", "magx_set_ms_profile", "magx_heff", "magx_llg_rhs", "magx_step", "magx_step_static", "magx_step_mri",
            "magx_step_euler", "magx_set_bias_schedule", "magx_get_time",
            "magx_heff_backward", "magx_step_backward", "magx_rollout_forward", "magx_rollout_backward",
            "magx_energy", "magx_status", "magx_heff_count", "magx_ctx_info", "magx_spectrum_layout", "magx_profile_start",
@@ -83,6 +83,7 @@ def load(path=LIB_PATH):
         "magx_heff": (i, [vp, vp, P(magx_params), vp, vp, vp]),
         "magx_llg_rhs": (i, [vp, vp, vp, P(magx_params), vp, vp]),
         "magx_step": (i, [vp, vp, P(magx_params), d, i, vp, vp, vp]),
+        "magx_step_static": (i, [vp, vp, P(magx_params), d, i, vp]),
         "magx_step_mri": (i, [vp, vp, P(magx_params), d, d, i, vp, vp]),
         "magx_step_euler": (i, [vp, vp, P(magx_params), d, i, vp, vp]),
         "magx_set_bias_schedule": (i, [vp, i, P(d), P(d), d]),
@@ -273,6 +274,14 @@ class Context:
         self._chk(m, "m")
         _check(self.lib.magx_step(self.h, _ptr(m), ctypes.byref(p), float(dt), int(nsteps), _ptr(tape),
                                   _ptr(self.ws), _stream()), "magx_step")
+        return m
+
+    def step_static(self, m, p, dt, nsteps):
+        """Advances m in place by nsteps RK4 steps through magx_step_static
+        (the library's own fixed device workspace; nothing is allocated)."""
+        self._chk(m, "m")
+        _check(self.lib.magx_step_static(self.h, _ptr(m), ctypes.byref(p), float(dt), int(nsteps), _stream()),
+               "magx_step_static")
         return m
 
     def step_mri(self, m, p, dt, nsteps, dt_fast=None):

@@ -138,6 +138,7 @@ def test_entry_points_reject_null_arguments_without_a_gpu():
     assert lib.magx_energy(nul, nul, ctypes.byref(p), nul, nul, nul) == -1
     assert lib.magx_heff_count(nul) == -1
     assert lib.magx_status(nul) == -1
+    assert lib.magx_step_static(nul, nul, ctypes.byref(p), 1e-13, 1, nul) == -1
     assert lib.magx_step_euler(nul, nul, ctypes.byref(p), 1e-13, 1, nul, nul) == -1
     assert lib.magx_step_mri(nul, nul, ctypes.byref(p), 1e-13, 1e-14, 1, nul, nul) == -1
     assert lib.magx_set_bias_schedule(nul, 0, None, None, 0.0) == -1
@@ -149,7 +150,7 @@ def test_entry_points_reject_null_arguments_without_a_gpu():
 
 def test_binding_wraps_every_entry_point():
     from paper_2602_12242_amd import magx
-    for name in ("heff", "llg_rhs", "step", "status", "step_mri", "step_euler", "set_bias_schedule", "heff_backward", "step_backward", "rollout_forward",
+    for name in ("heff", "llg_rhs", "step", "step_static", "status", "step_mri", "step_euler", "set_bias_schedule", "heff_backward", "step_backward", "rollout_forward",
                  "rollout_backward", "energy", "set_member_bias", "set_ms_profile", "spectrum_array", "profile_start",
                  "profile_stop", "tape", "checkpoint_store", "field"):
         assert callable(getattr(magx.Context, name)), name
