@@ -75,6 +75,16 @@ CASES = {
     # Pz = 1024: the longest z transform, one column per z tile
     "tall": ((3, 2, 300), (2e-9, 2e-9, 1e-9),
              dict(Ms=8e5, A=1.3e-11, alpha=0.1, Hbias=(0, 0, 1e4), terms=1 | 2 | 16)),
+    # the planes of the timed workloads: 512 x 512 (pencil lines with
+    # compile-time geometry at Lh = 512, y passes at Py = 1024 with 128 KiB
+    # tiles of 512 threads) and 256 x 256 (Lh = 256, Py = 512; with nz = 4,
+    # Pz = 8: the register-resident z pass without an exchange)
+    "sq512": ((512, 512, 2), (2.5e-9, 2.5e-9, 2.5e-9),
+              dict(Ms=8e5, A=1.3e-11, D=1e-3, Ku=3e5, eK=(0.0, 0.6, 0.8), alpha=0.5, Hbias=(2e3, -1e3, 4e3),
+                   terms=ALL)),
+    "sq256": ((256, 256, 4), (2e-9, 2e-9, 2e-9),
+              dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, eK=(0, 0, 1), alpha=0.1, Hbias=(1e3, 2e3, -3e3),
+                   terms=ALL)),
 }
 
 
@@ -126,7 +136,7 @@ def _dev(a, dtype):
     return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=t)
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "film", "column", "tiles", "thick"])
+@pytest.mark.parametrize("name", ["tiny_all", "film", "column", "tiles", "thick", "sq256"])
 def test_tensor_spectrum_matches_oracle(name):
     n, d, _ = CASES[name]
     g, spec, P = _oracle_setup(name)
@@ -169,7 +179,7 @@ def test_llg_rhs_matches_oracle(dtype):
 
 
 @pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "film", "line", "cell", "tiles", "thick", "long_y",
-                                  "pow2_256", "pow2_1024"])
+                                  "pow2_256", "pow2_1024", "sq512", "sq256"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_one_rk4_step_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -206,7 +216,7 @@ def test_several_steps_f64_and_norm(renorm):
         assert np.abs(np.sqrt(np.sum(out ** 2, axis=0)) - 1).max() < 1e-15
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "film", "tiles", "thick", "pow2_256"])
+@pytest.mark.parametrize("name", ["tiny_all", "film", "tiles", "thick", "pow2_256", "sq512"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_energy_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -222,7 +232,7 @@ def test_energy_matches_oracle(name, dtype):
     assert abs(e[5] - ref["total"]) <= (1e-11 if dtype == 1 else 2e-5) * scale
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "pow2_256"])
+@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "pow2_256", "sq512", "sq256"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_heff_backward_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -238,7 +248,7 @@ def test_heff_backward_matches_oracle(name, dtype):
 
 
 @pytest.mark.parametrize("renorm", [0, 1, 2])
-@pytest.mark.parametrize("name", ["tiny_all", "tiles", "pow2_256"])
+@pytest.mark.parametrize("name", ["tiny_all", "tiles", "pow2_256", "sq512", "sq256"])
 def test_step_backward_matches_oracle(name, renorm):
     n, d, mat = CASES[name]
     mat = dict(mat, renorm=renorm)

@@ -17,7 +17,8 @@ random states stand in for the standard-problem initial conditions):
            D 2.5e-3, alpha 0.1, 100 steps of 5e-14 s, loss = masked mean m_z,
            checkpoint every 10 steps
   large    1024x1024x64 cells of 3 nm, Ms 8e5, A 1.3e-11, alpha 0.02,
-           10 mT along a seeded random direction, 50 steps, checkpoint 10
+           10 mT along a seeded random direction, 50 steps, checkpoint 10,
+           the adjoint workload's loss form with its own mask (seed 2005)
   sp4_fine the Standard Problem 4 film (500 x 125 x 3.125 nm) at 0.78125 nm
            cells, 640x160x4, permalloy, field 1 (mu0 H = (-24.6, 4.3, 0) mT),
            demag + exchange + Zeeman: the integrator comparison of the paper
@@ -98,7 +99,7 @@ def _workloads():
         "large": Workload("large", (1024, 1024, 64), (3e-9, 3e-9, 3e-9), 8.0e5, 1.3e-11, 0.02,
                           TERM_DEMAG | TERM_EXCH | TERM_ZEEMAN,
                           Hbias=tuple(h10 * c for c in d10), steps=50, dt=1e-13, seed=1005,
-                          smooth=3, ckpt=10),
+                          smooth=3, ckpt=10, extra=dict(mask_seed=2005)),
         "sp4_fine": Workload("sp4_fine", (640, 160, 4), (0.78125e-9, 0.78125e-9, 0.78125e-9), 8.0e5, 1.3e-11,
                              0.02, TERM_DEMAG | TERM_EXCH | TERM_ZEEMAN,
                              Hbias=(-0.0246 / MU0, 0.0043 / MU0, 0.0), steps=5, dt=2.5e-14, seed=1006,
