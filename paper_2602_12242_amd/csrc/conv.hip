@@ -12,6 +12,8 @@
 //           has a register-resident variant (zconvr).
 //  * yinv : inverse y FFT; only rows y < ny (inside the box) are written.
 // FFT pass twiddles come from a two-level LDS table filled by each block.
+// yfwd, zconv and yinv write their outputs with streaming stores, and yinv
+// reads its input with streaming loads (see st_stream).
 #include <algorithm>
 #include <map>
 #include <mutex>
@@ -121,7 +123,7 @@ __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, 
         cx<R>* dst = X2 + plane * Py * (long long)Sx + kx0;
         const int ncol = min(T, Hx - kx0);
         auto store = [&](int b, int j, cx<R> v) {
-            if (b < ncol) dst[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b] = v;
+            if (b < ncol) st_stream<R>(&dst[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b], v);
         };
         auto next = [&]() {
             if (un < pw.u1)
@@ -150,7 +152,7 @@ __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, 
         const cx<R>* src = X2 + plane * Py * (long long)Sx + kx0;
         const int ncol = min(T, Hx - kx0);
         return [=](int b, int j) -> cx<R> {
-            if (b < ncol) return src[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b];
+            if (b < ncol) return ld_stream<R>(&src[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b]);
             return mk<R>(0, 0);
         };
     };
@@ -167,7 +169,7 @@ __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, 
         const int ncol = min(T, Hx - kx0);
         // only rows inside the box are written
         auto store = [&](int b, int j, cx<R> v) {
-            if (j < ny && b < ncol) dst[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b] = v;
+            if (j < ny && b < ncol) st_stream<R>(&dst[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b], v);
         };
         auto next = [&]() {
             if (un < pw.u1)
@@ -274,7 +276,8 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
         const int ncol = min(T, Hx - d.kx0);
         auto store = [&](int b, int j, cx<R> v) {
             const int c = b >> lgT, col = b & (T - 1);
-            if (j < nz && col < ncol) base[(unsigned)c * (unsigned)comp_stride + umul24((unsigned)j, (unsigned)plane_stride) + (unsigned)col] = v;
+            if (j < nz && col < ncol)
+                st_stream<R>(&base[(unsigned)c * (unsigned)comp_stride + umul24((unsigned)j, (unsigned)plane_stride) + (unsigned)col], v);
         };
         auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
         auto none_store = [&](int, int, cx<R>) {};
@@ -486,7 +489,7 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
             for (int n1 = 0; n1 < 4; ++n1) {
                 const int z = g + G * n1;
                 if (okc && z < nz)
-                    base[(unsigned)c * comp_stride + (unsigned)z * plane_stride + (unsigned)col] = v[n1];
+                    st_stream<R>(&base[(unsigned)c * comp_stride + (unsigned)z * plane_stride + (unsigned)col], v[n1]);
             }
         }
         __syncthreads();   // the next tile's forward exchange rewrites E

@@ -523,6 +523,24 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nblocks) {
     return x * q + min(x, r) + i;
 }
 
+// Streaming (non-temporal) global accesses of complex values.  A pass whose
+// output is read only by the next pass stores it this way, and the inverse y
+// pass loads its input this way: measured at 512 x 512 x 32, the consumer of
+// streamed data runs faster (inverse y pass 155 -> 126 us, z pass 229 -> 217 us)
+// than when the same lines are written through the caches.
+template <typename R> __device__ __forceinline__ void st_stream(cx<R>* p, cx<R> v) {
+    typedef R V __attribute__((ext_vector_type(2)));
+    V t;
+    t.x = v.x;
+    t.y = v.y;
+    __builtin_nontemporal_store(t, reinterpret_cast<V*>(p));
+}
+template <typename R> __device__ __forceinline__ cx<R> ld_stream(const cx<R>* p) {
+    typedef R V __attribute__((ext_vector_type(2)));
+    const V t = __builtin_nontemporal_load(reinterpret_cast<const V*>(p));
+    return mk<R>(t.x, t.y);
+}
+
 __host__ __device__ inline int ilog2(int v) {
     int r = 0;
     while ((1 << r) < v) ++r;
