@@ -197,7 +197,7 @@ int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nstep
 int magx_step_static(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps, void* stream);
 
 /* Advances m (device, in place) by nsteps forward Euler steps
- * m <- m + dt R(m) (the integrator of the paper's scaling runs, Section IV),
+ * m <- m + dt R(m) (the integrator of the paper's scaling runs, Section III-E),
  * one field evaluation per step, renormalising the new state when
  * p->renorm >= 1.  ws: workspace of workspace_bytes. */
 int magx_step_euler(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps,
