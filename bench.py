@@ -9,10 +9,19 @@ alpha 0.5, seeded smoothed random start; the loss seed is the gradient of
 the masked mean of m_z).  Inputs are resident in HBM before the timed
 region.  Prints one JSON line.
 
-Also reported (outside the timed region): H_eff Mcells/s and forward RK4
-steps/s in float32 and float64, the float32-vs-float64 errors, the live
-roofline of the dominant kernel (HIP events on its stream), and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+Also reported, outside the timed region:
+* the live roofline of the dominant kernel (HIP events on its stream) and
+  the whole step's fraction under the algorithmic bytes model;
+* per workload (film 128x32x1, dmi 256x256x16, demag 512x512x32, adjoint
+  256x256x8, large 1024x1024x64): H_eff Mcells/s and RK4 steps/s in float32
+  and float64 with their fractions of the HBM roofline under the bytes model,
+  the errors of H_eff and of one step against the FP64 oracle (stored values
+  at seeded cells, written by tests/golden/make_workload_golden.py), float32
+  against float64 after the workload's N steps, the adjoint workload's
+  gradient against the oracle's, the large workload's forward+adjoint rate,
+  and the FP64 oracle's own rates on a sample of each workload;
+* the Standard Problem 4 integrator comparison and the batched film;
+* the FP64 CPU oracle timed on a bounded sample of the headline workload.
 """
 import argparse
 import hashlib
@@ -52,6 +61,45 @@ def kernel_bytes(kind, n, es):
     if kind == "xfwd":
         return 3 * N * es + x1
     raise ValueError(kind)
+
+
+def stage_bytes(s, taped=False):
+    """Algorithmic bytes per cell of one RK4 stage kernel (float32): inverse x
+    pass input 24, stage input 12 (+ m_n and the accumulator 12 each from
+    s = 2), outputs accumulator 12 (s < 4), next input 12, forward x pass 24;
+    a taped stage also writes H 12 and |x| 4, stage 1 a copy of y 12, stage 4
+    a copy of the new state 12."""
+    b = 24 + 12 + (24 if s > 1 else 0) + (12 if s < 4 else 0) + 12 + 24
+    if taped:
+        b += 16 + (12 if s in (1, 4) else 0)
+    return b
+
+
+def bstage_bytes(s):
+    """Reverse stage (float32): reads Y1 24, mu (stencil) 12, y_s 12, H_s 12,
+    kappa 12, lambda 12 (+ |x_s| 4, xi_5 12, y_{s-1} 12 from s = 2); writes
+    lambda 12 (+ kappa 12, mu_{s-1} 12, forward x pass 24 from s = 2)."""
+    return 84 + 12 + ((4 + 12 + 12) + (12 + 12 + 24) if s > 1 else 0)
+
+
+BSTART_BYTES = 12 + 12 + 12 + 4 + 12 + 12 + 12 + 12 + 24   # reads gm, y4, y5, |x5|; writes xi5, gm, kappa, mu, X1
+CONV_BYTES = 72 + 120 + 72                                  # y forward, z pass with the product, y inverse
+
+
+def model_bytes_per_cell(kind):
+    """Algorithmic HBM bytes per cell (float32; float64 doubles them):
+    heff: x forward 36 + convolution 264 + inverse x pass with the local
+    field 48 = 348; rk4: one step of four stages and four convolutions;
+    fwdbwd: one checkpointed forward+adjoint step (forward step, taped
+    re-run, reverse start and four reverse stages with a convolution each)."""
+    if kind == "heff":
+        return 36 + CONV_BYTES + 48
+    fwd = 4 * CONV_BYTES + sum(stage_bytes(s) for s in (1, 2, 3, 4))
+    if kind == "rk4":
+        return fwd
+    taped = 4 * CONV_BYTES + sum(stage_bytes(s, True) for s in (1, 2, 3, 4))
+    rev = BSTART_BYTES + 4 * CONV_BYTES + sum(bstage_bytes(s) for s in (1, 2, 3, 4))
+    return fwd + taped + rev
 
 
 def source_hash():
@@ -119,6 +167,170 @@ def cpu_baseline(w, budget_cells=(128, 128, 32)):
     return {"value": rate, "unit": "steps/s", "cores": onewell._workers(), "kind": "oracle",
             "sample": f"{steps} fwd+bwd RK4 steps on a {n[0]}x{n[1]}x{n[2]} sub-box of the workload "
                       f"({dt:.1f} s), scaled by cell count {sub}/{w.ncell}"}
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+SAMPLED = {"film": "film_sampled.npz", "dmi": "dmi256_sampled.npz", "demag": "demag512_sampled.npz",
+           "adjoint": "adjoint256_sampled.npz"}
+NSTEP_DRIFT = {"dmi": 1000, "demag": 200, "large": 50}
+
+
+def _sampled_errors(gold, H, m1):
+    """Normwise H_eff error (denominator max |H| over every cell, stored) and
+    absolute one-step error at the stored oracle cells."""
+    import numpy as np
+    x, y, z = (_cuda_index(v) for v in gold["cells"].T)
+    Hs = H[:, z, y, x].T.double().cpu().numpy()
+    ms = m1[:, z, y, x].T.double().cpu().numpy()
+    eh = float(np.sqrt(((Hs - gold["H"]) ** 2).sum(1)).max() / float(gold["hmax"]))
+    em = float(np.abs(ms - gold["m1"]).max())
+    return eh, em
+
+
+def _cuda_index(v):
+    import torch
+    return torch.from_numpy(v.astype("int64")).cuda()
+
+
+def oracle_rates(w, max_cells=(128, 128)):
+    """FP64 oracle H_eff and one RK4 step timed on a sub-box of the workload
+    (at most 128 x 128 cells per layer, all layers), scaled by cell count."""
+    import numpy as np
+
+    from oracle import field as ofield
+    from oracle import llg as ollg
+    from oracle import newell as onewell
+    from oracle.params import Grid, Params
+    from workloads import random_unit_field
+
+    n = (min(w.n[0], max_cells[0]), min(w.n[1], max_cells[1]), w.n[2])
+    g = Grid(*n, *w.d)
+    mat = w.material()
+    p = Params(**{k: mat[k] for k in ("Ms", "A", "D", "Ku", "eK", "Hbias", "alpha", "terms", "renorm")})
+    spec = onewell.spectrum(g)
+    m = random_unit_field(n, w.seed, w.smooth).astype(np.float32).astype(np.float64)
+    t0 = time.perf_counter()
+    ofield.heff(g, p, m, spec)
+    t1 = time.perf_counter()
+    ollg.rk4_step(g, p, m, w.dt, spec)
+    t2 = time.perf_counter()
+    sub = n[0] * n[1] * n[2]
+    return {"heff_mcells_per_s": round(sub / (t1 - t0) / 1e6, 3),
+            "rk4_steps_per_s": round(sub / w.ncell / (t2 - t1), 5),
+            "cores": onewell._workers(),
+            "sample": f"one H_eff and one RK4 step on {n[0]}x{n[1]}x{n[2]} cells, scaled by cell count"}
+
+
+def config_measurements(magx, torch, timeit):
+    """Every workload in float32 and float64: rates, roofline fractions under
+    the bytes model, errors against the oracle and between precisions."""
+    import numpy as np
+
+    from workloads import WORKLOADS, bernoulli_mask, initial_state, tangent_direction
+    out = {}
+    hb = model_bytes_per_cell("heff")
+    rb = model_bytes_per_cell("rk4")
+    for name in ("film", "dmi", "demag", "adjoint", "large"):
+        w = WORKLOADS[name]
+        N = w.ncell
+        p = magx.make_params(**w.material())
+        m0 = torch.from_numpy(initial_state(w, np.float32)).cuda()
+        gold = np.load(os.path.join(GOLDEN, SAMPLED[name])) if name in SAMPLED else None
+        rec = {"cells": N, "grid": "x".join(str(v) for v in w.n), "dt_s": w.dt}
+        res = {}
+        for dt_name, dt_code in (("f64", magx.F64), ("f32", magx.F32)):
+            es = 8 if dt_code == magx.F64 else 4
+            ctx = magx.Context(w.n, w.d, dt_code)
+            m = m0.to(ctx.tdtype)
+            H = ctx.field()
+            reps = 3 if name == "large" else 10
+            t_h = timeit(lambda: ctx.heff(m, p, out=H), reps)
+            y = m.clone()
+            nst = 2 if name == "large" else 5
+            t_s = timeit(lambda: ctx.step(y, p, w.dt, nst), 2) / nst
+            m1 = m.clone()
+            ctx.step(m1, p, w.dt, 1)
+            H = ctx.heff(m, p)
+            r = {"heff_mcells_per_s": round(N / t_h / 1e6, 1), "rk4_steps_per_s": round(1.0 / t_s, 2),
+                 "heff_model_frac": round(hb * (es // 4) * N / t_h / 1e9 / PEAK_HBM_GBS, 4),
+                 "rk4_model_frac": round(rb * (es // 4) * N / t_s / 1e9 / PEAK_HBM_GBS, 4)}
+            if gold is not None:
+                eh, em = _sampled_errors(gold, H, m1)
+                r["err_heff_vs_oracle"] = eh
+                r["err_m_1step_vs_oracle"] = em
+            res[dt_name] = (r, H.double().cpu(), m1.double().cpu())
+            if name in NSTEP_DRIFT:
+                mN = m.clone()
+                ctx.step(mN, p, w.dt, NSTEP_DRIFT[name])
+                res[dt_name] = res[dt_name] + (mN.double().cpu(),)
+            del ctx, H, y, m1, m
+            torch.cuda.empty_cache()
+        r64, H64, m64 = res["f64"][:3]
+        r32, H32, m32 = res["f32"][:3]
+        rec["f32"], rec["f64"] = r32, r64
+        rec["err_heff_f32_vs_f64"] = err_norm(H32, H64)
+        rec["err_m_1step_f32_vs_f64"] = float((m32 - m64).abs().max())
+        if name in NSTEP_DRIFT:
+            rec[f"err_m_{NSTEP_DRIFT[name]}steps_f32_vs_f64"] = float((res["f32"][3] - res["f64"][3]).abs().max())
+        if name == "adjoint":
+            g = np.load(os.path.join(GOLDEN, "adjoint256_grad.npz"))
+            ctx = magx.Context(w.n, w.d, magx.F32)
+            mask = torch.from_numpy(bernoulli_mask(w.n, w.extra["mask_seed"])).cuda().float()
+            store = ctx.checkpoint_store(w.steps, w.ckpt)
+            tape = ctx.tape(w.ckpt)
+            mwork = ctx.field()
+            mm = m0.clone()
+            gm = ctx.field()
+
+            def fb():
+                mm.copy_(m0)
+                ctx.rollout_forward(mm, p, w.dt, w.steps, w.ckpt, store)
+                gm.zero_()
+                gm[2] = mask / mask.sum()
+                return ctx.rollout_backward(store, p, w.dt, w.steps, w.ckpt, gm, tape=tape, mwork=mwork)[1]
+
+            t_fb = timeit(fb, 2)
+            gh = fb()
+            torch.cuda.synchronize()
+            m0d = m0.double().cpu().numpy()
+            proj = np.array([float((gm.double().cpu().numpy() * tangent_direction(m0d, int(sd))).sum())
+                             for sd in g["seeds"]])
+            rec["fwdbwd_f32"] = {"steps": w.steps, "checkpoint": w.ckpt,
+                                 "steps_per_s": round(w.steps / t_fb, 2),
+                                 "model_frac": round(model_bytes_per_cell("fwdbwd") * N * w.steps / t_fb / 1e9
+                                                     / PEAK_HBM_GBS, 4),
+                                 "err_grad_vs_oracle": float(np.linalg.norm(proj - g["proj"]) / np.linalg.norm(g["proj"])),
+                                 "err_dHbias_vs_oracle": float(np.linalg.norm(gh.double().cpu().numpy() - g["gHbias"])
+                                                               / np.linalg.norm(g["gHbias"])),
+                                 "directions": int(len(g["seeds"]))}
+            del ctx, store, tape, mwork, gm
+            torch.cuda.empty_cache()
+        if name == "large":
+            ctx = magx.Context(w.n, w.d, magx.F32)
+            store = ctx.checkpoint_store(w.steps, w.ckpt)
+            tape = ctx.tape(w.ckpt)
+            mwork = ctx.field()
+            mm = m0.clone()
+            gm = ctx.field()
+            mask = torch.from_numpy(bernoulli_mask(w.n, w.extra["mask_seed"])).cuda().float()
+
+            def fb():
+                mm.copy_(m0)
+                ctx.rollout_forward(mm, p, w.dt, w.steps, w.ckpt, store)
+                gm.zero_()
+                gm[2] = mask / mask.sum()
+                ctx.rollout_backward(store, p, w.dt, w.steps, w.ckpt, gm, tape=tape, mwork=mwork)
+
+            t_fb = timeit(fb, 1)
+            gb = model_bytes_per_cell("fwdbwd") * N * w.steps / t_fb / 1e9
+            rec["fwdbwd_f32"] = {"steps": w.steps, "checkpoint": w.ckpt, "seconds": round(t_fb, 3),
+                                 "steps_per_s": round(w.steps / t_fb, 2), "model_GBps": round(gb, 1),
+                                 "model_frac": round(gb / PEAK_HBM_GBS, 4)}
+            del ctx, store, tape, mwork, gm, mm
+            torch.cuda.empty_cache()
+        rec["oracle"] = oracle_rates(w)
+        out[name] = rec
+    return out
 
 
 def integrator_comparison(magx, torch, timeit):
@@ -296,13 +508,13 @@ def main():
     ctx.profile_start(DOMINANT)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    gh = fwd_bwd(args.steps)
+    fwd_bwd(args.steps)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     launches, kern_ms = ctx.profile_stop()
     T = t1 - t0
     value = args.steps / T
-    grad_norm = float(gm.double().norm())
+    step_bytes = model_bytes_per_cell("fwdbwd") * N * args.steps
 
     avg_ms = kern_ms / max(launches, 1)
     algo = kernel_bytes(DOMINANT, n, 4)
@@ -323,37 +535,9 @@ def main():
             torch.cuda.synchronize()
             return (time.perf_counter() - a) / reps
 
-        H32 = ctx.field()
-        t_h32 = timeit(lambda: ctx.heff(m0, p, out=H32), 20)
-        mm = ctx.field()
-        mm.copy_(m0)
-        t_s32 = timeit(lambda: ctx.step(mm, p, w.dt, 5), 3) / 5
-        m1_32 = m0.clone()
-        ctx.step(m1_32, p, w.dt, 1)
-        H32 = ctx.heff(m0, p)
         del store, tape, mwork
         torch.cuda.empty_cache()
-        ctx64 = magx.Context(n, d, magx.F64)
-        m0_64 = m0.double()
-        H64 = ctx64.field()
-        t_h64 = timeit(lambda: ctx64.heff(m0_64, p, out=H64), 10)
-        mm64 = ctx64.field()
-        mm64.copy_(m0_64)
-        t_s64 = timeit(lambda: ctx64.step(mm64, p, w.dt, 5), 2) / 5
-        m1_64 = m0_64.clone()
-        ctx64.step(m1_64, p, w.dt, 1)
-        torch.cuda.synchronize()
-        extras = {
-            "heff_mcells_per_s_f32": round(N / t_h32 / 1e6, 1),
-            "heff_mcells_per_s_f64": round(N / t_h64 / 1e6, 1),
-            "fwd_rk4_steps_per_s_f32": round(1.0 / t_s32, 2),
-            "fwd_rk4_steps_per_s_f64": round(1.0 / t_s64, 2),
-            "err_heff_f32_vs_f64": err_norm(H32, H64),
-            "err_m_1step_f32_vs_f64": float((m1_32.double() - m1_64).abs().max()),
-            "heff_hbm_model_frac_f32": round(348 * N / t_h32 / 1e9 / PEAK_HBM_GBS, 4),
-        }
-        del ctx64, H64, mm64, m1_64, m0_64
-        torch.cuda.empty_cache()
+        extras["configs"] = config_measurements(magx, torch, timeit)
         extras["sp4_fine_interval"] = integrator_comparison(magx, torch, timeit)
         extras["batched_film"] = batched_throughput(magx, torch, timeit)
 
@@ -378,8 +562,10 @@ def main():
                                "forward+adjoint RK4 step, dt 1e-13 s",
                    "cells": N, "checkpoint": ckpt, "dt_s": w.dt},
         "roofline": roofline,
+        "step_model": {"bytes_per_cell": model_bytes_per_cell("fwdbwd"),
+                       "GBps": round(step_bytes / T / 1e9, 1),
+                       "frac": round(step_bytes / T / 1e9 / PEAK_HBM_GBS, 4)},
         "cpu_baseline": cpu,
-        "grad_checks": {"dL_dHbias": [float(v) for v in gh.cpu()], "grad_m_norm": grad_norm},
     }
     out.update(extras)
     print(json.dumps(out), flush=True)

@@ -6,12 +6,16 @@ root:
 
     python tests/golden/make_workload_golden.py demag512   # ~5 min on 8 cores
     python tests/golden/make_workload_golden.py adjoint256 # ~15 min
+    python tests/golden/make_workload_golden.py film dmi256 adjoint256_cells  # ~2 min
 
 demag512_sampled.npz -- the 512 x 512 x 32 demag workload (Section II-B
     convolution + exchange): the oracle's H_eff (Eq. (2)) and the state after
-    one RK4 step (dt 1e-13 s) at 4096 seeded cells plus the box's corners and
-    face centres, and max_i |H_i| over every cell (the denominator of the
-    normwise error).
+    one RK4 step (the workload's dt) at 4096 seeded cells plus the box's
+    corners and face centres, and max_i |H_i| over every cell (the
+    denominator of the normwise error).
+film_sampled.npz, dmi256_sampled.npz, adjoint256_sampled.npz -- the same for
+    the 128 x 32 x 1 film (every cell), the 256 x 256 x 16 DMI workload and the
+    256 x 256 x 8 adjoint workload.
 adjoint256_grad.npz -- the 256 x 256 x 8 adjoint workload: loss L = masked
     mean of m_z after 100 RK4 steps of 5e-14 s (mask seed 2004), the oracle's
     checkpointed reverse sweep (checkpoint every 10 steps): dL/dm0 projected on
@@ -66,8 +70,8 @@ def sample_cells(n, seed=SAMPLE_SEED, k=NSAMPLE):
     return np.array(out, dtype=np.int64)
 
 
-def demag512():
-    w = WORKLOADS["demag"]
+def sampled(wname, fname):
+    w = WORKLOADS[wname]
     g = Grid(*w.n, *w.d)
     p = _params(w.material())
     t0 = time.time()
@@ -78,13 +82,13 @@ def demag512():
     print(f"heff {time.time() - t0:.1f} s", flush=True)
     m1 = ollg.rk4_step(g, p, m, w.dt, spec)
     print(f"rk4 step {time.time() - t0:.1f} s", flush=True)
-    cells = sample_cells(w.n)
+    cells = sample_cells(w.n, k=min(NSAMPLE, w.ncell))
     x, y, z = cells[:, 0], cells[:, 1], cells[:, 2]
     hmax = float(np.sqrt((H ** 2).sum(0)).max())
-    np.savez_compressed(os.path.join(HERE, "demag512_sampled.npz"), cells=cells,
+    np.savez_compressed(os.path.join(HERE, fname), cells=cells,
                         H=H[:, z, y, x].T.copy(), m1=m1[:, z, y, x].T.copy(), hmax=hmax,
                         dt=w.dt, seed=w.seed)
-    print(f"wrote demag512_sampled.npz: {len(cells)} cells, hmax {hmax:.6e}", flush=True)
+    print(f"wrote {fname}: {len(cells)} cells, hmax {hmax:.6e}", flush=True)
 
 
 def adjoint256():
@@ -107,6 +111,10 @@ def adjoint256():
 
 
 if __name__ == "__main__":
-    jobs = {"demag512": demag512, "adjoint256": adjoint256}
+    jobs = {"demag512": lambda: sampled("demag", "demag512_sampled.npz"),
+            "film": lambda: sampled("film", "film_sampled.npz"),
+            "dmi256": lambda: sampled("dmi", "dmi256_sampled.npz"),
+            "adjoint256_cells": lambda: sampled("adjoint", "adjoint256_sampled.npz"),
+            "adjoint256": adjoint256}
     for name in sys.argv[1:] or list(jobs):
         jobs[name]()
