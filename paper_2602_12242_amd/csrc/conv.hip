@@ -340,12 +340,14 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
     const int tid = threadIdx.x;
     const int col = tid & (T - 1);
     const int g = tid / T;
+    __builtin_assume(g >= 0 && g < G);
     const unsigned plane_stride = (unsigned)Py * (unsigned)Sx;
     const unsigned comp_stride = (unsigned)nz * plane_stride;
     // w1[k1] = W_Pz^(g k1) (forward pass over r); w2[j][q] = W_Pz^(q (g + G j))
     // (the twiddles between the length-G DFTs of the items k1 = g + G j);
-    // the inverse uses the conjugates
-    // (for G = 8, J = 1 and w2[0] = w1)
+    // the inverse uses the conjugates.  w1[0] = 1 and w2[j][0] = 1: those
+    // products are skipped.  (for G = 8, J = 1 and w2[0] = w1)
+    const R s = -Ms;
     cx<R> w1[8], w2[J][G];
 #pragma unroll
     for (int k1 = 0; k1 < 8; ++k1) w1[k1] = tw_fwd<R>(((g * k1) & (PZ - 1)) << (kTwLog - LGPZ));
@@ -373,7 +375,10 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
     auto base_of = [=](const Tile& d) {
         return X2 + (long long)d.mb * 3 * comp_stride + (long long)d.ky * Sx + d.kx0;
     };
-    // Inputs of a tile: rows g + G r, r < 4, of the three components.  Every
+    // Inputs of a tile: rows g + G r, r < 4, of the three components (scaled
+    // by the spectral product's factor s = -Ms when the forward pass takes
+    // them: the pass is linear, and there are fewer inputs than spectral
+    // values; not at the load, which would make it wait for the data).  Every
     // operation of the pass acts on one column, so a column beyond Hx (read at
     // the clamped column Hx-1 of the same row) only produces values that are
     // never stored; rows z >= nz are the zero padding.
@@ -397,7 +402,6 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
     const int t0 = (int)((long long)nunits * pr / npairs);
     const int t1 = (int)((long long)nunits * (pr + 1) / npairs);
     if (t0 < t1) load_tile(t0);
-    const R s = -Ms;
     for (int t = t0; t < t1; ++t) {
         const Tile d = tile_of(t);
         const R sy = d.ky <= Py / 2 ? (R)1 : (R)-1;
@@ -419,7 +423,8 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
                     const int olo = lo + k0 * T, ohi = hi - k0 * T;
                     const int o = k0 + G - 1 <= H2 ? olo : (k0 > H2 ? ohi : (g + k0 <= H2 ? olo : ohi));
 #pragma unroll
-                    for (int c6 = 0; c6 < 6; ++c6) tv[jj * G + k2][c6] = blk[c6 * (Hz * T) + o];
+                    for (int c6 = 0; c6 < 6; ++c6)
+                        tv[jj * G + k2][c6] = ld_off<R>(blk, (unsigned)(c6 * (Hz * T) + o) * (unsigned)sizeof(R));
                 }
         }
         // forward: DFT over r, twiddles, exchange
@@ -427,12 +432,13 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
         for (int c = 0; c < 3; ++c) {
             cx<R> v[8];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) v[r] = pin[c * 4 + r];
+            for (int r = 0; r < 4; ++r) v[r] = cscale<R>(pin[c * 4 + r], s);
 #pragma unroll
             for (int r = 4; r < 8; ++r) v[r] = mk<R>((R)0, (R)0);
             dft8<R, false>(v);
 #pragma unroll
-            for (int k1 = 0; k1 < 8; ++k1) E[((c * 8 + k1) * G + g) * T + col] = cmul<R>(v[k1], w1[k1]);
+            for (int k1 = 0; k1 < 8; ++k1)
+                E[((c * 8 + k1) * G + g) * T + col] = (k1 == 0 || G == 1) ? v[k1] : cmul<R>(v[k1], w1[k1]);
         }
         if constexpr (G > 1) __syncthreads();
         // length-G DFTs over g: X[c][j G + k2] is the spectrum at kz = g + G j + 8 k2
@@ -446,7 +452,7 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
                 for (int q = 0; q < G; ++q) X[c][jj * G + q] = E[((c * 8 + k1) * G + q) * T + col];
                 if constexpr (G > 1) dft<R, G, false>(&X[c][jj * G]);
             }
-        // spectral product
+        // spectral product N M (its factor -Ms was applied to the inputs)
 #pragma unroll
         for (int jj = 0; jj < J; ++jj)
 #pragma unroll
@@ -457,9 +463,9 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
                 const R nxx = tv[e][0], nyy = tv[e][1], nzz = tv[e][2];
                 const R nxy = sy * tv[e][3], nxz = sz * tv[e][4], nyz = sy * sz * tv[e][5];
                 const cx<R> mx = X[0][e], my = X[1][e], mz = X[2][e];
-                X[0][e] = mk<R>(s * (nxx * mx.x + nxy * my.x + nxz * mz.x), s * (nxx * mx.y + nxy * my.y + nxz * mz.y));
-                X[1][e] = mk<R>(s * (nxy * mx.x + nyy * my.x + nyz * mz.x), s * (nxy * mx.y + nyy * my.y + nyz * mz.y));
-                X[2][e] = mk<R>(s * (nxz * mx.x + nyz * my.x + nzz * mz.x), s * (nxz * mx.y + nyz * my.y + nzz * mz.y));
+                X[0][e] = mk<R>(nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y);
+                X[1][e] = mk<R>(nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y);
+                X[2][e] = mk<R>(nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y);
             }
         // the next tile's inputs are in flight during the inverse transform
         if (t + 1 < t1) load_tile(t + 1);
@@ -473,7 +479,8 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
                 if constexpr (G > 1) dft<R, G, true>(&X[c][jj * G]);
 #pragma unroll
                 for (int q = 0; q < G; ++q)
-                    E[((c * 8 + k1) * G + q) * T + col] = cmul<R>(X[c][jj * G + q], cconj<R>(w2[jj][q]));
+                    E[((c * 8 + k1) * G + q) * T + col] =
+                        q == 0 ? X[c][jj * G] : cmul<R>(X[c][jj * G + q], cconj<R>(w2[jj][q]));
             }
         if constexpr (G > 1) __syncthreads();
         cx<R>* base = base_of(d);

@@ -541,6 +541,13 @@ template <typename R> __device__ __forceinline__ cx<R> ld_stream(const cx<R>* p)
     return mk<R>(t.x, t.y);
 }
 
+// Element at a 32-bit byte offset from a base pointer: with a uniform base
+// the access is one scalar-base + 32-bit vector-offset instruction, without
+// 64-bit address arithmetic per lane.  The caller guarantees off < 2^32.
+template <typename R> __device__ __forceinline__ R ld_off(const R* base, unsigned off) {
+    return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) + off);
+}
+
 __host__ __device__ inline int ilog2(int v) {
     int r = 0;
     while ((1 << r) < v) ++r;
