@@ -67,9 +67,13 @@ struct PairWalk {
 // tile width, tile count) becomes a constant, so the FFT strides and row
 // offsets are immediates.  LG = 0 keeps runtime sizes.  The tile width is the
 // plan's, ty = min(16, budget / Py) with a budget of 2^14 complex values in
-// single and 2^12 in double precision.
+// single precision and in double precision 2^13 for Py >= 1024, 2^12 below
+// (128 KiB and 64 KiB of LDS; at Py = 512 the smaller tile measured faster).
 template <typename R> constexpr int ytile_lg(int LG) {
-    constexpr int lgb = sizeof(R) == 4 ? 14 : 12;
+    constexpr int lgb = sizeof(R) == 4 ? 14 : 13;
+    if constexpr (sizeof(R) == 8) {
+        if (LG <= 9) return LG >= 8 ? 12 - LG : 4;
+    }
     return LG >= lgb - 4 ? lgb - LG : 4;
 }
 
@@ -503,6 +507,199 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
     }
 }
 
+// Register-resident z pass for Pz = 128 (single precision, nz = 33 ... 64).
+// Sixteen threads per column, T = 16 columns per tile (256 threads).
+// Thread (col, g), g < 16, holds the elements z = g + 16 r (r < 8; r < 4 are
+// inside the box) of all three components.  Forward: a length-8 DFT over r,
+// the twiddles W_128^(g k1) (k1 < 8), one LDS exchange, then the length-16
+// DFT over g split by decimation in frequency: thread (col, h) with
+// k1 = h & 7 and parity p = h >> 3 (one parity per wave) forms
+// u[g'] + (-1)^p u[g' + 8], multiplies by W_16^(p g') and takes a length-8
+// DFT over g', which gives the spectrum at kz = k1 + 8 (2 m + p), m < 8, of
+// all three components: the 3x3 product runs on registers.  The inverse
+// retraces the steps (length-8 inverse DFTs over m, W_16^(-p g'), exchange,
+// recombination a + (-1)^h W_16^(-g') c of the two parities, conjugate
+// twiddles, length-8 inverse DFT over k1); rows z >= nz are not written.
+// The tensor spectrum is in the tile-major layout with a tile width of 16.
+template <typename R>
+__global__ void __launch_bounds__(256) zconvr128_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
+                                                        int nz, int Py, int Hx, int Sx, int ntx,
+                                                        int units_per_member, int nunits) {
+    constexpr int T = 16, PZ = 128, Hz = PZ / 2 + 1;
+    constexpr int LGPZ = 7;
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* E = reinterpret_cast<cx<R>*>(smem_raw);   // [3][8][16][T]
+    const int tid = threadIdx.x;
+    const int col = tid & (T - 1);
+    const int g = tid / T;                          // forward layout: row phase g < 16
+    __builtin_assume(g >= 0 && g < 16);
+    const int k1h = g & 7, par = g >> 3;            // spectral layout: (k1, parity), parity uniform per wave
+    const unsigned plane_stride = (unsigned)Py * (unsigned)Sx;
+    const unsigned comp_stride = (unsigned)nz * plane_stride;
+    const R s = -Ms;
+    // W_128^(g k1), k1 = 1 ... 7 (w1[0] = 1 is not used)
+    cx<R> w1[8];
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) w1[k1] = tw_fwd<R>(((g * k1) & (PZ - 1)) << (kTwLog - LGPZ));
+    struct Tile {
+        int mb, kx0, ky, tx, kyo;
+    };
+    const int lbp = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int side = lbp & 1;
+    auto tile_of = [=](int u) {
+        Tile d;
+        d.mb = u / units_per_member;
+        const int r = u - d.mb * units_per_member;
+        const int q = r / ntx;
+        d.tx = r - q * ntx;
+        d.kyo = side ? (q == 0 ? Py >> 1 : q) : q;
+        d.ky = side ? (q == 0 ? Py >> 1 : Py - q) : q;
+        d.kx0 = d.tx * T;
+        return d;
+    };
+    auto base_of = [=](const Tile& d) {
+        return X2 + (long long)d.mb * 3 * comp_stride + (long long)d.ky * Sx + d.kx0;
+    };
+    // inputs: rows g + 16 r, r < 4 (the rest is zero padding), columns beyond
+    // Hx read at the clamped column (their values are never stored)
+    cx<R> pin[12];
+    auto load_tile = [&](int u) {
+        const Tile d = tile_of(u);
+        const cx<R>* base = base_of(d);
+        const unsigned voff = (unsigned)g * plane_stride + (unsigned)min(col, Hx - 1 - d.kx0);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int z = g + 16 * r;
+                const unsigned zoff = (unsigned)min(16 * r, nz - 1 - g) * plane_stride;
+                const cx<R> v = base[(unsigned)c * comp_stride + zoff + voff];
+                pin[c * 4 + r] = z < nz ? v : mk<R>((R)0, (R)0);
+            }
+    };
+    const int npairs = gridDim.x >> 1;
+    const int pr = lbp >> 1;
+    const int t0 = (int)((long long)nunits * pr / npairs);
+    const int t1 = (int)((long long)nunits * (pr + 1) / npairs);
+    if (t0 < t1) load_tile(t0);
+    for (int t = t0; t < t1; ++t) {
+        const Tile d = tile_of(t);
+        const R sy = d.ky <= Py / 2 ? (R)1 : (R)-1;
+        // tensor values of this thread's kz = k1 + 16 m + 8 p: octant row kz
+        // for m < 4 and 128 - kz (odd components change sign) for m >= 4
+        R tv[8][6];
+        {
+            const R* blk = spec + (long long)(d.kyo * ntx + d.tx) * 6 * (Hz * T);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const int kz = k1h + 16 * m + 8 * par;
+                const int row = m < 4 ? kz : PZ - kz;
+#pragma unroll
+                for (int c6 = 0; c6 < 6; ++c6)
+                    tv[m][c6] = ld_off<R>(blk, (unsigned)(c6 * (Hz * T) + row * T + col) * (unsigned)sizeof(R));
+            }
+        }
+        // forward: length-8 DFT over r, twiddles W_128^(g k1), exchange
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<R> v[8];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) v[r] = cscale<R>(pin[c * 4 + r], s);
+#pragma unroll
+            for (int r = 4; r < 8; ++r) v[r] = mk<R>((R)0, (R)0);
+            dft8<R, false>(v);
+#pragma unroll
+            for (int k1 = 0; k1 < 8; ++k1)
+                E[((c * 8 + k1) * 16 + g) * T + col] = k1 == 0 ? v[0] : cmul<R>(v[k1], w1[k1]);
+        }
+        __syncthreads();
+        // length-16 DFT over g, parity p of the outputs: X[c][m] at kz = k1 + 8 (2 m + p)
+        cx<R> X[3][8];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const cx<R>* src = E + (c * 8 + k1h) * 16 * T + col;
+            cx<R> u[8];
+            if (par == 0) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) u[q] = cadd<R>(src[q * T], src[(q + 8) * T]);
+            } else {
+                u[0] = csub<R>(src[0], src[8 * T]);
+                u[1] = mul_w32<R, false, 2>(csub<R>(src[1 * T], src[9 * T]));
+                u[2] = mul_w32<R, false, 4>(csub<R>(src[2 * T], src[10 * T]));
+                u[3] = mul_w32<R, false, 6>(csub<R>(src[3 * T], src[11 * T]));
+                u[4] = mul_w32<R, false, 8>(csub<R>(src[4 * T], src[12 * T]));
+                u[5] = mul_w32<R, false, 10>(csub<R>(src[5 * T], src[13 * T]));
+                u[6] = mul_w32<R, false, 12>(csub<R>(src[6 * T], src[14 * T]));
+                u[7] = mul_w32<R, false, 14>(csub<R>(src[7 * T], src[15 * T]));
+            }
+            dft8<R, false>(u);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) X[c][m] = u[m];
+        }
+        // spectral product N M (its factor -Ms was applied to the inputs)
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const R sz = m < 4 ? (R)1 : (R)-1;
+            const R nxx = tv[m][0], nyy = tv[m][1], nzz = tv[m][2];
+            const R nxy = sy * tv[m][3], nxz = sz * tv[m][4], nyz = sy * sz * tv[m][5];
+            const cx<R> mx = X[0][m], my = X[1][m], mz = X[2][m];
+            X[0][m] = mk<R>(nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y);
+            X[1][m] = mk<R>(nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y);
+            X[2][m] = mk<R>(nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y);
+        }
+        // the next tile's inputs are in flight during the inverse transform
+        if (t + 1 < t1) load_tile(t + 1);
+        // inverse: length-8 inverse DFTs over m, W_16^(-p g'), exchange back
+        __syncthreads();   // every thread has read its exchange values
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<R> u[8];
+#pragma unroll
+            for (int m = 0; m < 8; ++m) u[m] = X[c][m];
+            dft8<R, true>(u);
+            cx<R>* dst = E + ((c * 8 + k1h) * 2 + par) * 8 * T + col;
+            if (par == 0) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) dst[q * T] = u[q];
+            } else {
+                dst[0] = u[0];
+                dst[1 * T] = mul_w32<R, true, 2>(u[1]);
+                dst[2 * T] = mul_w32<R, true, 4>(u[2]);
+                dst[3 * T] = mul_w32<R, true, 6>(u[3]);
+                dst[4 * T] = mul_w32<R, true, 8>(u[4]);
+                dst[5 * T] = mul_w32<R, true, 10>(u[5]);
+                dst[6 * T] = mul_w32<R, true, 12>(u[6]);
+                dst[7 * T] = mul_w32<R, true, 14>(u[7]);
+            }
+        }
+        __syncthreads();
+        // recombination for row phase g = g' + 8 h: a[g'] + (-1)^h c'[g'], conjugate
+        // twiddles, length-8 inverse DFT over k1; rows z = g + 16 n1, n1 < 4
+        cx<R>* base = base_of(d);
+        const bool okc = d.kx0 + col < Hx;
+        const int gl = g & 7;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<R> v[8];
+#pragma unroll
+            for (int k1 = 0; k1 < 8; ++k1) {
+                const cx<R>* src = E + ((c * 8 + k1) * 2) * 8 * T + gl * T + col;
+                const cx<R> a = src[0], b = src[8 * T];
+                const cx<R> y = par == 0 ? cadd<R>(a, b) : csub<R>(a, b);
+                v[k1] = k1 == 0 ? y : cmul<R>(y, cconj<R>(w1[k1]));
+            }
+            dft8<R, true>(v);
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) {
+                const int z = g + 16 * n1;
+                if (okc && z < nz)
+                    st_stream<R>(&base[(unsigned)c * comp_stride + (unsigned)z * plane_stride + (unsigned)col], v[n1]);
+            }
+        }
+        __syncthreads();   // the next tile's forward exchange rewrites E
+    }
+}
+
 static inline bool em_big(long long elements) { return elements > (long long)kNT * 16; }
 
 // Blocks of a persistent launch: as many as can be resident on the device
@@ -598,14 +795,17 @@ hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) 
             default: break;
         }
     } else {
-        // double precision: tiles of 2^12 values, 256 threads of 16
+        // double precision: tiles of 2^12 values (256 threads of 16) or 2^13 (512 threads of 16)
         switch (y_lg<R>(pl)) {
             case 8: return run_yfwd<R, 16, kNT, 8>(pl, X1, X2, s);
             case 9: return run_yfwd<R, 16, kNT, 9>(pl, X1, X2, s);
-            case 10: return run_yfwd<R, 16, kNT, 10>(pl, X1, X2, s);
-            case 11: return run_yfwd<R, 16, kNT, 11>(pl, X1, X2, s);
+            case 10: return run_yfwd<R, 16, 512, 10>(pl, X1, X2, s);
+            case 11: return run_yfwd<R, 16, 512, 11>(pl, X1, X2, s);
             default: break;
         }
+        // tiles of up to 2^12 values: 256 threads of 16; up to 2^13 (128 KiB): 512 threads of 16
+        if (!em_big((long long)pl.Py * pl.ty)) return run_yfwd<R, 16, kNT>(pl, X1, X2, s);
+        return run_yfwd<R, 16, 512>(pl, X1, X2, s);
     }
     // tiles of up to 256 x 16 elements: 256 threads of 16; up to 256 x 32
     // (64 KiB in single precision): 256 threads of 32
@@ -628,10 +828,13 @@ hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) 
         switch (y_lg<R>(pl)) {
             case 8: return run_yinv<R, 16, kNT, 8>(pl, X2, Y1, s);
             case 9: return run_yinv<R, 16, kNT, 9>(pl, X2, Y1, s);
-            case 10: return run_yinv<R, 16, kNT, 10>(pl, X2, Y1, s);
-            case 11: return run_yinv<R, 16, kNT, 11>(pl, X2, Y1, s);
+            case 10: return run_yinv<R, 16, 512, 10>(pl, X2, Y1, s);
+            case 11: return run_yinv<R, 16, 512, 11>(pl, X2, Y1, s);
             default: break;
         }
+        // tiles of up to 2^12 values: 256 threads of 16; up to 2^13 (128 KiB): 512 threads of 16
+        if (!em_big((long long)pl.Py * pl.ty)) return run_yinv<R, 16, kNT>(pl, X2, Y1, s);
+        return run_yinv<R, 16, 512>(pl, X2, Y1, s);
     }
     if (!em_big((long long)pl.Py * pl.ty)) return run_yinv<R, 16, kNT>(pl, X2, Y1, s);
     if (y_huge(pl)) return run_yinv<R, 32, 512>(pl, X2, Y1, s);
@@ -676,8 +879,26 @@ static hipError_t run_zconvr(const Plan& pl, void* X2, const void* spec, float M
     return hipGetLastError();
 }
 
+static hipError_t run_zconvr128(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
+    if (pl.Pz != 128 || pl.tz != 16 || 2 * pl.nz > pl.Pz || 4 * pl.nz <= pl.Pz) return hipErrorInvalidValue;
+    const int ntx = pl.ntz;
+    const int upm = ntx * (pl.Py / 2);
+    const long long nunits = (long long)upm * pl.nbatch;
+    const size_t lds = (size_t)3 * 8 * 16 * 16 * sizeof(cx<float>);
+    const int resident =
+        persistent_grid(reinterpret_cast<const void*>(&zconvr128_kernel<float>), lds, 1LL << 30, 256);
+    if (resident < 2) return hipErrorInvalidValue;
+    long long grid = 2 * std::min<long long>(nunits, std::max(1, resident / 2));
+    if (grid >= 16) grid -= grid % 16;
+    hipLaunchKernelGGL((zconvr128_kernel<float>), dim3((unsigned)grid), dim3(256), lds, s,
+                       static_cast<cx<float>*>(X2), static_cast<const float*>(spec), Ms, pl.nz, pl.Py, pl.Hx, pl.Sx,
+                       ntx, upm, (int)nunits);
+    return hipGetLastError();
+}
+
 static hipError_t run_zreg(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
     switch (pl.Pz) {
+        case 128: return run_zconvr128(pl, X2, spec, Ms, s);
         case 8: return run_zconvr<64, 1>(pl, X2, spec, Ms, s);
         case 16: return run_zconvr<32, 2>(pl, X2, spec, Ms, s);
         case 32: return run_zconvr<32, 4>(pl, X2, spec, Ms, s);

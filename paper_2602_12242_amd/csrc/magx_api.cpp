@@ -110,9 +110,11 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
         return MAGX_ESIZE;
     p.ncell = (long long)p.nx * p.ny * p.nz;
     if (3LL * nbatch * p.ncell >= (1LL << 31) || nbatch > 65535) return MAGX_ESIZE;
-    // y tile: Py*ty complex in LDS; single precision takes up to 128 KiB (one
-    // block of 512 threads per CU, 16 columns = whole 128-byte row segments)
-    const int y_cplx = dt == MAGX_F32 ? 2 * lds_cplx : lds_cplx;
+    // y tile: Py*ty complex in LDS, up to 128 KiB (one block of 512 threads
+    // per CU; single precision: 16 columns = whole 128-byte row segments at
+    // Py = 1024; double precision: 8 columns, 128 bytes); double precision
+    // with Py <= 512 keeps 64 KiB tiles (256 threads)
+    const int y_cplx = dt == MAGX_F32 ? 16384 : (p.Py <= 512 ? 4096 : 8192);
     p.ty = std::min(16, pow2_floor(y_cplx / p.Py));
     // z tile: data 3*Pz*tz complex in LDS (at most 64 KiB), at most 16 FFT
     // elements per thread when possible (32 at most), and at most 4 tensor
@@ -126,10 +128,10 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
         int tz = 64;
         while (tz > 1 && !fits(tz, 16)) tz >>= 1;
         if (!fits(tz, 32)) return MAGX_ESIZE;
-        // single precision with Pz = 8 ... 64: the register-resident z pass (Pz/8 T threads per
-        // T-column tile; T = 32, and 64 for Pz = 8 so a block has at least 64 threads)
-        p.zreg = (dt == MAGX_F32 && p.Pz >= 8 && p.Pz <= 64) ? 1 : 0;
-        if (p.zreg) tz = p.Pz == 8 ? 64 : 32;
+        // single precision with Pz = 8 ... 128: the register-resident z pass (Pz/8 T threads per
+        // T-column tile; T = 32, 64 for Pz = 8 so a block has at least 64 threads, 16 for Pz = 128)
+        p.zreg = (dt == MAGX_F32 && p.Pz >= 8 && p.Pz <= 128) ? 1 : 0;
+        if (p.zreg) tz = p.Pz == 8 ? 64 : (p.Pz == 128 ? 16 : 32);
         p.tz = tz;
         p.ntz = (p.Hx + tz - 1) / tz;
         if ((long long)p.Hy * p.ntz * 6 * p.Hz * tz >= (1LL << 31)) return MAGX_ESIZE;

@@ -72,6 +72,15 @@ CASES = {
                 dict(Ms=8e5, A=1.3e-11, alpha=0.1, Hbias=(0, 0, 1e4), terms=1 | 2 | 16)),
     "row9": ((3, 1, 9), (2e-9, 2e-9, 2e-9),
              dict(Ms=8e5, A=1.3e-11, D=1e-3, Ku=5e5, eK=(0, 0, 1), alpha=0.1, terms=ALL)),
+    # Pz = 128 (nz = 33 ... 64): in single precision the register-resident z
+    # pass with 16 threads per column and 16-column tiles (ragged last tile)
+    "slab40": ((24, 7, 40), (2e-9, 2e-9, 1e-9),
+               dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, eK=(0.0, 0.6, 0.8), alpha=0.1,
+                    Hbias=(1e3, -2e3, 5e3), terms=ALL)),
+    "slab64": ((5, 3, 64), (2e-9, 2e-9, 1e-9),
+               dict(Ms=8e5, A=1.3e-11, alpha=0.2, Hbias=(0, 3e3, 1e4), terms=1 | 2 | 16)),
+    "slab33": ((9, 1, 33), (2e-9, 2e-9, 2e-9),
+               dict(Ms=8e5, A=1.3e-11, D=1e-3, Ku=5e5, eK=(0, 0, 1), alpha=0.1, terms=ALL)),
     # Pz = 1024: the longest z transform, one column per z tile
     "tall": ((3, 2, 300), (2e-9, 2e-9, 1e-9),
              dict(Ms=8e5, A=1.3e-11, alpha=0.1, Hbias=(0, 0, 1e4), terms=1 | 2 | 16)),
@@ -179,7 +188,7 @@ def test_llg_rhs_matches_oracle(dtype):
 
 
 @pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "film", "line", "cell", "tiles", "thick", "long_y",
-                                  "pow2_256", "pow2_1024", "sq512", "sq256"])
+                                  "pow2_256", "pow2_1024", "sq512", "sq256", "slab40", "slab64"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_one_rk4_step_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -232,7 +241,7 @@ def test_energy_matches_oracle(name, dtype):
     assert abs(e[5] - ref["total"]) <= (1e-11 if dtype == 1 else 2e-5) * scale
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "pow2_256", "sq512", "sq256"])
+@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "pow2_256", "sq512", "sq256", "slab40"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_heff_backward_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
