@@ -185,6 +185,132 @@ __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, 
     }
 }
 
+// y passes for Py = 2048 (ny = 513 ... 1024) as two transforms of length 1024
+// each, so a tile of 2^14 (single) or 2^13 (double) values spans 16 or 8
+// columns instead of 8 or 4 (whole 128-byte row segments).
+//  * forward, input rows n < ny: X[2k] = DFT_1024(x)[k] and
+//    X[2k+1] = DFT_1024(x W_2048^n)[k]; the tile's inputs stay in registers
+//    for the second transform, twiddled there.
+//  * inverse, output rows n < ny: x[n] = A[n] + W_2048^-n B[n] with
+//    A = IDFT_1024(X[2k]) and B = IDFT_1024(X[2k+1]); A is parked in the
+//    output rows (L2) while B is computed, and each half of the input is
+//    fetched while the transform before it runs.
+template <typename R, int EM, int NT>
+__global__ void __launch_bounds__(NT) yfwd2_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
+                                                   int Hx, int Sx, int lgT, int ntx, int ntiles) {
+    constexpr int LGL = 10, PY = 2048;
+    tw_lds_fill<R>();   // read by the second pass, after the first barrier
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    const int T = 1 << lgT;
+    const PairWalk pw(ntiles, ntx);
+    auto loader = [=](int t) {
+        const int tx = t % ntx;
+        const long long plane = t / ntx;
+        const int kx0 = tx * T;
+        const cx<R>* src = X1 + plane * ny * (long long)Sx + kx0;
+        const int ncol = min(T, Hx - kx0);
+        return [=](int b, int j) -> cx<R> {
+            if (j < ny && b < ncol) return src[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b];
+            return mk<R>(0, 0);
+        };
+    };
+    FirstIn<R, EM, false> in;
+    int u = pw.first();
+    if (u < pw.u1) first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(in, LGL, lgT, T, loader(pw.tile(u)));
+    while (u < pw.u1) {
+        const int un = pw.next(u);
+        const int t = pw.tile(u);
+        const int tx = t % ntx;
+        const long long plane = t / ntx;
+        const int kx0 = tx * T;
+        cx<R>* dst = X2 + plane * PY * (long long)Sx + kx0;
+        const int ncol = min(T, Hx - kx0);
+        auto store_even = [&](int b, int j, cx<R> v) {
+            if (b < ncol) st_stream<R>(&dst[umul24((unsigned)(2 * j), (unsigned)Sx) + (unsigned)b], v);
+        };
+        auto store_odd = [&](int b, int j, cx<R> v) {
+            if (b < ncol) st_stream<R>(&dst[umul24((unsigned)(2 * j + 1), (unsigned)Sx) + (unsigned)b], v);
+        };
+        auto none = [&]() {};
+        fft_reg<R, false, EM, false, kCols, 1, false, false, lgmax<EM>(), NT, true>(buf, LGL, lgT, T, in, none,
+                                                                                     store_even);
+        __syncthreads();   // the last pass read LDS; the second transform's first pass writes it
+        // x[n] W_2048^n: entry 2n of the 4096-point table
+        first_apply<R, EM, kCols, 1, false, lgmax<EM>(), NT>(
+            in, LGL, lgT, T, [](int, int j, cx<R> v) { return cmul<R>(v, tw_pass<R, false, true>(j << 1)); });
+        auto next = [&]() {
+            if (un < pw.u1)
+                first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(in, LGL, lgT, T, loader(pw.tile(un)));
+        };
+        fft_reg<R, false, EM, false, kCols, 1, false, false, lgmax<EM>(), NT, true>(buf, LGL, lgT, T, in, next,
+                                                                                     store_odd);
+        __syncthreads();
+        u = un;
+    }
+}
+
+template <typename R, int EM, int NT>
+__global__ void __launch_bounds__(NT) yinv2_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
+                                                   int Hx, int Sx, int lgT, int ntx, int ntiles) {
+    constexpr int LGL = 10, PY = 2048;
+    tw_lds_fill<R>();   // read by the second pass and by the final twiddles, after the first barrier
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    const int T = 1 << lgT;
+    const PairWalk pw(ntiles, ntx);
+    // even (par 0) or odd (par 1) rows of a tile: sequence b = column, element j = row 2j + par
+    auto loader = [=](int t, int par) {
+        const int tx = t % ntx;
+        const long long plane = t / ntx;
+        const int kx0 = tx * T;
+        const cx<R>* src = X2 + plane * PY * (long long)Sx + kx0 + (long long)par * Sx;
+        const int ncol = min(T, Hx - kx0);
+        return [=](int b, int j) -> cx<R> {
+            if (b < ncol) return ld_stream<R>(&src[umul24((unsigned)(2 * j), (unsigned)Sx) + (unsigned)b]);
+            return mk<R>(0, 0);
+        };
+    };
+    FirstIn<R, EM, false> ev, od;
+    int u = pw.first();
+    if (u < pw.u1) first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(ev, LGL, lgT, T, loader(pw.tile(u), 0));
+    while (u < pw.u1) {
+        const int un = pw.next(u);
+        const int t = pw.tile(u);
+        const int tx = t % ntx;
+        const long long plane = t / ntx;
+        const int kx0 = tx * T;
+        cx<R>* dst = Y1 + plane * ny * (long long)Sx + kx0;
+        const int ncol = min(T, Hx - kx0);
+        // A = IDFT_1024 of the even rows, written to the output rows with plain
+        // stores (kept in L2); the odd rows are fetched meanwhile
+        auto store_a = [&](int b, int n, cx<R> v) {
+            if (n < ny && b < ncol) dst[umul24((unsigned)n, (unsigned)Sx) + (unsigned)b] = v;
+        };
+        auto fetch_odd = [&]() { first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(od, LGL, lgT, T, loader(t, 1)); };
+        fft_reg<R, true, EM, false, kCols, 1, false, false, lgmax<EM>(), NT, true>(buf, LGL, lgT, T, ev, fetch_odd,
+                                                                                    store_a);
+        __syncthreads();   // the last pass read LDS; the second transform's first pass writes it
+        // B = IDFT_1024 of the odd rows; x[n] = A[n] + W_2048^-n B[n].  Both
+        // transforms give output n to the same thread, which reads back its own
+        // store of A (same address, same wave: ordered)
+        auto store_x = [&](int b, int n, cx<R> v) {
+            if (n < ny && b < ncol) {
+                cx<R>* p = &dst[umul24((unsigned)n, (unsigned)Sx) + (unsigned)b];
+                st_stream<R>(p, cadd<R>(*p, cmul<R>(v, tw_pass<R, true, true>(n << 1))));
+            }
+        };
+        auto next = [&]() {
+            if (un < pw.u1)
+                first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(ev, LGL, lgT, T, loader(pw.tile(un), 0));
+        };
+        fft_reg<R, true, EM, false, kCols, 1, false, false, lgmax<EM>(), NT, true>(buf, LGL, lgT, T, od, next,
+                                                                                    store_x);
+        __syncthreads();
+        u = un;
+    }
+}
+
 // LDS layout: element (z, c, col) at (z * 3 + c) * T + col, i.e. sequence
 // b = c*T + col with unit sequence stride and element stride 3T.
 //
@@ -771,6 +897,36 @@ static hipError_t run_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t
     return hipGetLastError();
 }
 
+// Py = 2048: two transforms of length 1024 per tile, 16 (single) or 8
+// (double) columns, 128 KiB of LDS; 512 threads, 1024 for the inverse (it
+// holds two sets of first-pass values).
+template <typename R, bool INV>
+static hipError_t run_y2(const Plan& pl, const void* in, void* out, hipStream_t s) {
+    constexpr int NT = INV ? 1024 : 512;
+    constexpr int EM = (sizeof(R) == 4 ? 32 : 16) * 512 / NT;
+    constexpr int lgT = sizeof(R) == 4 ? 4 : 3;
+    constexpr int T = 1 << lgT;
+    if (pl.Py != 2048 || 2 * pl.ny <= 1024) return hipErrorInvalidValue;
+    const int ntx = (pl.Hx + T - 1) / T;
+    const int ntiles = ntx * 3 * pl.nz * pl.nbatch;
+    const size_t lds = (size_t)1024 * T * sizeof(cx<R>);
+    const long long units = (long long)(ntiles / ntx) * ((ntx + 1) / 2);
+    if constexpr (INV) {
+        const int grid = pair_grid(
+            persistent_grid(reinterpret_cast<const void*>(&yinv2_kernel<R, EM, NT>), lds, 1LL << 30, NT), units);
+        if (grid < 2) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((yinv2_kernel<R, EM, NT>), dim3(grid), dim3(NT), lds, s, static_cast<const cx<R>*>(in),
+                           static_cast<cx<R>*>(out), pl.ny, pl.Hx, pl.Sx, lgT, ntx, ntiles);
+    } else {
+        const int grid = pair_grid(
+            persistent_grid(reinterpret_cast<const void*>(&yfwd2_kernel<R, EM, NT>), lds, 1LL << 30, NT), units);
+        if (grid < 2) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((yfwd2_kernel<R, EM, NT>), dim3(grid), dim3(NT), lds, s, static_cast<const cx<R>*>(in),
+                           static_cast<cx<R>*>(out), pl.ny, pl.Hx, pl.Sx, lgT, ntx, ntiles);
+    }
+    return hipGetLastError();
+}
+
 // Tiles of more than 256 x 32 elements (up to 128 KiB of LDS, one block per
 // CU): 512 threads of 32 elements (two radix-32 passes for Py = 1024).
 static bool y_huge(const Plan& pl) { return (long long)pl.Py * pl.ty > (long long)kNT * 32; }
@@ -786,6 +942,7 @@ static int y_lg(const Plan& pl) {
 
 template <typename R>
 hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) {
+    if (pl.Py == 2048) return run_y2<R, false>(pl, X1, X2, s);
     if constexpr (std::is_same<R, float>::value) {
         switch (y_lg<R>(pl)) {
             case 8: return run_yfwd<R, 16, kNT, 8>(pl, X1, X2, s);
@@ -816,6 +973,10 @@ hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) 
 
 template <typename R>
 hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
+    // single precision only: the double-precision variant would spill
+    if constexpr (std::is_same<R, float>::value) {
+        if (pl.Py == 2048) return run_y2<R, true>(pl, X2, Y1, s);
+    }
     if constexpr (std::is_same<R, float>::value) {
         switch (y_lg<R>(pl)) {
             case 8: return run_yinv<R, 16, kNT, 8>(pl, X2, Y1, s);

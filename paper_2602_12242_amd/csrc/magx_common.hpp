@@ -450,6 +450,39 @@ __device__ __forceinline__ void first_load(FirstIn<R, EMAX, HIN>& in, int lgL, i
 #undef MAGX_BODY
 }
 
+// Replaces every value held for the first pass by f(b, j, value), where
+// (b, j) is the sequence and the element index first_load gave it; entries
+// first_load did not fill are left alone.
+template <typename R, int RAD, int EMAX, int LAYOUT, int NC, bool HIN, int NT, class F>
+__device__ __forceinline__ void first_apply_rad(FirstIn<R, EMAX, HIN>& in, int lgL, int lgT, int nseq, F& f) {
+    constexpr int PER = EMAX / RAD > 0 ? EMAX / RAD : 1;
+    constexpr int LGR = ilog2c(RAD);
+    constexpr int RIN = HIN ? RAD / 2 : RAD;
+    const int lgnb = lgL - LGR;
+    const unsigned total = (1u << lgnb) * (unsigned)nseq;
+    const unsigned tid = (unsigned)tid_opaque();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+        const unsigned t = tid + (unsigned)(i * NT);
+        if (t < total) {
+            unsigned b, j;
+            seq_split<LAYOUT, NC>(t, lgT, lgnb, (unsigned)nseq, b, j);
+#pragma unroll
+            for (int r = 0; r < RIN; ++r)
+                in.v[i * RIN + r] = f((int)b, (int)(j + ((unsigned)r << lgnb)), in.v[i * RIN + r]);
+        }
+    }
+}
+
+template <typename R, int EMAX, int LAYOUT, int NC, bool HIN, int LGM = lgmax<EMAX>(), int NT = kNT, class F>
+__device__ __forceinline__ void first_apply(FirstIn<R, EMAX, HIN>& in, int lgL, int lgT, int nseq, F f) {
+    const int rem = lgL % LGM;
+    const int g = rem ? rem : LGM;
+#define MAGX_BODY(RADIX) first_apply_rad<R, RADIX, EMAX, LAYOUT, NC, HIN, NT>(in, lgL, lgT, nseq, f);
+    MAGX_RADIX_SWITCH(g, LGM)
+#undef MAGX_BODY
+}
+
 // fft_io with the first pass taken from registers (filled by first_load);
 // after_first() runs once the first pass has consumed them, typically to
 // issue the next tile's first_load.  Requires lgL >= 1.

@@ -55,6 +55,10 @@ CASES = {
                dict(Ms=8e5, A=1.3e-11, D=1e-3, alpha=0.1, Hbias=(0, 1e4, 0), terms=1 | 2 | 4 | 16)),
     "longest_y": ((3, 1100, 2), (2e-9, 1e-9, 2e-9),
                   dict(Ms=8e5, A=1.3e-11, alpha=0.1, terms=1 | 2)),
+    # Py = 2048: the y passes as two transforms of length 1024 (16-column
+    # tiles in single precision, three of them here, the last one ragged)
+    "y2048": ((40, 600, 2), (2e-9, 1.5e-9, 2e-9),
+              dict(Ms=8e5, A=1.3e-11, D=1e-3, Ku=3e5, eK=(0, 0, 1), alpha=0.1, Hbias=(0, 1e4, 2e3), terms=ALL)),
     # power-of-two lines (nx = 256, 1024): pencil kernels with compile-time
     # line geometry (as are the 128-cell film and the 512-cell workloads)
     "pow2_256": ((256, 3, 2), (2e-9, 2e-9, 2e-9),
@@ -188,7 +192,7 @@ def test_llg_rhs_matches_oracle(dtype):
 
 
 @pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "film", "line", "cell", "tiles", "thick", "long_y",
-                                  "pow2_256", "pow2_1024", "sq512", "sq256", "slab40", "slab64"])
+                                  "pow2_256", "pow2_1024", "sq512", "sq256", "slab40", "slab64", "y2048"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_one_rk4_step_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -241,7 +245,8 @@ def test_energy_matches_oracle(name, dtype):
     assert abs(e[5] - ref["total"]) <= (1e-11 if dtype == 1 else 2e-5) * scale
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "pow2_256", "sq512", "sq256", "slab40"])
+@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "pow2_256", "sq512", "sq256", "slab40",
+                                  "y2048"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_heff_backward_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
