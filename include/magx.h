@@ -177,7 +177,12 @@ int magx_llg_rhs(magx_ctx* ctx, const void* m, const void* H,
  * steps of size dt (Section III-C: four right-hand-side evaluations per
  * step), renormalising per p->renorm.  If `tape` is not NULL (device,
  * nsteps*tape_bytes_per_step + tape_bytes_extra) every stage input, stage
- * field and pre-normalisation length is recorded for magx_step_backward. */
+ * field and pre-normalisation length is recorded for magx_step_backward.
+ * On grids of at most 2^18 cells (whole batch), without a tape, a bias
+ * schedule or active launch timing, the steps are replayed from HIP graphs
+ * the context captures per argument signature (m, ws, p, dt, chunk of up to
+ * 16 steps; at most 8 kept, released by magx_destroy); the results are the
+ * same bit for bit. */
 int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nsteps,
               void* tape, void* ws, void* stream);
 

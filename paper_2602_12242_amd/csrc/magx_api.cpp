@@ -33,6 +33,22 @@ struct magx_ctx {
     int prof_kind;
     size_t prof_used;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_events;
+    // RK4 step sequences of small grids replayed as HIP graphs: one
+    // instantiated graph per argument signature, captured on a private stream
+    struct StepGraph {
+        void* m;
+        void* ws;
+        magx_params p;
+        double dt;
+        int nsteps;
+        const void* hbm;
+        const void* msp;
+        hipGraphExec_t exec;
+        hipStream_t last;        // stream of the last replay
+        long long heff;          // field evaluations per replay
+    };
+    std::vector<StepGraph> graphs;
+    hipStream_t cap_stream;
 };
 
 namespace magx {
@@ -434,6 +450,87 @@ static int do_step(magx_ctx* c, R* m, const magx_params* p, double dt, int nstep
     return MAGX_OK;
 }
 
+// ---- HIP graph replay of RK4 steps on small grids ------------------------------
+// A 4096-cell grid spends most of a step launching its 17 kernels; replaying a
+// captured graph of up to kGraphChunk steps removes the per-launch host cost.
+// Chunks give the same results bit for bit as one long call (the forward x
+// pass a chunk starts with reproduces the one the previous stage kernel would
+// have fused).  Used without a tape (its layout depends on the call's step
+// count), without a bias schedule (the stage biases are baked into the
+// launches) and while no launch timing is active.
+constexpr long long kGraphMaxCells = 1LL << 18;
+constexpr int kGraphChunk = 16;
+constexpr size_t kGraphCache = 8;
+
+static bool same_params(const magx_params& a, const magx_params& b) {
+    for (int k = 0; k < 3; ++k)
+        if (a.eK[k] != b.eK[k] || a.Hbias[k] != b.Hbias[k]) return false;
+    return a.Ms == b.Ms && a.A == b.A && a.D == b.D && a.Ku == b.Ku && a.alpha == b.alpha && a.gamma == b.gamma &&
+           a.mu0 == b.mu0 && a.terms == b.terms && a.renorm == b.renorm && a.check_finite == b.check_finite;
+}
+
+static bool graph_eligible(const magx_ctx* c, const void* tape) {
+    return !tape && c->sched_t.empty() && c->prof_kind == 0 && c->pl.ncell * c->pl.nbatch <= kGraphMaxCells;
+}
+
+static void drop_graph(magx_ctx::StepGraph& g) {
+    if (g.last) (void)hipStreamSynchronize(g.last);
+    (void)hipGraphExecDestroy(g.exec);
+}
+
+// The cached graph for these arguments, captured now if needed; nullptr if
+// capture failed (the caller then launches directly).
+template <typename R>
+static magx_ctx::StepGraph* step_graph(magx_ctx* c, R* m, const magx_params* p, double dt, int k, void* ws) {
+    for (auto& g : c->graphs)
+        if (g.m == m && g.ws == ws && g.dt == dt && g.nsteps == k && g.hbm == c->hbias_members &&
+            g.msp == c->ms_profile && same_params(g.p, *p))
+            return &g;
+    if (!c->cap_stream && hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        c->cap_stream = nullptr;
+        return nullptr;
+    }
+    const long long h0 = c->heff_count;
+    if (hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed) != hipSuccess) return nullptr;
+    const int rc = do_step<R>(c, m, p, dt, k, nullptr, ws, c->cap_stream);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+    const long long dh = c->heff_count - h0;
+    c->heff_count = h0;
+    hipGraphExec_t exec = nullptr;
+    const bool ok = rc == MAGX_OK && ec == hipSuccess && graph &&
+                    hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
+    if (graph) (void)hipGraphDestroy(graph);
+    if (!ok) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (c->graphs.size() >= kGraphCache) {
+        drop_graph(c->graphs.front());
+        c->graphs.erase(c->graphs.begin());
+    }
+    c->graphs.push_back({m, ws, *p, dt, k, c->hbias_members, c->ms_profile, exec, nullptr, dh});
+    return &c->graphs.back();
+}
+
+template <typename R>
+static int do_step_graphed(magx_ctx* c, R* m, const magx_params* p, double dt, int nsteps, void* ws,
+                           hipStream_t s) {
+    int done = 0;
+    while (done < nsteps) {
+        const int k = std::min(kGraphChunk, nsteps - done);
+        magx_ctx::StepGraph* g = step_graph<R>(c, m, p, dt, k, ws);
+        if (!g) break;
+        if (hipGraphLaunch(g->exec, s) != hipSuccess) return MAGX_EHIP;
+        g->last = s;
+        c->heff_count += g->heff;
+        if (p->check_finite) c->chk_stream = s;
+        done += k;
+    }
+    if (done < nsteps) return do_step<R>(c, m, p, dt, nsteps - done, nullptr, ws, s);
+    return MAGX_OK;
+}
+
 // Forward Euler (stage 0 of the stage kernel), ping-pong between m and a
 // workspace field.
 template <typename R>
@@ -711,6 +808,7 @@ int magx_tensor_init_batched(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, 
     c->chk_flag = nullptr;
     c->chk_stream = nullptr;
     c->chk_hold = 0;
+    c->cap_stream = nullptr;
     *ctx = c;
     return MAGX_OK;
 }
@@ -777,6 +875,10 @@ int magx_step(magx_ctx* ctx, void* m, const magx_params* p, double dt, int nstep
     if (rc) return rc;
     if (nsteps == 0) return MAGX_OK;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    if (graph_eligible(ctx, tape)) {
+        if (ctx->pl.dtype == MAGX_F32) return do_step_graphed<float>(ctx, static_cast<float*>(m), p, dt, nsteps, ws, s);
+        return do_step_graphed<double>(ctx, static_cast<double*>(m), p, dt, nsteps, ws, s);
+    }
     if (ctx->pl.dtype == MAGX_F32)
         return do_step<float>(ctx, static_cast<float*>(m), p, dt, nsteps, static_cast<float*>(tape), ws, s);
     return do_step<double>(ctx, static_cast<double*>(m), p, dt, nsteps, static_cast<double*>(tape), ws, s);
@@ -1016,6 +1118,8 @@ void magx_destroy(magx_ctx* ctx) {
         (void)hipEventDestroy(ev.first);
         (void)hipEventDestroy(ev.second);
     }
+    for (auto& g : ctx->graphs) drop_graph(g);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
 }
 
