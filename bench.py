@@ -221,7 +221,10 @@ def oracle_rates(w, max_cells=(128, 128)):
             "sample": f"one H_eff and one RK4 step on {n[0]}x{n[1]}x{n[2]} cells, scaled by cell count"}
 
 
-def config_measurements(magx, torch, timeit):
+CONFIG_NAMES = ("film", "dmi", "demag", "adjoint", "large")
+
+
+def config_measurements(magx, torch, timeit, names=CONFIG_NAMES, oracle=True):
     """Every workload in float32 and float64: rates, roofline fractions under
     the bytes model, errors against the oracle and between precisions."""
     import numpy as np
@@ -230,7 +233,7 @@ def config_measurements(magx, torch, timeit):
     out = {}
     hb = model_bytes_per_cell("heff")
     rb = model_bytes_per_cell("rk4")
-    for name in ("film", "dmi", "demag", "adjoint", "large"):
+    for name in names:
         w = WORKLOADS[name]
         N = w.ncell
         p = magx.make_params(**w.material())
@@ -328,7 +331,8 @@ def config_measurements(magx, torch, timeit):
                                  "model_frac": round(gb / PEAK_HBM_GBS, 4)}
             del ctx, store, tape, mwork, gm, mm
             torch.cuda.empty_cache()
-        rec["oracle"] = oracle_rates(w)
+        if oracle:
+            rec["oracle"] = oracle_rates(w)
         out[name] = rec
     return out
 
@@ -400,13 +404,13 @@ def _pmc_rows(path, counter):
     return rows
 
 
-def trace_summary(db, out_path, command):
+def trace_summary(db, out_path, title, command):
     """Writes a kernel-time summary (rocprofv3 --kernel-trace --stats result)."""
     import sqlite3
     con = sqlite3.connect(db)
     rows = list(con.execute("select name, total_calls, total_duration, average, percentage from top_kernels "
                             "order by total_duration desc"))
-    lines = ["# rocprofv3 kernel trace: demag 512x512x32 FP32, checkpointed forward+adjoint RK4 steps", "",
+    lines = ["# rocprofv3 kernel trace: " + title, "",
              "command: `" + command + "`", "",
              "| kernel | calls | total ms | mean us | share % |", "|---|---|---|---|---|"]
     for name, calls, tot, avg, pct in rows:
@@ -451,7 +455,7 @@ def main():
         pmc_summarize(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
         return
     if len(sys.argv) > 1 and sys.argv[1] == "--trace-summarize":
-        trace_summary(sys.argv[2], sys.argv[3], " ".join(sys.argv[4:]))
+        trace_summary(sys.argv[2], sys.argv[3], sys.argv[4], " ".join(sys.argv[5:]))
         return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -459,6 +463,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-extras", action="store_true", help="skip the FP64/H_eff side measurements")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--config", choices=CONFIG_NAMES, default=None,
+                    help="measure this workload alone (no headline step; for profiling runs)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -472,6 +478,21 @@ def main():
 
     from paper_2602_12242_amd import magx
     from workloads import WORKLOADS, bernoulli_mask, initial_state
+
+    def timeit(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - a) / reps
+
+    if args.config:
+        torch.cuda.set_device(0)
+        print(json.dumps({"configs": config_measurements(magx, torch, timeit, (args.config,), oracle=False)}),
+              flush=True)
+        return
 
     w = WORKLOADS["demag"]
     n, d = w.n, w.d
@@ -526,15 +547,14 @@ def main():
 
     extras = {}
     if not args.no_extras:
-        def timeit(fn, reps):
-            fn()
-            torch.cuda.synchronize()
-            a = time.perf_counter()
-            for _ in range(reps):
-                fn()
-            torch.cuda.synchronize()
-            return (time.perf_counter() - a) / reps
-
+        # practical bandwidth of the passes' access patterns on this device:
+        # plain copy, and in-place read + write with the z and y tilings
+        probe = {}
+        for kind, label in ((0, "copy"), (1, "z_tiling"), (2, "y_tiling")):
+            nbytes = ctx.memory_probe(kind)
+            t = timeit(lambda: ctx.memory_probe(kind), 10)
+            probe[label + "_GBps"] = round(nbytes / t / 1e9, 1)
+        roofline["pattern_ceilings"] = probe
         del store, tape, mwork
         torch.cuda.empty_cache()
         extras["configs"] = config_measurements(magx, torch, timeit)

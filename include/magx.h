@@ -313,6 +313,17 @@ int magx_spectrum_layout(const magx_ctx* ctx, int dims[5]);
 int magx_profile_start(magx_ctx* ctx, int kind);
 int magx_profile_stop(magx_ctx* ctx, long long* launches, double* total_ms);
 
+/* Diagnostics: enqueues one pass of a plain memory pattern, with no
+ * arithmetic, over the X2 region of the workspace ws (its contents are
+ * overwritten): kind 0 copies its first half onto its second half as float4;
+ * kind 1 reads and writes it in place with the z pass's tiling (tiles of 32
+ * columns, every row z < nz of the three components, rows one plane apart);
+ * kind 2 reads and writes it in place with the y pass's tiling (16 columns x
+ * all Py rows of one plane).  *bytes receives the bytes read plus written.
+ * The time of such a pass is the practical bandwidth of that pattern on
+ * this device.  Single-precision contexts only (MAGX_EDTYPE otherwise). */
+int magx_memory_probe(magx_ctx* ctx, int kind, void* ws, void* stream, double* bytes);
+
 const char* magx_strerror(int code);
 void magx_destroy(magx_ctx* ctx);
 

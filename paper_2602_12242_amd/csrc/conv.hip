@@ -1076,6 +1076,74 @@ hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStr
     return em_big(3LL * pl.Pz * pl.tz) ? run_zconv<R, 32>(pl, X2, spec, Ms, s) : run_zconv<R, 16>(pl, X2, spec, Ms, s);
 }
 
+// ---- memory patterns without arithmetic (diagnostics) ---------------------------
+// The practical bandwidth of the access patterns of the passes, measured on
+// the same buffer: a float4 stream copy, and in-place read + write (scaled by
+// a runtime factor 1, so nothing is elided) with the z pass's tiling (tiles
+// of 32 columns x the nz rows of three components, rows a plane apart) and
+// with the y pass's (16 columns x Py rows of one plane).
+__global__ void __launch_bounds__(256) probe_copy_kernel(const float4* __restrict__ a, float4* __restrict__ b,
+                                                         long long n4) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n4) b[i] = a[i];
+}
+
+__global__ void __launch_bounds__(256) probe_ztile_kernel(float2* X, int nz, int Py, int Hx, int Sx, int ntx,
+                                                          float f) {
+    const int col = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const long long plane = (long long)Py * Sx, comp = (long long)nz * plane;
+    const int ky = blockIdx.x / ntx, tx = blockIdx.x % ntx;
+    const int kx = tx * 32 + col;
+    if (kx >= Hx) return;
+    float2* base = X + (long long)ky * Sx + kx;
+    for (int z = g; z < nz; z += 8) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float2* q = base + c * comp + z * plane;
+            const float2 v = *q;
+            *q = make_float2(v.x * f, v.y * f);
+        }
+    }
+}
+
+__global__ void __launch_bounds__(512) probe_ytile_kernel(float2* X, int Py, int Hx, int Sx, int ntx, float f) {
+    const int col = threadIdx.x & 15, rg = threadIdx.x >> 4;
+    const long long pl = blockIdx.x / ntx;
+    const int tx = blockIdx.x % ntx;
+    const int kx = tx * 16 + col;
+    if (kx >= Hx) return;
+    float2* base = X + pl * Py * (long long)Sx + kx;
+    for (int r = rg; r < Py; r += 32) {
+        float2* q = base + (long long)r * Sx;
+        const float2 v = *q;
+        *q = make_float2(v.x * f, v.y * f);
+    }
+}
+
+hipError_t launch_memory_probe(const Plan& pl, int kind, void* X2, hipStream_t s, double* bytes) {
+    const long long n2 = 3LL * pl.nbatch * pl.nz * pl.Py * pl.Sx;       // complex values in X2
+    const double useful = 2.0 * 3.0 * pl.nbatch * pl.nz * pl.Py * (double)pl.Hx * sizeof(float2);
+    if (kind == 0) {
+        const long long n4 = n2 / 4;                                     // float4 in each half
+        hipLaunchKernelGGL(probe_copy_kernel, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, s,
+                           static_cast<const float4*>(X2), static_cast<float4*>(X2) + n4, n4);
+        *bytes = 2.0 * n4 * sizeof(float4);
+    } else if (kind == 1) {
+        const int ntx = (pl.Hx + 31) / 32;
+        for (int mb = 0; mb < pl.nbatch; ++mb)
+            hipLaunchKernelGGL(probe_ztile_kernel, dim3((unsigned)(pl.Py * ntx)), dim3(256), 0, s,
+                               static_cast<float2*>(X2) + (long long)mb * 3 * pl.nz * pl.Py * pl.Sx, pl.nz, pl.Py,
+                               pl.Hx, pl.Sx, ntx, 1.0f);
+        *bytes = useful;
+    } else {
+        const int ntx = (pl.Hx + 15) / 16;
+        hipLaunchKernelGGL(probe_ytile_kernel, dim3((unsigned)(3 * pl.nbatch * pl.nz * ntx)), dim3(512), 0, s,
+                           static_cast<float2*>(X2), pl.Py, pl.Hx, pl.Sx, ntx, 1.0f);
+        *bytes = useful;
+    }
+    return hipGetLastError();
+}
+
 template hipError_t launch_yfwd<float>(const Plan&, const void*, void*, hipStream_t);
 template hipError_t launch_yfwd<double>(const Plan&, const void*, void*, hipStream_t);
 template hipError_t launch_yinv<float>(const Plan&, const void*, void*, hipStream_t);

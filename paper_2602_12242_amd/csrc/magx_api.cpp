@@ -1088,6 +1088,14 @@ const char* magx_strerror(int code) {
     }
 }
 
+int magx_memory_probe(magx_ctx* ctx, int kind, void* ws, void* stream, double* bytes) {
+    if (!ctx || !ws || !bytes || kind < 0 || kind > 2) return MAGX_EINVAL;
+    if (ctx->pl.dtype != MAGX_F32) return MAGX_EDTYPE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (launch_memory_probe(ctx->pl, kind, bptr(ws, ctx->pl.off_x2), s, bytes) != hipSuccess) return MAGX_EHIP;
+    return MAGX_OK;
+}
+
 int magx_profile_start(magx_ctx* ctx, int kind) {
     if (!ctx || kind < 0 || kind > kProfBstage) return MAGX_EINVAL;
     ctx->prof_kind = kind;

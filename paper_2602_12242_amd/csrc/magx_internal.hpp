@@ -80,6 +80,8 @@ template <typename R>
 hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s);
 template <typename R>
 hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s);
+// Diagnostic memory patterns over X2 (single precision plans): 0 copy, 1 z tiling, 2 y tiling.
+hipError_t launch_memory_probe(const Plan& pl, int kind, void* X2, hipStream_t s, double* bytes);
 
 // Pencil kernels (pencil.hip): x passes fused with the local field, LLG and RK4.
 template <typename R>

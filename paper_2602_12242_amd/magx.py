@@ -56,7 +56,7 @@ EXPORTS = ("magx_sizes", "magx_sizes_batched", "magx_tensor_init", "magx_tensor_
            "magx_set_member_bias", "magx_ctx_batch", "magx_set_ms_profile", "magx_heff", "magx_llg_rhs", "magx_step", "magx_step_static", "magx_step_mri",
            "magx_step_euler", "magx_set_bias_schedule", "magx_get_time",
            "magx_heff_backward", "magx_step_backward", "magx_rollout_forward", "magx_rollout_backward",
-           "magx_energy", "magx_status", "magx_heff_count", "magx_ctx_info", "magx_spectrum_layout", "magx_profile_start",
+           "magx_energy", "magx_status", "magx_heff_count", "magx_ctx_info", "magx_spectrum_layout", "magx_memory_probe", "magx_profile_start",
            "magx_profile_stop", "magx_strerror", "magx_destroy")
 
 _lib = None
@@ -97,6 +97,7 @@ def load(path=LIB_PATH):
         "magx_heff_count": (ctypes.c_longlong, [vp]),
         "magx_ctx_info": (i, [vp, P(magx_grid), P(ctypes.c_int)]),
         "magx_spectrum_layout": (i, [vp, P(ctypes.c_int)]),
+        "magx_memory_probe": (i, [vp, i, vp, vp, P(d)]),
         "magx_profile_start": (i, [vp, i]),
         "magx_profile_stop": (i, [vp, P(ctypes.c_longlong), P(ctypes.c_double)]),
         "magx_strerror": (ctypes.c_char_p, [i]),
@@ -354,6 +355,14 @@ class Context:
 
     PROFILE_KINDS = {"xfwd": 1, "yfwd": 2, "zconv": 3, "yinv": 4, "stage": 5, "field": 6, "bstart": 7,
                      "bstage": 8}
+
+    def memory_probe(self, kind):
+        """Enqueues one plain memory pattern over the workspace (0 copy, 1 z
+        tiling, 2 y tiling) and returns the bytes it moves."""
+        b = ctypes.c_double()
+        _check(self.lib.magx_memory_probe(self.h, int(kind), _ptr(self.ws), _stream(), ctypes.byref(b)),
+               "magx_memory_probe")
+        return float(b.value)
 
     def profile_start(self, kind):
         _check(self.lib.magx_profile_start(self.h, self.PROFILE_KINDS[kind]), "magx_profile_start")

@@ -138,6 +138,8 @@ def test_entry_points_reject_null_arguments_without_a_gpu():
     assert lib.magx_energy(nul, nul, ctypes.byref(p), nul, nul, nul) == -1
     assert lib.magx_heff_count(nul) == -1
     assert lib.magx_status(nul) == -1
+    b = ctypes.c_double()
+    assert lib.magx_memory_probe(nul, 0, nul, nul, ctypes.byref(b)) == -1
     assert lib.magx_step_static(nul, nul, ctypes.byref(p), 1e-13, 1, nul) == -1
     assert lib.magx_step_euler(nul, nul, ctypes.byref(p), 1e-13, 1, nul, nul) == -1
     assert lib.magx_step_mri(nul, nul, ctypes.byref(p), 1e-13, 1e-14, 1, nul, nul) == -1

@@ -107,3 +107,21 @@ def test_rollout_counts_as_one_checked_call():
     ctx.rollout_backward(store, p_on, 1e-13, 6, 2, gm)
     assert ctx.status() == 0
     assert math.isfinite(float(gm.abs().sum()))
+
+
+def test_memory_probe_patterns():
+    # the diagnostic memory patterns run over the workspace and report the
+    # bytes they move: the copy moves the X2 region once, the tilings read and
+    # write every stored column of every row
+    from paper_2602_12242_amd import magx
+    n = (37, 11, 5)
+    ctx = magx.Context(n, (2e-9, 2e-9, 2e-9), dtype=0)
+    Px, Py, Pz = 128, 32, 16
+    Hx = Px // 2 + 1
+    Sx = (Hx + 15) // 16 * 16
+    assert ctx.memory_probe(0) == 3 * n[2] * Py * Sx * 8
+    assert ctx.memory_probe(1) == 2 * 3 * n[2] * Py * Hx * 8
+    assert ctx.memory_probe(2) == 2 * 3 * n[2] * Py * Hx * 8
+    torch.cuda.synchronize()
+    with pytest.raises(magx.MagxError):
+        magx.Context(n, (2e-9, 2e-9, 2e-9), dtype=1).memory_probe(0)
