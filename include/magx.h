@@ -130,7 +130,8 @@ int magx_sizes_batched(const magx_grid* g, magx_dtype dt, int nbatch, magx_size_
  * (cell-averaged Newell closed forms near the source cell, Gauss-Legendre
  * quadrature of the dipole kernel against the cell-cell autocorrelation
  * elsewhere), transformed in double precision and, for MAGX_F32, rounded once
- * to float.  `spectrum` (device, spectrum_bytes) is kept by the context and
+ * to float.  `spectrum` (device, spectrum_bytes, 16-byte aligned as every
+ * device allocation is; MAGX_EINVAL otherwise) is kept by the context and
  * must stay valid until magx_destroy; `scratch` (device, init_scratch_bytes)
  * is free again when the stream reaches the end of this call's work.
  * On success *ctx is set; on failure *ctx is NULL. */

@@ -633,6 +633,28 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
     }
 }
 
+// Copy of nbytes (a multiple of 16) from 16-byte aligned global memory to LDS
+// without registers: each wave moves 64 x 16 bytes per instruction
+// (global_load_lds_dwordx4 writes lane i's 16 bytes at the wave's LDS address
+// + 16 i).  Completion is counted by the vector memory counter: the caller
+// waits for it and synchronises the block before the copy is read.
+template <int NT>
+__device__ __forceinline__ void lds_copy_async(const void* src, void* lds, int nbytes) {
+    const int lane = (int)threadIdx.x & 63;
+    const int w0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6) * 64;
+    const int n16 = nbytes >> 4;
+    for (int base = w0; base < n16; base += NT) {
+        const int piece = base + lane;
+        if (piece < n16)
+            __builtin_amdgcn_global_load_lds(
+                static_cast<const char*>(src) + (size_t)piece * 16,
+                (__attribute__((address_space(3))) void*)(static_cast<char*>(lds) + (size_t)base * 16), 16, 0, 0);
+    }
+}
+
+// s_waitcnt vmcnt(0): every vector memory access of the wave has completed
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Register-resident z pass for Pz = 128 (single precision, nz = 33 ... 64).
 // Sixteen threads per column, T = 16 columns per tile (256 threads).
 // Thread (col, g), g < 16, holds the elements z = g + 16 r (r < 8; r < 4 are
@@ -646,15 +668,19 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
 // retraces the steps (length-8 inverse DFTs over m, W_16^(-p g'), exchange,
 // recombination a + (-1)^h W_16^(-g') c of the two parities, conjugate
 // twiddles, length-8 inverse DFT over k1); rows z >= nz are not written.
-// The tensor spectrum is in the tile-major layout with a tile width of 16.
+// The tensor spectrum is in the tile-major layout with a tile width of 16; a
+// tile's block is copied to LDS by direct global-to-LDS loads, issued one
+// tile ahead while the inverse transform runs.
 template <typename R>
 __global__ void __launch_bounds__(256) zconvr128_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
                                                         int nz, int Py, int Hx, int Sx, int ntx,
                                                         int units_per_member, int nunits) {
     constexpr int T = 16, PZ = 128, Hz = PZ / 2 + 1;
     constexpr int LGPZ = 7;
+    constexpr int TSB = 6 * Hz * T * (int)sizeof(R);
     extern __shared__ unsigned char smem_raw[];
-    cx<R>* E = reinterpret_cast<cx<R>*>(smem_raw);   // [3][8][16][T]
+    R* TS = reinterpret_cast<R*>(smem_raw);                        // [6][Hz][T]
+    cx<R>* E = reinterpret_cast<cx<R>*>(smem_raw + TSB);          // [3][8][16][T]
     const int tid = threadIdx.x;
     const int col = tid & (T - 1);
     const int g = tid / T;                          // forward layout: row phase g < 16
@@ -703,28 +729,23 @@ __global__ void __launch_bounds__(256) zconvr128_kernel(cx<R>* __restrict__ X2, 
                 pin[c * 4 + r] = z < nz ? v : mk<R>((R)0, (R)0);
             }
     };
+    auto tensor_copy = [&](int u) {
+        const Tile d = tile_of(u);
+        lds_copy_async<256>(spec + (long long)(d.kyo * ntx + d.tx) * 6 * (Hz * T), TS, TSB);
+    };
     const int npairs = gridDim.x >> 1;
     const int pr = lbp >> 1;
     const int t0 = (int)((long long)nunits * pr / npairs);
     const int t1 = (int)((long long)nunits * (pr + 1) / npairs);
-    if (t0 < t1) load_tile(t0);
+    if (t0 < t1) {
+        tensor_copy(t0);
+        load_tile(t0);
+    }
     for (int t = t0; t < t1; ++t) {
         const Tile d = tile_of(t);
         const R sy = d.ky <= Py / 2 ? (R)1 : (R)-1;
         // tensor values of this thread's kz = k1 + 16 m + 8 p: octant row kz
         // for m < 4 and 128 - kz (odd components change sign) for m >= 4
-        R tv[8][6];
-        {
-            const R* blk = spec + (long long)(d.kyo * ntx + d.tx) * 6 * (Hz * T);
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                const int kz = k1h + 16 * m + 8 * par;
-                const int row = m < 4 ? kz : PZ - kz;
-#pragma unroll
-                for (int c6 = 0; c6 < 6; ++c6)
-                    tv[m][c6] = ld_off<R>(blk, (unsigned)(c6 * (Hz * T) + row * T + col) * (unsigned)sizeof(R));
-            }
-        }
         // forward: length-8 DFT over r, twiddles W_128^(g k1), exchange
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -738,6 +759,7 @@ __global__ void __launch_bounds__(256) zconvr128_kernel(cx<R>* __restrict__ X2, 
             for (int k1 = 0; k1 < 8; ++k1)
                 E[((c * 8 + k1) * 16 + g) * T + col] = k1 == 0 ? v[0] : cmul<R>(v[k1], w1[k1]);
         }
+        wait_vm_all();
         __syncthreads();
         // length-16 DFT over g, parity p of the outputs: X[c][m] at kz = k1 + 8 (2 m + p)
         cx<R> X[3][8];
@@ -766,8 +788,10 @@ __global__ void __launch_bounds__(256) zconvr128_kernel(cx<R>* __restrict__ X2, 
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
             const R sz = m < 4 ? (R)1 : (R)-1;
-            const R nxx = tv[m][0], nyy = tv[m][1], nzz = tv[m][2];
-            const R nxy = sy * tv[m][3], nxz = sz * tv[m][4], nyz = sy * sz * tv[m][5];
+            const int kz = k1h + 16 * m + 8 * par;
+            const R* tv = TS + (m < 4 ? kz : PZ - kz) * T + col;
+            const R nxx = tv[0], nyy = tv[Hz * T], nzz = tv[2 * Hz * T];
+            const R nxy = sy * tv[3 * Hz * T], nxz = sz * tv[4 * Hz * T], nyz = sy * sz * tv[5 * Hz * T];
             const cx<R> mx = X[0][m], my = X[1][m], mz = X[2][m];
             X[0][m] = mk<R>(nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y);
             X[1][m] = mk<R>(nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y);
@@ -777,6 +801,7 @@ __global__ void __launch_bounds__(256) zconvr128_kernel(cx<R>* __restrict__ X2, 
         if (t + 1 < t1) load_tile(t + 1);
         // inverse: length-8 inverse DFTs over m, W_16^(-p g'), exchange back
         __syncthreads();   // every thread has read its exchange values
+        if (t + 1 < t1) tensor_copy(t + 1);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             cx<R> u[8];
@@ -820,6 +845,215 @@ __global__ void __launch_bounds__(256) zconvr128_kernel(cx<R>* __restrict__ X2, 
                 const int z = g + 16 * n1;
                 if (okc && z < nz)
                     st_stream<R>(&base[(unsigned)c * comp_stride + (unsigned)z * plane_stride + (unsigned)col], v[n1]);
+            }
+        }
+        __syncthreads();   // the next tile's forward exchange rewrites E
+    }
+}
+
+// Register-resident z pass for double precision, Pz = 16 P (P = 1, 2, 4, 8):
+// G = 4 P threads per column, each holding four values per component, and
+// T = 64 / P columns per tile (8 for P = 8: 256 threads, 128-byte rows).  Row layout: thread (col, g) holds
+// z = g + G r, r < 4, of all three components (r < 2 lie inside the box).
+// Forward: a length-4 DFT over r, the twiddles W_Pz^(g k1), one LDS exchange.
+// The length-G DFT over g at k2 = p + P m is split by decimation in frequency
+// with g = g' + 4 h: thread (col, q), k1 = q & 3, p = q >> 2, forms
+// b[g'] = W_G^(g' p) sum_h u[g' + 4 h] W_P^(h p) (the length-P DFT over h at
+// frequency p) and takes a length-4 DFT over g'; it then owns kz = q + G m
+// (m < 4) of all three components, so the 3x3 product runs on registers.
+// Inverse: length-4 inverse DFT over m, twiddles W_G^(-g' p), exchange; the
+// thread of row phase g = g' + 4 h sums the P parts with W_P^(-h p), applies
+// W_Pz^(-g k1) and takes a length-4 inverse DFT over k1 for the rows g and
+// g + G.  For P <= 4 a wave spans at most four consecutive g, so p = h = g >> 2
+// is the same for the whole wave and the twiddles of the split are uniform
+// (scalar registers); for P = 8 they are per lane.
+// The tile's tensor block ([6][Hz][T] of the tile-major spectrum, tile width
+// T) is copied to LDS by direct global-to-LDS loads, issued one tile ahead
+// while the inverse transform runs, so it occupies no registers.
+template <int P> struct ZD {
+    static constexpr int G = 4 * P, PZ = 4 * G, T = 64 / P, Hz = PZ / 2 + 1, NT = G * T;
+    static constexpr bool UNIFORM = 64 / T <= 4;                       // p = g >> 2 uniform per wave
+    static constexpr int TS_BYTES = 6 * Hz * T * 8;                    // tensor block (double)
+    static constexpr int LDS_BYTES = TS_BYTES + 3 * 4 * G * T * 16;    // + exchange [3][4][G][T] complex
+};
+
+template <typename R, int P>
+__global__ void __launch_bounds__(ZD<P>::NT)
+    zconvd_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms, int nz, int Py, int Hx, int Sx,
+                  int ntx, int units_per_member, int nunits) {
+    constexpr int G = ZD<P>::G, PZ = ZD<P>::PZ, T = ZD<P>::T, Hz = ZD<P>::Hz, NT = ZD<P>::NT;
+    constexpr int LGPZ = ilog2c(PZ), LGG = ilog2c(G), LGP = ilog2c(P), LGT = ilog2c(T);
+    extern __shared__ unsigned char smem_raw[];
+    R* TS = reinterpret_cast<R*>(smem_raw);                                // [6][Hz][T]
+    cx<R>* E = reinterpret_cast<cx<R>*>(smem_raw + ZD<P>::TS_BYTES);    // [3][4][G][T]
+    const int tid = threadIdx.x;
+    const int col = tid & (T - 1);
+    const int g = tid >> LGT;                       // row phase; spectral index q = g
+    __builtin_assume(g >= 0 && g < G);
+    const int k1s = g & 3;                          // spectral layout: k1 = q & 3
+    const int gq = g & 3;                           // inverse gather: g' = g & 3
+    const int pu = ZD<P>::UNIFORM ? __builtin_amdgcn_readfirstlane(g >> 2) : (g >> 2);   // p = h = g >> 2
+    const unsigned plane_stride = (unsigned)Py * (unsigned)Sx;
+    const unsigned comp_stride = (unsigned)nz * plane_stride;
+    const R s = -Ms;
+    // w1[k1] = W_Pz^(g k1); wp[h] = W_P^(h p); wg[g'] = W_G^(g' p) (index 0 unused)
+    cx<R> w1[4], wp[P], wg[4];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) w1[k1] = tw_fwd<R>(((g * k1) & (PZ - 1)) << (kTwLog - LGPZ));
+#pragma unroll
+    for (int hh = 0; hh < P; ++hh) {
+        wp[hh] = tw_fwd<R>(((hh * pu) & (P - 1)) << (kTwLog - LGP));
+        if constexpr (ZD<P>::UNIFORM) wp[hh] = wave_uniform<R>(wp[hh]);
+    }
+#pragma unroll
+    for (int gp = 0; gp < 4; ++gp) {
+        wg[gp] = tw_fwd<R>(((gp * pu) & (G - 1)) << (kTwLog - LGG));
+        if constexpr (ZD<P>::UNIFORM) wg[gp] = wave_uniform<R>(wg[gp]);
+    }
+    struct Tile {
+        int mb, kx0, ky, tx, kyo;
+    };
+    const int lbp = xcd_logical_block(blockIdx.x, gridDim.x);
+    const int side = lbp & 1;
+    auto tile_of = [=](int u) {
+        Tile d;
+        d.mb = u / units_per_member;
+        const int r = u - d.mb * units_per_member;
+        const int q = r / ntx;
+        d.tx = r - q * ntx;
+        d.kyo = side ? (q == 0 ? Py >> 1 : q) : q;
+        d.ky = side ? (q == 0 ? Py >> 1 : Py - q) : q;
+        d.kx0 = d.tx * T;
+        return d;
+    };
+    auto base_of = [=](const Tile& d) {
+        return X2 + (long long)d.mb * 3 * comp_stride + (long long)d.ky * Sx + d.kx0;
+    };
+    auto tensor_copy = [&](int u) {
+        const Tile d = tile_of(u);
+        lds_copy_async<NT>(spec + (long long)(d.kyo * ntx + d.tx) * 6 * (Hz * T), TS, ZD<P>::TS_BYTES);
+    };
+    // inputs: rows g (always below nz > G) and g + G of the three components,
+    // columns beyond Hx read at the clamped column (their values are never stored)
+    cx<R> pin[6];
+    auto load_tile = [&](int u) {
+        const Tile d = tile_of(u);
+        const cx<R>* base = base_of(d);
+        const unsigned voff = (unsigned)g * plane_stride + (unsigned)min(col, Hx - 1 - d.kx0);
+        const bool two = g + G < nz;
+        const unsigned zoff = two ? (unsigned)G * plane_stride : 0u;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            pin[c * 2] = base[(unsigned)c * comp_stride + voff];
+            const cx<R> v = base[(unsigned)c * comp_stride + zoff + voff];
+            pin[c * 2 + 1] = two ? v : mk<R>((R)0, (R)0);
+        }
+    };
+    const int npairs = gridDim.x >> 1;
+    const int pr = lbp >> 1;
+    const int t0 = (int)((long long)nunits * pr / npairs);
+    const int t1 = (int)((long long)nunits * (pr + 1) / npairs);
+    if (t0 < t1) {
+        tensor_copy(t0);
+        load_tile(t0);
+    }
+    for (int t = t0; t < t1; ++t) {
+        const Tile d = tile_of(t);
+        const R sy = d.ky <= Py / 2 ? (R)1 : (R)-1;
+        // forward: length-4 DFT over r (two nonzero inputs), twiddles W_Pz^(g k1), exchange
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const cx<R> x0 = cscale<R>(pin[c * 2], s), x1 = cscale<R>(pin[c * 2 + 1], s);
+            cx<R> a[4];
+            a[0] = cadd<R>(x0, x1);
+            a[1] = cadd<R>(x0, mul_mi<R, false>(x1));
+            a[2] = csub<R>(x0, x1);
+            a[3] = csub<R>(x0, mul_mi<R, false>(x1));
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1)
+                E[((c * 4 + k1) * G + g) * T + col] = k1 == 0 ? a[0] : cmul<R>(a[k1], w1[k1]);
+        }
+        wait_vm_all();     // this wave's part of the tensor block has arrived
+        __syncthreads();
+        // length-G DFT over g at k2 = p + P m: X[c][m] at kz = q + G m
+        cx<R> X[3][4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const cx<R>* src = E + (c * 4 + k1s) * G * T + col;
+            cx<R> b[4];
+#pragma unroll
+            for (int gp = 0; gp < 4; ++gp) b[gp] = src[gp * T];
+#pragma unroll
+            for (int hh = 1; hh < P; ++hh) {
+#pragma unroll
+                for (int gp = 0; gp < 4; ++gp) b[gp] = cadd<R>(b[gp], cmul<R>(src[(gp + 4 * hh) * T], wp[hh]));
+            }
+#pragma unroll
+            for (int gp = 1; gp < 4; ++gp) b[gp] = cmul<R>(b[gp], wg[gp]);
+            dft4<R, false>(b);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) X[c][m] = b[m];
+        }
+        // spectral product N M (its factor -Ms was applied to the inputs); the
+        // tensor at kz = q + G m sits at the octant rows q, G + q, 2G - q and
+        // G - q (the last two mirrored: odd components negated, except at kz = Pz/2)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int row = m == 0 ? g : (m == 1 ? G + g : (m == 2 ? 2 * G - g : G - g));
+            const R* tv = TS + row * T + col;
+            const R sz = m < 2 || (m == 2 && g == 0) ? (R)1 : (R)-1;
+            const R nxx = tv[0], nyy = tv[Hz * T], nzz = tv[2 * Hz * T];
+            const R nxy = sy * tv[3 * Hz * T], nxz = sz * tv[4 * Hz * T], nyz = sy * sz * tv[5 * Hz * T];
+            const cx<R> mx = X[0][m], my = X[1][m], mz = X[2][m];
+            X[0][m] = mk<R>(nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y);
+            X[1][m] = mk<R>(nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y);
+            X[2][m] = mk<R>(nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y);
+        }
+        // the spectra are formed here, not after the barrier (which would keep
+        // every exchange value and tensor entry in registers across it)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int m = 0; m < 4; ++m) keep_in_regs<R>(X[c][m]);
+        __syncthreads();   // every thread has read its exchange values and tensor block
+        // the next tile's tensor block and inputs are in flight during the inverse transform
+        if (t + 1 < t1) {
+            tensor_copy(t + 1);
+            load_tile(t + 1);
+        }
+        // inverse: length-4 inverse DFTs over m, W_G^(-g' p), exchange back as [3][4][P][4][T]
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<R> u[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) u[m] = X[c][m];
+            dft4<R, true>(u);
+            cx<R>* dst = E + (((c * 4 + k1s) * P + pu) * 4) * T + col;
+#pragma unroll
+            for (int gp = 0; gp < 4; ++gp) dst[gp * T] = gp == 0 ? u[0] : cmul<R>(u[gp], cconj<R>(wg[gp]));
+        }
+        __syncthreads();
+        // row phase g = g' + 4 h: sum over the parts p' with W_P^(-h p'),
+        // conjugate twiddles, length-4 inverse DFT over k1; rows g and g + G
+        cx<R>* base = base_of(d);
+        const bool okc = d.kx0 + col < Hx;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            cx<R> e[4];
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) {
+                const cx<R>* src = E + ((c * 4 + k1) * P * 4 + gq) * T + col;
+                cx<R> acc = src[0];
+#pragma unroll
+                for (int pp = 1; pp < P; ++pp) acc = cadd<R>(acc, cmul<R>(src[pp * 4 * T], cconj<R>(wp[pp])));
+                e[k1] = k1 == 0 ? acc : cmul<R>(acc, cconj<R>(w1[k1]));
+            }
+            dft4<R, true>(e);
+            if (okc) {
+                st_stream<R>(&base[(unsigned)c * comp_stride + (unsigned)g * plane_stride + (unsigned)col], e[0]);
+                if (g + G < nz)
+                    st_stream<R>(&base[(unsigned)c * comp_stride + (unsigned)(g + G) * plane_stride + (unsigned)col],
+                                 e[1]);
             }
         }
         __syncthreads();   // the next tile's forward exchange rewrites E
@@ -1041,11 +1275,13 @@ static hipError_t run_zconvr(const Plan& pl, void* X2, const void* spec, float M
 }
 
 static hipError_t run_zconvr128(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
-    if (pl.Pz != 128 || pl.tz != 16 || 2 * pl.nz > pl.Pz || 4 * pl.nz <= pl.Pz) return hipErrorInvalidValue;
+    if (pl.Pz != 128 || pl.tz != 16 || 2 * pl.nz > pl.Pz || 4 * pl.nz <= pl.Pz ||
+        (reinterpret_cast<uintptr_t>(spec) & 15) != 0)
+        return hipErrorInvalidValue;
     const int ntx = pl.ntz;
     const int upm = ntx * (pl.Py / 2);
     const long long nunits = (long long)upm * pl.nbatch;
-    const size_t lds = (size_t)3 * 8 * 16 * 16 * sizeof(cx<float>);
+    const size_t lds = (size_t)3 * 8 * 16 * 16 * sizeof(cx<float>) + 6 * 65 * 16 * sizeof(float);   // E + tensor
     const int resident =
         persistent_grid(reinterpret_cast<const void*>(&zconvr128_kernel<float>), lds, 1LL << 30, 256);
     if (resident < 2) return hipErrorInvalidValue;
@@ -1055,6 +1291,37 @@ static hipError_t run_zconvr128(const Plan& pl, void* X2, const void* spec, floa
                        static_cast<cx<float>*>(X2), static_cast<const float*>(spec), Ms, pl.nz, pl.Py, pl.Hx, pl.Sx,
                        ntx, upm, (int)nunits);
     return hipGetLastError();
+}
+
+template <int P>
+static hipError_t run_zconvd(const Plan& pl, void* X2, const void* spec, double Ms, hipStream_t s) {
+    constexpr int G = ZD<P>::G, T = ZD<P>::T, NT = ZD<P>::NT;
+    if (pl.Pz != 4 * G || pl.tz != T || 2 * pl.nz > pl.Pz || 4 * pl.nz <= pl.Pz ||
+        (reinterpret_cast<uintptr_t>(spec) & 15) != 0)
+        return hipErrorInvalidValue;
+    const int ntx = pl.ntz;
+    const int upm = ntx * (pl.Py / 2);
+    const long long nunits = (long long)upm * pl.nbatch;
+    const size_t lds = ZD<P>::LDS_BYTES;
+    const int resident =
+        persistent_grid(reinterpret_cast<const void*>(&zconvd_kernel<double, P>), lds, 1LL << 30, NT);
+    if (resident < 2) return hipErrorInvalidValue;
+    long long grid = 2 * std::min<long long>(nunits, std::max(1, resident / 2));
+    if (grid >= 16) grid -= grid % 16;
+    hipLaunchKernelGGL((zconvd_kernel<double, P>), dim3((unsigned)grid), dim3(NT), lds, s,
+                       static_cast<cx<double>*>(X2), static_cast<const double*>(spec), Ms, pl.nz, pl.Py, pl.Hx,
+                       pl.Sx, ntx, upm, (int)nunits);
+    return hipGetLastError();
+}
+
+static hipError_t run_zregd(const Plan& pl, void* X2, const void* spec, double Ms, hipStream_t s) {
+    switch (pl.Pz) {
+        case 16: return run_zconvd<1>(pl, X2, spec, Ms, s);
+        case 32: return run_zconvd<2>(pl, X2, spec, Ms, s);
+        case 64: return run_zconvd<4>(pl, X2, spec, Ms, s);
+        case 128: return run_zconvd<8>(pl, X2, spec, Ms, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 static hipError_t run_zreg(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
@@ -1072,6 +1339,8 @@ template <typename R>
 hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s) {
     if constexpr (std::is_same<R, float>::value) {
         if (pl.zreg) return run_zreg(pl, X2, spec, Ms, s);
+    } else {
+        if (pl.zreg) return run_zregd(pl, X2, spec, Ms, s);
     }
     return em_big(3LL * pl.Pz * pl.tz) ? run_zconv<R, 32>(pl, X2, spec, Ms, s) : run_zconv<R, 16>(pl, X2, spec, Ms, s);
 }

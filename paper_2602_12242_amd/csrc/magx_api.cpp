@@ -144,10 +144,17 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
         int tz = 64;
         while (tz > 1 && !fits(tz, 16)) tz >>= 1;
         if (!fits(tz, 32)) return MAGX_ESIZE;
-        // single precision with Pz = 8 ... 128: the register-resident z pass (Pz/8 T threads per
-        // T-column tile; T = 32, 64 for Pz = 8 so a block has at least 64 threads, 16 for Pz = 128)
-        p.zreg = (dt == MAGX_F32 && p.Pz >= 8 && p.Pz <= 128) ? 1 : 0;
-        if (p.zreg) tz = p.Pz == 8 ? 64 : (p.Pz == 128 ? 16 : 32);
+        // register-resident z passes: single precision with Pz = 8 ... 128 (Pz/8 T threads per
+        // T-column tile; T = 32, 64 for Pz = 8 so a block has at least 64 threads, 16 for
+        // Pz = 128), double precision with Pz = 16 ... 128 (Pz/4 threads per column,
+        // T = 1024/Pz columns)
+        if (dt == MAGX_F32) {
+            p.zreg = (p.Pz >= 8 && p.Pz <= 128) ? 1 : 0;
+            if (p.zreg) tz = p.Pz == 8 ? 64 : (p.Pz == 128 ? 16 : 32);
+        } else {
+            p.zreg = (p.Pz >= 16 && p.Pz <= 128) ? 1 : 0;
+            if (p.zreg) tz = 1024 / p.Pz;
+        }
         p.tz = tz;
         p.ntz = (p.Hx + tz - 1) / tz;
         if ((long long)p.Hy * p.ntz * 6 * p.Hz * tz >= (1LL << 31)) return MAGX_ESIZE;
@@ -783,7 +790,8 @@ int magx_tensor_init_batched(magx_ctx** ctx, const magx_grid* g, magx_dtype dt, 
                              void* scratch, void* stream) {
     if (!ctx) return MAGX_EINVAL;
     *ctx = nullptr;
-    if (!spectrum || !scratch) return MAGX_EINVAL;
+    // the z passes copy tensor blocks in 16-byte pieces
+    if (!spectrum || !scratch || (reinterpret_cast<uintptr_t>(spectrum) & 15) != 0) return MAGX_EINVAL;
     Plan pl;
     int rc = make_plan(g, dt, nbatch, &pl);
     if (rc) return rc;

@@ -581,6 +581,27 @@ template <typename R> __device__ __forceinline__ R ld_off(const R* base, unsigne
     return *reinterpret_cast<const R*>(reinterpret_cast<const char*>(base) + off);
 }
 
+// A complex value that is the same in every lane of the wave, moved to
+// scalar registers (operands of vector instructions without occupying
+// vector registers).
+__device__ __forceinline__ unsigned uniform_u32(unsigned v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform_r(float v) { return __uint_as_float(uniform_u32(__float_as_uint(v))); }
+__device__ __forceinline__ double uniform_r(double v) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long lo = uniform_u32((unsigned)b), hi = uniform_u32((unsigned)(b >> 32));
+    return __longlong_as_double((long long)((hi << 32) | lo));
+}
+template <typename R> __device__ __forceinline__ cx<R> wave_uniform(cx<R> v) {
+    return mk<R>(uniform_r(v.x), uniform_r(v.y));
+}
+
+// An empty statement that takes v in vector registers and may change it: the
+// computation of v stays before this point (the compiler may otherwise sink
+// pure arithmetic past a barrier, keeping all of its inputs live instead).
+template <typename R> __device__ __forceinline__ void keep_in_regs(cx<R>& v) {
+    asm volatile("" : "+v"(v.x), "+v"(v.y));
+}
+
 __host__ __device__ inline int ilog2(int v) {
     int r = 0;
     while ((1 << r) < v) ++r;

@@ -35,7 +35,7 @@ struct Plan {
     // column tiles of the y and z passes, pencils per block of the x passes
     int ty, tz, np;
     int ntz;                    // column tiles of the z pass (and of the tensor spectrum)
-    int zreg;                   // z pass held in registers (single precision, Pz = 8 ... 128)
+    int zreg;                   // z pass held in registers (Pz = 8 ... 128 single, 16 ... 128 double precision)
     int pencil_blocks;
     // workspace layout (bytes): the non-finite flag word first, then X1, X2,
     // five fields and the per-block partials

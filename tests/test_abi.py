@@ -130,6 +130,11 @@ def test_entry_points_reject_null_arguments_without_a_gpu():
     h = ctypes.c_void_p(12345)
     assert lib.magx_tensor_init(ctypes.byref(h), ctypes.byref(g), 0, nul, nul, nul) == -1
     assert h.value is None
+    # a spectrum that is not 16-byte aligned is refused before anything touches it
+    h = ctypes.c_void_p(12345)
+    odd = ctypes.c_void_p(0x10008)
+    assert lib.magx_tensor_init(ctypes.byref(h), ctypes.byref(g), 1, odd, ctypes.c_void_p(0x20000), nul) == -1
+    assert h.value is None
     assert lib.magx_heff(nul, nul, ctypes.byref(p), nul, nul, nul) == -1
     assert lib.magx_step(nul, nul, ctypes.byref(p), 1e-13, 1, nul, nul, nul) == -1
     assert lib.magx_heff_backward(nul, nul, ctypes.byref(p), nul, nul, nul, nul) == -1
