@@ -1345,6 +1345,93 @@ hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStr
     return em_big(3LL * pl.Pz * pl.tz) ? run_zconv<R, 32>(pl, X2, spec, Ms, s) : run_zconv<R, 16>(pl, X2, spec, Ms, s);
 }
 
+// ---- films: the y and z passes fused ---------------------------------------------
+// With nz = 1 (Pz = 2) the z transform of the single input row is that row
+// for both kz = 0 and 1, and the inverse adds the two products, so the z pass
+// is the product with N(kz = 0) + N(kz = 1).  One block takes T columns of all
+// three components: forward y FFT from X1 (rows >= ny are the zero padding)
+// into LDS, the 3x3 product there, inverse y FFT from LDS to Y1 (rows < ny;
+// Y1 may be X1: a block reads its columns completely before it writes them).
+// Element ky of sequence b = c T + col sits at ky 3T + b.
+template <typename R, int EM>
+__global__ void __launch_bounds__(kNT) yzfilm_kernel(const cx<R>* X1, cx<R>* Y1, const R* __restrict__ spec, R Ms,
+                                                     int ny, int lgPy, int Hx, int Sx, int lgT, int ntx, int tz,
+                                                     int ntz, int ntiles) {
+    tw_lds_fill<R>();   // read from the second pass on, after the first barrier
+    extern __shared__ unsigned char smem_raw[];
+    cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
+    const int T = 1 << lgT;
+    const int T3 = 3 * T;
+    const int Py = 1 << lgPy;
+    const R s = -Ms;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int mb = t / ntx;
+        const int kx0 = (t - mb * ntx) * T;
+        const int ncol = min(T, Hx - kx0);
+        const long long mrow = (long long)mb * 3 * ny;    // first row of the member's component 0
+        auto load = [&](int b, int j) -> cx<R> {
+            const int c = b >> lgT, col = b & (T - 1);
+            if (j < ny && col < ncol) return X1[(mrow + (long long)c * ny + j) * Sx + kx0 + col];
+            return mk<R>((R)0, (R)0);
+        };
+        auto none_load = [&](int, int) -> cx<R> { return mk<R>((R)0, (R)0); };
+        auto none_store = [&](int, int, cx<R>) {};
+        fft_io<R, false, EM, false, true, kCols, 3, true, false, lgmax<EM>(), kNT, true>(buf, lgPy, lgT, T3, load,
+                                                                                         none_store);
+        __syncthreads();
+        // product with N(kz = 0) + N(kz = 1) (octant rows 0 and 1, both with
+        // the even sign in z); components odd in y change sign for ky > Py/2
+        for (int e = threadIdx.x; e < (Py << lgT); e += kNT) {
+            const int ky = e >> lgT, col = e & (T - 1);
+            if (col >= ncol) continue;
+            const int kx = kx0 + col;
+            const int kyo = ky <= Py / 2 ? ky : Py - ky;
+            const R sy = ky <= Py / 2 ? (R)1 : (R)-1;
+            const int txs = kx / tz;
+            const R* blk = spec + ((long long)(kyo * ntz + txs) * 6) * (2 * tz) + (kx - txs * tz);
+            R n6[6];
+#pragma unroll
+            for (int c6 = 0; c6 < 6; ++c6) n6[c6] = blk[c6 * 2 * tz] + blk[c6 * 2 * tz + tz];
+            const R nxx = s * n6[0], nyy = s * n6[1], nzz = s * n6[2];
+            const R nxy = s * sy * n6[3], nxz = s * n6[4], nyz = s * sy * n6[5];
+            cx<R>* p = buf + ky * T3 + col;
+            const cx<R> mx = p[0], my = p[T], mz = p[2 * T];
+            p[0] = mk<R>(nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y);
+            p[T] = mk<R>(nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y);
+            p[2 * T] = mk<R>(nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y);
+        }
+        __syncthreads();
+        auto store = [&](int b, int j, cx<R> v) {
+            const int c = b >> lgT, col = b & (T - 1);
+            if (j < ny && col < ncol) Y1[(mrow + (long long)c * ny + j) * Sx + kx0 + col] = v;
+        };
+        fft_io<R, true, EM, true, false, kCols, 3, false, true, lgmax<EM>(), kNT, true>(buf, lgPy, lgT, T3, none_load,
+                                                                                        store);
+        __syncthreads();   // the next tile's first pass writes LDS
+    }
+}
+
+template <typename R>
+hipError_t launch_yzfilm(const Plan& pl, void* X1, const void* spec, R Ms, hipStream_t s) {
+    if (!pl.yzfilm || pl.nz != 1 || pl.Pz != 2 || pl.Hz != 2) return hipErrorInvalidValue;
+    const int T = pl.yzt;
+    const int lgT = ilog2(T);
+    const int ntx = (pl.Hx + T - 1) / T;
+    const int ntiles = ntx * pl.nbatch;
+    const long long elems = 3LL * pl.Py * T;
+    const size_t lds = (size_t)elems * sizeof(cx<R>);
+    const int grid = std::min(ntiles, 4096);
+    if (elems <= (long long)kNT * 16)
+        hipLaunchKernelGGL((yzfilm_kernel<R, 16>), dim3(grid), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
+                           static_cast<cx<R>*>(X1), static_cast<const R*>(spec), Ms, pl.ny, pl.lgPy, pl.Hx, pl.Sx,
+                           lgT, ntx, pl.tz, pl.ntz, ntiles);
+    else
+        hipLaunchKernelGGL((yzfilm_kernel<R, 32>), dim3(grid), dim3(kNT), lds, s, static_cast<const cx<R>*>(X1),
+                           static_cast<cx<R>*>(X1), static_cast<const R*>(spec), Ms, pl.ny, pl.lgPy, pl.Hx, pl.Sx,
+                           lgT, ntx, pl.tz, pl.ntz, ntiles);
+    return hipGetLastError();
+}
+
 // ---- memory patterns without arithmetic (diagnostics) ---------------------------
 // The practical bandwidth of the access patterns of the passes, measured on
 // the same buffer: a float4 stream copy, and in-place read + write (scaled by
@@ -1419,5 +1506,7 @@ template hipError_t launch_yinv<float>(const Plan&, const void*, void*, hipStrea
 template hipError_t launch_yinv<double>(const Plan&, const void*, void*, hipStream_t);
 template hipError_t launch_zconv<float>(const Plan&, void*, const void*, float, hipStream_t);
 template hipError_t launch_zconv<double>(const Plan&, void*, const void*, double, hipStream_t);
+template hipError_t launch_yzfilm<float>(const Plan&, void*, const void*, float, hipStream_t);
+template hipError_t launch_yzfilm<double>(const Plan&, void*, const void*, double, hipStream_t);
 
 }  // namespace magx

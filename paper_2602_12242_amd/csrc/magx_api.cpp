@@ -159,9 +159,29 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
         p.ntz = (p.Hx + tz - 1) / tz;
         if ((long long)p.Hy * p.ntz * 6 * p.Hz * tz >= (1LL << 31)) return MAGX_ESIZE;
     }
-    p.np = std::max(1, 1024 / p.Lh);
+    // films: y and z passes fused when a tile of 3 Py ty values with ty >= 8
+    // columns (8 ... 16, whole 64- to 128-byte row segments) fits in 64 KiB;
+    // on small films the tiles narrow (down to 4 columns) until there are 64
+    // of them, since there the kernel's latency, not its traffic, counts
+    if (p.nz == 1) {
+        int t = 16;
+        while (t >= 8 && 3LL * p.Py * t * 2 * p.esize > 65536) t >>= 1;
+        if (t >= 8) {
+            while (t > 4 && (p.Hx + t - 1) / t < 64) t >>= 1;
+            p.yzfilm = 1;
+            p.yzt = t;
+        }
+    }
+    // pencils per block: up to 1024/Lh (one block holds 3 np lines of Lh
+    // complex values); fewer on small grids, so that a member has at least
+    // 256 blocks when it has enough pencils (a block's instruction stream, not
+    // the traffic, bounds a small grid's kernels).  Independent of the batch
+    // size: a member's block partition, and so the order of its block sums,
+    // is the same in a batch as alone.
     const int npen = p.ny * p.nz;
+    p.np = std::max(1, 1024 / p.Lh);
     if (p.np > npen) p.np = npen;
+    while (p.np > 1 && (npen + p.np - 1) / p.np < 256) p.np >>= 1;
     // pencil blocks never straddle two members (the last one of a member may be
     // ragged); with ny >= np and nz > 1 a block holds np rows of one plane and
     // blocks run through z fastest
@@ -349,6 +369,12 @@ static int conv_passes(magx_ctx* c, void* ws, R Ms, hipStream_t s) {
     const Plan& pl = c->pl;
     void* X1 = bptr(ws, pl.off_x1);
     void* X2 = bptr(ws, pl.off_x2);
+    if (pl.yzfilm) {
+        ProfScope ps(c, kProfZconv, s);
+        if (launch_yzfilm<R>(pl, X1, c->spectrum, Ms, s) != hipSuccess) return MAGX_EHIP;
+        c->heff_count++;
+        return MAGX_OK;
+    }
     {
         ProfScope ps(c, kProfYfwd, s);
         if (launch_yfwd<R>(pl, X1, X2, s) != hipSuccess) return MAGX_EHIP;

@@ -36,6 +36,7 @@ struct Plan {
     int ty, tz, np;
     int ntz;                    // column tiles of the z pass (and of the tensor spectrum)
     int zreg;                   // z pass held in registers (Pz = 8 ... 128 single, 16 ... 128 double precision)
+    int yzfilm, yzt;            // films (nz = 1): the y and z passes fused into one kernel on yzt-column tiles
     int pencil_blocks;
     // workspace layout (bytes): the non-finite flag word first, then X1, X2,
     // five fields and the per-block partials
@@ -80,6 +81,9 @@ template <typename R>
 hipError_t launch_zconv(const Plan& pl, void* X2, const void* spec, R Ms, hipStream_t s);
 template <typename R>
 hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s);
+// Films (plan.yzfilm): forward y pass, z pass and inverse y pass in one kernel, X1 -> Y1 in place.
+template <typename R>
+hipError_t launch_yzfilm(const Plan& pl, void* X1, const void* spec, R Ms, hipStream_t s);
 // Diagnostic memory patterns over X2 (single precision plans): 0 copy, 1 z tiling, 2 y tiling.
 hipError_t launch_memory_probe(const Plan& pl, int kind, void* X2, hipStream_t s, double* bytes);
 
