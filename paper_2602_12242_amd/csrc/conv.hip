@@ -191,10 +191,13 @@ __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, 
 //  * forward, input rows n < ny: X[2k] = DFT_1024(x)[k] and
 //    X[2k+1] = DFT_1024(x W_2048^n)[k]; the tile's inputs stay in registers
 //    for the second transform, twiddled there.
-//  * inverse, output rows n < ny: x[n] = A[n] + W_2048^-n B[n] with
-//    A = IDFT_1024(X[2k]) and B = IDFT_1024(X[2k+1]); A is parked in the
-//    output rows (L2) while B is computed, and each half of the input is
-//    fetched while the transform before it runs.
+//  * inverse, output rows n < ny <= 1024, by decimation in frequency:
+//    x[2n] = IDFT_1024(X[k] + X[k+1024])[n] and
+//    x[2n+1] = IDFT_1024((X[k] - X[k+1024]) W_2048^-k)[n], n < 512 (the last
+//    pass computes only that half); both halves of the input are combined in
+//    registers, the second waits there while the first is transformed, and
+//    the next tile's input is fetched while the transforms run.  Radix-8
+//    passes keep the two register sets within 128 registers (1024 threads).
 template <typename R, int EM, int NT>
 __global__ void __launch_bounds__(NT) yfwd2_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
                                                    int Hx, int Sx, int lgT, int ntx, int ntiles) {
@@ -254,26 +257,30 @@ template <typename R, int EM, int NT>
 __global__ void __launch_bounds__(NT) yinv2_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
                                                    int Hx, int Sx, int lgT, int ntx, int ntiles) {
     constexpr int LGL = 10, PY = 2048;
-    tw_lds_fill<R>();   // read by the second pass and by the final twiddles, after the first barrier
+    tw_lds_fill<R>();   // read by the second pass and by the twiddles W_2048^-k, after the first barrier
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int T = 1 << lgT;
     const PairWalk pw(ntiles, ntx);
-    // even (par 0) or odd (par 1) rows of a tile: sequence b = column, element j = row 2j + par
-    auto loader = [=](int t, int par) {
+    // rows k (half 0) or k + 1024 (half 1) of a tile: sequence b = column, element k
+    auto loader = [=](int t, int half) {
         const int tx = t % ntx;
         const long long plane = t / ntx;
         const int kx0 = tx * T;
-        const cx<R>* src = X2 + plane * PY * (long long)Sx + kx0 + (long long)par * Sx;
+        const cx<R>* src = X2 + plane * PY * (long long)Sx + kx0 + (long long)half * 1024 * Sx;
         const int ncol = min(T, Hx - kx0);
-        return [=](int b, int j) -> cx<R> {
-            if (b < ncol) return ld_stream<R>(&src[umul24((unsigned)(2 * j), (unsigned)Sx) + (unsigned)b]);
+        return [=](int b, int k) -> cx<R> {
+            if (b < ncol) return ld_stream<R>(&src[umul24((unsigned)k, (unsigned)Sx) + (unsigned)b]);
             return mk<R>(0, 0);
         };
     };
-    FirstIn<R, EM, false> ev, od;
+    FirstIn<R, EM, false> lo, hi;
     int u = pw.first();
-    if (u < pw.u1) first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(ev, LGL, lgT, T, loader(pw.tile(u), 0));
+    if (u < pw.u1) {
+        first_load<R, EM, kCols, 1, false, 3, NT>(lo, LGL, lgT, T, loader(pw.tile(u), 0));
+        first_load<R, EM, kCols, 1, false, 3, NT>(hi, LGL, lgT, T, loader(pw.tile(u), 1));
+    }
+    bool first_tile = true;
     while (u < pw.u1) {
         const int un = pw.next(u);
         const int t = pw.tile(u);
@@ -282,30 +289,38 @@ __global__ void __launch_bounds__(NT) yinv2_kernel(const cx<R>* __restrict__ X2,
         const int kx0 = tx * T;
         cx<R>* dst = Y1 + plane * ny * (long long)Sx + kx0;
         const int ncol = min(T, Hx - kx0);
-        // A = IDFT_1024 of the even rows, written to the output rows with plain
-        // stores (kept in L2); the odd rows are fetched meanwhile
-        auto store_a = [&](int b, int n, cx<R> v) {
-            if (n < ny && b < ncol) dst[umul24((unsigned)n, (unsigned)Sx) + (unsigned)b] = v;
+        if (first_tile) __syncthreads();   // the LDS twiddle table is complete
+        first_tile = false;
+        // u = X[k] + X[k + 1024] (in lo), v = (X[k] - X[k + 1024]) W_2048^-k (in hi)
+#pragma unroll
+        for (int e = 0; e < FirstIn<R, EM, false>::N; ++e) {
+            const cx<R> a = lo.v[e], b = hi.v[e];
+            lo.v[e] = cadd<R>(a, b);
+            hi.v[e] = csub<R>(a, b);
+        }
+        first_apply<R, EM, kCols, 1, false, 3, NT>(
+            hi, LGL, lgT, T, [](int, int k, cx<R> v) { return cmul<R>(v, tw_pass<R, true, true>(k << 1)); });
+        // even output rows 2n = IDFT_1024(u)[n], odd rows 2n + 1 = IDFT_1024(v)[n], n < 512
+        auto store_even = [&](int b, int n, cx<R> v) {
+            if (2 * n < ny && b < ncol) st_stream<R>(&dst[umul24((unsigned)(2 * n), (unsigned)Sx) + (unsigned)b], v);
         };
-        auto fetch_odd = [&]() { first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(od, LGL, lgT, T, loader(t, 1)); };
-        fft_reg<R, true, EM, false, kCols, 1, false, false, lgmax<EM>(), NT, true>(buf, LGL, lgT, T, ev, fetch_odd,
-                                                                                    store_a);
-        __syncthreads();   // the last pass read LDS; the second transform's first pass writes it
-        // B = IDFT_1024 of the odd rows; x[n] = A[n] + W_2048^-n B[n].  Both
-        // transforms give output n to the same thread, which reads back its own
-        // store of A (same address, same wave: ordered)
-        auto store_x = [&](int b, int n, cx<R> v) {
-            if (n < ny && b < ncol) {
-                cx<R>* p = &dst[umul24((unsigned)n, (unsigned)Sx) + (unsigned)b];
-                st_stream<R>(p, cadd<R>(*p, cmul<R>(v, tw_pass<R, true, true>(n << 1))));
-            }
+        auto store_odd = [&](int b, int n, cx<R> v) {
+            if (2 * n + 1 < ny && b < ncol)
+                st_stream<R>(&dst[umul24((unsigned)(2 * n + 1), (unsigned)Sx) + (unsigned)b], v);
         };
-        auto next = [&]() {
+        auto next_lo = [&]() {
             if (un < pw.u1)
-                first_load<R, EM, kCols, 1, false, lgmax<EM>(), NT>(ev, LGL, lgT, T, loader(pw.tile(un), 0));
+                first_load<R, EM, kCols, 1, false, 3, NT>(lo, LGL, lgT, T, loader(pw.tile(un), 0));
         };
-        fft_reg<R, true, EM, false, kCols, 1, false, false, lgmax<EM>(), NT, true>(buf, LGL, lgT, T, od, next,
-                                                                                    store_x);
+        auto next_hi = [&]() {
+            if (un < pw.u1)
+                first_load<R, EM, kCols, 1, false, 3, NT>(hi, LGL, lgT, T, loader(pw.tile(un), 1));
+        };
+        fft_reg<R, true, EM, false, kCols, 1, false, true, 3, NT, true>(buf, LGL, lgT, T, lo, next_lo,
+                                                                                   store_even);
+        __syncthreads();   // the last pass read LDS; the second transform's first pass writes it
+        fft_reg<R, true, EM, false, kCols, 1, false, true, 3, NT, true>(buf, LGL, lgT, T, hi, next_hi,
+                                                                                   store_odd);
         __syncthreads();
         u = un;
     }
@@ -1207,10 +1222,7 @@ hipError_t launch_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t s) 
 
 template <typename R>
 hipError_t launch_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t s) {
-    // single precision only: the double-precision variant would spill
-    if constexpr (std::is_same<R, float>::value) {
-        if (pl.Py == 2048) return run_y2<R, true>(pl, X2, Y1, s);
-    }
+    if (pl.Py == 2048) return run_y2<R, true>(pl, X2, Y1, s);
     if constexpr (std::is_same<R, float>::value) {
         switch (y_lg<R>(pl)) {
             case 8: return run_yinv<R, 16, kNT, 8>(pl, X2, Y1, s);
