@@ -426,6 +426,57 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int mb, int 
         return mk<R>(A.x - B.y, A.y + B.x);
     };
     tw_lds_fill<R>();   // pass twiddles, read after the barrier below
+    if ((1 << lgq) >= kNT) {
+        // at least one item per thread and line: thread tid takes items
+        // t = tid + k kNT of every line, so its twiddles are the same for all
+        // lines and each line's row address is uniform (scalar registers)
+        constexpr int IPL = 2;                         // items per thread and line at most (Lh <= 1024)
+        const int ipl = (1 << lgq) / kNT;
+        cx<R> wc[IPL];
+#pragma unroll
+        for (int k = 0; k < IPL; ++k)
+            if (k < ipl) wc[k] = cconj<R>(tw_fwd<R>(((int)threadIdx.x + k * kNT) << twsh));
+        const int nl = npen * 3;
+        constexpr int LC = kXIt / IPL;                 // lines per chunk
+        for (int l0 = 0; l0 < nl; l0 += LC) {
+            cx<R> A[LC][IPL], B[LC][IPL], C[LC];
+#pragma unroll
+            for (int i = 0; i < LC; ++i) {
+                const int l = min(l0 + i, nl - 1);
+                const int p = l / 3, c = l - 3 * p;
+                const cx<R>* row = Y1 + x_row(g, mb, c, pen0 + p);
+#pragma unroll
+                for (int k = 0; k < IPL; ++k) {
+                    if (k < ipl) {
+                        const int t = (int)threadIdx.x + k * kNT;
+                        A[i][k] = row[t];
+                        B[i][k] = row[Lh - t];
+                    }
+                }
+                // X[Lh/2] for item 0 of a line (loaded by the first wave only)
+                C[i] = mk<R>((R)0, (R)0);
+                if (threadIdx.x < 64) C[i] = row[threadIdx.x == 0 ? (Lh >> 1) : (int)threadIdx.x];
+            }
+#pragma unroll
+            for (int i = 0; i < LC; ++i) {
+                const int l = l0 + i;
+                if (l >= nl) break;
+                cx<R>* out = buf + l * Lh;
+#pragma unroll
+                for (int k = 0; k < IPL; ++k) {
+                    if (k >= ipl) break;
+                    const int t = (int)threadIdx.x + k * kNT;
+                    if (t == 0) {
+                        out[0] = split(A[i][k], B[i][k], mk<R>((R)1, (R)0));
+                        out[Lh >> 1] = split(C[i], C[i], mk<R>((R)0, (R)1));   // conj(W^(Lh/2)) = i
+                    } else {
+                        out[t] = split(A[i][k], B[i][k], wc[k]);
+                        out[Lh - t] = split(B[i][k], A[i][k], mk<R>(-wc[k].x, wc[k].y));   // conj(W^(Lh-t)) = -W^t
+                    }
+                }
+            }
+        }
+    } else {
     // items in chunks of kXIt per thread: all loads of a chunk are issued
     // before any is used (no load behind a branch or a loop-carried wait)
     const int count = (npen * 3) << lgq;
@@ -461,6 +512,7 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int mb, int 
             }
         }
     }
+    }
     __syncthreads();
     auto none_load = [&](int, int) -> cx<R> { return mk<R>(0, 0); };
     auto none_store = [&](int, int, cx<R>) {};
@@ -484,6 +536,41 @@ __device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int mb, int pen0, 
     fft_io<R, false, pemax<BIG>(), true, true, kLines, 1, true, false, lgmax<pemax<BIG>()>(), kNT, true>(
         buf, g.lgLh, 0, npen * 3, none_load, none_store);
     const R half = (R)0.5;
+    if ((1 << lgq) >= kNT) {
+        // as in the split step: fixed items t = tid + k kNT of every line,
+        // uniform row addresses
+        constexpr int IPL = 2;
+        const int ipl = (1 << lgq) / kNT;
+        cx<R> W[IPL];
+#pragma unroll
+        for (int k = 0; k < IPL; ++k)
+            if (k < ipl) W[k] = tw_fwd<R>(((int)threadIdx.x + k * kNT) << twsh);
+        const int nl = npen * 3;
+        for (int l = 0; l < nl; ++l) {
+            const int p = l / 3, c = l - 3 * p;
+            cx<R>* row = X1 + x_row(g, mb, c, pen0 + p);
+            const cx<R>* in = buf + l * Lh;
+#pragma unroll
+            for (int k = 0; k < IPL; ++k) {
+                if (k >= ipl) break;
+                const int t = (int)threadIdx.x + k * kNT;
+                if (t == 0) {
+                    const cx<R> P = in[0];
+                    row[0] = mk<R>(P.x + P.y, (R)0);
+                    row[Lh] = mk<R>(P.x - P.y, (R)0);
+                    row[Lh >> 1] = cconj<R>(in[Lh >> 1]);   // W^(Lh/2) = -i
+                } else {
+                    const cx<R> P = in[t], Q = in[Lh - t];
+                    const cx<R> E = mk<R>(half * (P.x + Q.x), half * (P.y - Q.y));
+                    const cx<R> O = mk<R>(half * (P.y + Q.y), half * (Q.x - P.x));
+                    const cx<R> T = cmul<R>(W[k], O);
+                    row[t] = cadd<R>(E, T);
+                    row[Lh - t] = mk<R>(E.x - T.x, T.y - E.y);
+                }
+            }
+        }
+        return;
+    }
     const int count = (npen * 3) << lgq;
     for (int base = 0; base < count; base += kXIt * kNT) {
         cx<R> W[kXIt];
