@@ -37,6 +37,14 @@ CASES = {
     # square power-of-two plane: compile-time pencil and y geometry
     "sq128": ((128, 128, 2), (2e-9, 2e-9, 2e-9),
               dict(Ms=8e5, A=1.3e-11, D=1e-3, alpha=0.1, Hbias=(2e3, 0, 1e3), terms=ALL)),
+    # a film (nz = 1): the fused y and z passes take column tiles of every member
+    "film": ((100, 24, 1), (3e-9, 3e-9, 3e-9),
+             dict(Ms=8e5, A=1.3e-11, D=1e-3, alpha=0.02, Hbias=(2e4, 0, 0), terms=ALL)),
+    # Pz = 128: the single-precision z pass with 16 threads per column and the
+    # double-precision one with 32 (tensor blocks copied to LDS per tile)
+    "slab40": ((20, 6, 40), (2e-9, 2e-9, 1e-9),
+               dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, eK=(0.0, 0.6, 0.8), alpha=0.1, Hbias=(1e3, -2e3, 5e3),
+                    terms=ALL)),
 }
 B = 3
 
@@ -99,7 +107,7 @@ def test_batched_heff_energy_rhs_equal_single(name, dtype):
         assert _same(kB[b], single.llg_rhs(ms[b], H, pb[b])), b
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "tiles"])
+@pytest.mark.parametrize("name", ["tiny_all", "tiles", "film", "slab40"])
 def test_batched_member_matches_oracle(name):
     n, d, mat, single, batch, pb = _setup(name, 1)
     p = _magx().make_params(**mat)
@@ -117,7 +125,7 @@ def test_batched_member_matches_oracle(name):
         assert err <= 1e-11, (b, err)
 
 
-@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "sq128"])
+@pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "sq128", "film", "slab40"])
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_batched_steps_and_reverse_equal_single(name, dtype):
     n, d, mat, single, batch, pb = _setup(name, dtype)
