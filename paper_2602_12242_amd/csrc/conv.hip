@@ -89,9 +89,26 @@ __device__ __forceinline__ void ygeom_fix(int& ny, int& lgPy, int& Hx, int& Sx, 
     }
 }
 
+// Packed Nyquist column (plans with the single-precision register z pass,
+// Py <= 1024): the value of row ky at column Lh = Hx - 1 is kept at row prow,
+// column Lh + i instead.  Rows ky = q < Py/2 and the mirrored rows (q = Py - ky,
+// q = 0 for ky = Py/2) go, 16 consecutive q at a time, to the padding columns
+// Lh ... Lh + 15 of one row: prow = 16 floor(q/16) for the first kind,
+// Py - 1 - 16 floor(q/16) for the second, i = q mod 16.  The z pass then reads
+// 16 Nyquist values of a plane as one 128-byte segment.  Returns the element
+// offset from column Lh of row 0.
+__device__ __forceinline__ unsigned nyq_pack(int ky, int Py, unsigned Sx) {
+    const int h = Py >> 1;
+    const bool mirrored = ky >= h;
+    const int q = ky < h ? ky : (ky == h ? 0 : Py - ky);
+    const int k = q >> 4;
+    const int prow = mirrored ? Py - 1 - 16 * k : 16 * k;
+    return (unsigned)prow * Sx + (unsigned)(q & 15);
+}
+
 template <typename R, int EM, int NT, int LG>
 __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, cx<R>* __restrict__ X2, int ny,
-                                                  int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
+                                                  int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles, int nyq) {
     ygeom_fix<R, LG>(ny, lgPy, Hx, Sx, lgT, ntx);
     tw_lds_fill<R>();   // read by the second pass, after the first barrier
     extern __shared__ unsigned char smem_raw[];
@@ -126,8 +143,13 @@ __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, 
         const int kx0 = tx * T;
         cx<R>* dst = X2 + plane * Py * (long long)Sx + kx0;
         const int ncol = min(T, Hx - kx0);
+        // with a packed Nyquist column, column Hx - 1 (b = ncol - 1 of the last tile) moves
+        const int bnyq = nyq && kx0 + ncol == Hx ? ncol - 1 : -1;
         auto store = [&](int b, int j, cx<R> v) {
-            if (b < ncol) st_stream<R>(&dst[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b], v);
+            if (b < ncol) {
+                const unsigned off = b == bnyq ? nyq_pack(j, Py, (unsigned)Sx) : umul24((unsigned)j, (unsigned)Sx);
+                st_stream<R>(&dst[off + (unsigned)b], v);
+            }
         };
         auto next = [&]() {
             if (un < pw.u1)
@@ -141,7 +163,7 @@ __global__ void __launch_bounds__(NT) yfwd_kernel(const cx<R>* __restrict__ X1, 
 
 template <typename R, int EM, int NT, int LG>
 __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, cx<R>* __restrict__ Y1, int ny,
-                                                  int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles) {
+                                                  int lgPy, int Hx, int Sx, int lgT, int ntx, int ntiles, int nyq) {
     ygeom_fix<R, LG>(ny, lgPy, Hx, Sx, lgT, ntx);
     tw_lds_fill<R>();   // read by the second pass, after the first barrier
     extern __shared__ unsigned char smem_raw[];
@@ -155,8 +177,12 @@ __global__ void __launch_bounds__(NT) yinv_kernel(const cx<R>* __restrict__ X2, 
         const int kx0 = tx * T;
         const cx<R>* src = X2 + plane * Py * (long long)Sx + kx0;
         const int ncol = min(T, Hx - kx0);
+        const int bnyq = nyq && kx0 + ncol == Hx ? ncol - 1 : -1;   // packed Nyquist column
         return [=](int b, int j) -> cx<R> {
-            if (b < ncol) return ld_stream<R>(&src[umul24((unsigned)j, (unsigned)Sx) + (unsigned)b]);
+            if (b < ncol) {
+                const unsigned off = b == bnyq ? nyq_pack(j, Py, (unsigned)Sx) : umul24((unsigned)j, (unsigned)Sx);
+                return ld_stream<R>(&src[off + (unsigned)b]);
+            }
             return mk<R>(0, 0);
         };
     };
@@ -476,8 +502,8 @@ __global__ void __launch_bounds__(kNT) zconv_kernel(cx<R>* __restrict__ X2, cons
 // split of Pz = 64; G = 1 needs no exchange.
 template <typename R, int T, int G>
 __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, const R* __restrict__ spec, R Ms,
-                                                       int nz, int Py, int Hx, int Sx, int ntx,
-                                                       int units_per_member, int nunits) {
+                                                       int nz, int Py, int Hx, int Sx, int ntx, int ntxn,
+                                                       int upm, int ngm, int nbatch, int gw, long long tn_off) {
     constexpr int PZ = 8 * G, H2 = PZ / 2, Hz = H2 + 1, J = 8 / G;
     constexpr int LGPZ = ilog2c(PZ);
     extern __shared__ unsigned char smem_raw[];
@@ -501,25 +527,90 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
 #pragma unroll
         for (int q = 0; q < G; ++q)
             w2[jj][q] = G == 8 ? w1[q] : tw_fwd<R>(((q * (g + G * jj)) & (PZ - 1)) << (kTwLog - LGPZ));
+    // Units: upm = ntxn column tiles for each row pair q < Py/2 of a member
+    // and, with a packed Nyquist column (ntxn = ntx - 1, ngm > 0), ngm Nyquist
+    // units per member, each the column kx = Hx - 1 of T row pairs (lane col
+    // takes q = q0 + col: 16 consecutive q are one 128-byte segment of X2, and
+    // the tensor's Nyquist copy has the column tiles' block layout with q as
+    // the column), instead of one whole tile per row pair.
+    // The two blocks of a pair take the rows ky = q and Py - q (q = 0: 0 and
+    // Py/2) of the same units.  A pair's list is its Nyquist units (spread
+    // evenly over the pairs, each counted as gw column tiles), then a
+    // contiguous range of column tiles (the host picks gw = 2 only when every
+    // pair has at least gw column tiles, which keeps the ranges ordered).
     struct Tile {
-        int mb, kx0, ky, tx, kyo;
+        int mb, kx0, ky, tx, kyo, nyq, q0;
+        bool ok;        // this lane's column exists
+        unsigned off;   // this lane's element offset in its plane
     };
     const int lbp = xcd_logical_block(blockIdx.x, gridDim.x);
     const int side = lbp & 1;
-    auto tile_of = [=](int u) {
+    const int npairs = gridDim.x >> 1;
+    const int pr = lbp >> 1;
+    const int half = Py >> 1;
+    const long long NN = (long long)upm * nbatch, NG = (long long)ngm * nbatch, S = NN + gw * NG;
+    auto gstart = [=](long long p) { return (p * NG + npairs - 1) / npairs; };
+    auto nstart = [=](long long p) { return min(NN, max(0LL, p * S / npairs - gw * gstart(p))); };
+    const int kg0 = (int)gstart(pr), ng = (int)gstart(pr + 1) - kg0;
+    const int n0 = (int)nstart(pr), nn = (int)nstart(pr + 1) - n0;
+    // a unit of the pair's list (uniform): member, row pair q (column tiles),
+    // column tile tx, or Nyquist unit of rows q0 ...
+    struct Unit {
+        int mb, q, tx, nyq, q0;
+    };
+    auto unit_at = [=](int u) {
+        Unit a;
+        a.nyq = u < ng;
+        a.q0 = 0;
+        if (a.nyq) {
+            const int k = kg0 + u;
+            a.mb = k / ngm;
+            a.q0 = (k - a.mb * ngm) * T;
+            a.q = 0;
+            a.tx = ntx - 1;
+        } else {
+            const int n = n0 + u - ng;
+            a.mb = n / upm;
+            const int r = n - a.mb * upm;
+            a.q = r / ntxn;
+            a.tx = r - a.q * ntxn;
+        }
+        return a;
+    };
+    // the unit after a (unit u of the list): column tiles follow each other
+    // in (member, q, tx) order, so only the first one needs divisions
+    auto unit_next = [=](const Unit& a, int u) {
+        if (u <= ng) return unit_at(u);
+        Unit b = a;
+        if (++b.tx == ntxn) {
+            b.tx = 0;
+            if (++b.q == half) {
+                b.q = 0;
+                ++b.mb;
+            }
+        }
+        return b;
+    };
+    auto tile_of = [=](const Unit& a) {
         Tile d;
-        d.mb = u / units_per_member;
-        const int r = u - d.mb * units_per_member;
-        const int q = r / ntx;
-        d.tx = r - q * ntx;
-        d.kyo = side ? (q == 0 ? Py >> 1 : q) : q;
-        d.ky = side ? (q == 0 ? Py >> 1 : Py - q) : q;
+        d.nyq = a.nyq;
+        d.mb = a.mb;
+        d.q0 = a.q0;
+        d.tx = a.tx;
+        const int qu = a.q;   // the row pair of a column tile (uniform)
         d.kx0 = d.tx * T;
+        d.kyo = side ? (qu == 0 ? half : qu) : qu;   // column tiles only
+        // this lane's row pair: a Nyquist unit's lanes take consecutive ones
+        int q = d.nyq ? d.q0 + col : qu;
+        d.ok = d.nyq ? q < half : d.kx0 + col < Hx;
+        if (d.nyq && !d.ok) q = 0;   // a valid element; its results are never stored
+        d.ky = side ? (q == 0 ? half : Py - q) : q;
+        // columns beyond Hx read at the clamped column Hx - 1 of the same row
+        d.off = d.nyq ? nyq_pack(d.ky, Py, (unsigned)Sx) + (unsigned)(Hx - 1)
+                      : (unsigned)d.ky * (unsigned)Sx + (unsigned)(d.kx0 + min(col, Hx - 1 - d.kx0));
         return d;
     };
-    auto base_of = [=](const Tile& d) {
-        return X2 + (long long)d.mb * 3 * comp_stride + (long long)d.ky * Sx + d.kx0;
-    };
+    auto base_of = [=](const Tile& d) { return X2 + (long long)d.mb * 3 * comp_stride; };
     // Inputs of a tile: rows g + G r, r < 4, of the three components (scaled
     // by the spectral product's factor s = -Ms when the forward pass takes
     // them: the pass is linear, and there are fewer inputs than spectral
@@ -528,10 +619,10 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
     // the clamped column Hx-1 of the same row) only produces values that are
     // never stored; rows z >= nz are the zero padding.
     cx<R> pin[12];
-    auto load_tile = [&](int u) {
-        const Tile d = tile_of(u);
+    auto load_tile = [&](const Unit& un) {
+        const Tile d = tile_of(un);
         const cx<R>* base = base_of(d);
-        const unsigned voff = (unsigned)g * plane_stride + (unsigned)min(col, Hx - 1 - d.kx0);
+        const unsigned voff = (unsigned)g * plane_stride + d.off;
 #pragma unroll
         for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -542,31 +633,36 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
                 pin[c * 4 + r] = z < nz ? v : mk<R>((R)0, (R)0);
             }
     };
-    const int npairs = gridDim.x >> 1;
-    const int pr = lbp >> 1;
-    const int t0 = (int)((long long)nunits * pr / npairs);
-    const int t1 = (int)((long long)nunits * (pr + 1) / npairs);
-    if (t0 < t1) load_tile(t0);
+    const int t0 = 0, t1 = ng + nn;
+    Unit uc = unit_at(t0);
+    if (t0 < t1) load_tile(uc);
     for (int t = t0; t < t1; ++t) {
-        const Tile d = tile_of(t);
+        const Tile d = tile_of(uc);
+        const Unit un = unit_next(uc, t + 1);
         const R sy = d.ky <= Py / 2 ? (R)1 : (R)-1;
         // tensor values of this thread's kz = g + G j + 8 k2, read at the
         // octant row kzo = min(kz, Pz - kz); the tile's block [6][Hz][T] of the
         // tile-major spectrum is contiguous and includes the padding columns of
         // the last tile
         R tv[8][6];
+        // with g < G, kz <= H2 holds for all g when G j + 8 k2 + G - 1 <= H2 and
+        // for none when G j + 8 k2 > H2 (decided at compile time)
+        auto kzo_of = [&](int k0) {
+            return k0 + G - 1 <= H2 ? g + k0 : (k0 > H2 ? PZ - g - k0 : (g + k0 <= H2 ? g + k0 : PZ - g - k0));
+        };
         {
-            const R* blk = spec + (long long)(d.kyo * ntx + d.tx) * 6 * (Hz * T);
-            // with g < G, kz <= H2 holds for all g when G j + 8 k2 + G - 1 <= H2
-            // and for none when G j + 8 k2 > H2 (decided at compile time)
-            const int lo = g * T + col, hi = (PZ - g) * T + col;
+            // a column tile's block [6][Hz][T] of the tile-major spectrum, or for
+            // a Nyquist unit the block of the tensor's Nyquist copy whose column
+            // col holds row pair q0 + col (the extra last block: the mirrored
+            // side's first block, where q = 0 is row Py/2)
+            const int nblk = (half + T - 1) / T;
+            const long long bidx = d.nyq ? (side && d.q0 == 0 ? nblk : d.q0 / T) : (long long)d.kyo * ntx + d.tx;
+            const R* blk = spec + (d.nyq ? tn_off : 0LL) + bidx * 6 * (Hz * T);
 #pragma unroll
             for (int jj = 0; jj < J; ++jj)
 #pragma unroll
                 for (int k2 = 0; k2 < G; ++k2) {
-                    const int k0 = G * jj + 8 * k2;
-                    const int olo = lo + k0 * T, ohi = hi - k0 * T;
-                    const int o = k0 + G - 1 <= H2 ? olo : (k0 > H2 ? ohi : (g + k0 <= H2 ? olo : ohi));
+                    const int o = kzo_of(G * jj + 8 * k2) * T + col;
 #pragma unroll
                     for (int c6 = 0; c6 < 6; ++c6)
                         tv[jj * G + k2][c6] = ld_off<R>(blk, (unsigned)(c6 * (Hz * T) + o) * (unsigned)sizeof(R));
@@ -613,7 +709,7 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
                 X[2][e] = mk<R>(nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y);
             }
         // the next tile's inputs are in flight during the inverse transform
-        if (t + 1 < t1) load_tile(t + 1);
+        if (t + 1 < t1) load_tile(un);
         // inverse: length-G DFTs over k2, conjugate twiddles, exchange back
         if constexpr (G > 1) __syncthreads();
 #pragma unroll
@@ -629,7 +725,6 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
             }
         if constexpr (G > 1) __syncthreads();
         cx<R>* base = base_of(d);
-        const bool okc = d.kx0 + col < Hx;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             cx<R> v[8];
@@ -640,11 +735,12 @@ __global__ void __launch_bounds__(G * T) zconvr_kernel(cx<R>* __restrict__ X2, c
 #pragma unroll
             for (int n1 = 0; n1 < 4; ++n1) {
                 const int z = g + G * n1;
-                if (okc && z < nz)
-                    st_stream<R>(&base[(unsigned)c * comp_stride + (unsigned)z * plane_stride + (unsigned)col], v[n1]);
+                if (d.ok && z < nz)
+                    st_stream<R>(&base[(unsigned)c * comp_stride + (unsigned)z * plane_stride + d.off], v[n1]);
             }
         }
         __syncthreads();   // the next tile's forward exchange rewrites E
+        uc = un;
     }
 }
 
@@ -1127,7 +1223,7 @@ static hipError_t run_yfwd(const Plan& pl, const void* X1, void* X2, hipStream_t
                                (long long)(ntiles / ntx) * ((ntx + 1) / 2));
     if (grid < 2) return hipErrorInvalidValue;
     hipLaunchKernelGGL((yfwd_kernel<R, EM, NT, LG>), dim3(grid), dim3(NT), lds, s, static_cast<const cx<R>*>(X1),
-                       static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx, ntiles);
+                       static_cast<cx<R>*>(X2), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx, ntiles, pl.nyqpack);
     return hipGetLastError();
 }
 
@@ -1142,7 +1238,7 @@ static hipError_t run_yinv(const Plan& pl, const void* X2, void* Y1, hipStream_t
                                (long long)(ntiles / ntx) * ((ntx + 1) / 2));
     if (grid < 2) return hipErrorInvalidValue;
     hipLaunchKernelGGL((yinv_kernel<R, EM, NT, LG>), dim3(grid), dim3(NT), lds, s, static_cast<const cx<R>*>(X2),
-                       static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx, ntiles);
+                       static_cast<cx<R>*>(Y1), pl.ny, pl.lgPy, pl.Hx, pl.Sx, lgT, ntx, ntiles, pl.nyqpack);
     return hipGetLastError();
 }
 
@@ -1272,17 +1368,27 @@ template <int T, int G>
 static hipError_t run_zconvr(const Plan& pl, void* X2, const void* spec, float Ms, hipStream_t s) {
     if (pl.Pz != 8 * G || pl.tz != T || 2 * pl.nz > pl.Pz || 4 * pl.nz <= pl.Pz) return hipErrorInvalidValue;
     const int ntx = pl.ntz;
-    const int upm = ntx * (pl.Py / 2);
-    const long long nunits = (long long)upm * pl.nbatch;
+    const int half = pl.Py / 2;
     const size_t lds = (size_t)3 * 8 * G * T * sizeof(cx<float>);
     const int resident =
         persistent_grid(reinterpret_cast<const void*>(&zconvr_kernel<float, T, G>), lds, 1LL << 30, G * T);
     if (resident < 2) return hipErrorInvalidValue;
+    // with a packed Nyquist column the last column tile (only kx = Hx - 1 = Lh)
+    // becomes Nyquist units of T row pairs
+    if (pl.nyqpack && (ntx < 2 || (ntx - 1) * T != pl.Hx - 1 || half % 16 != 0)) return hipErrorInvalidValue;
+    const int ntxn = pl.nyqpack ? ntx - 1 : ntx;
+    const int upm = ntxn * half;
+    const int ngm = pl.nyqpack ? (half + T - 1) / T : 0;
+    const long long nunits = ((long long)upm + ngm) * pl.nbatch;
     long long grid = 2 * std::min<long long>(nunits, std::max(1, resident / 2));
     if (grid >= 16) grid -= grid % 16;
+    // a Nyquist unit costs about two column tiles; balance with that weight
+    // when every pair gets several column tiles and at most one Nyquist unit
+    const long long npairs = grid / 2, NN = (long long)upm * pl.nbatch, NG = (long long)ngm * pl.nbatch;
+    const int gw = (NG > 0 && NG <= npairs && NN >= 4 * npairs) ? 2 : 0;
     hipLaunchKernelGGL((zconvr_kernel<float, T, G>), dim3((unsigned)grid), dim3(G * T), lds, s,
                        static_cast<cx<float>*>(X2), static_cast<const float*>(spec), Ms, pl.nz, pl.Py, pl.Hx, pl.Sx,
-                       ntx, upm, (int)nunits);
+                       ntx, ntxn, upm, ngm, pl.nbatch, gw, pl.tn_off);
     return hipGetLastError();
 }
 

@@ -291,6 +291,25 @@ hipError_t launch_twiddle_init(hipStream_t s) {
     return hipGetLastError();
 }
 
+// The tensor's Nyquist column kx = Hx - 1 (column 0 of each row's last tile)
+// once more, for the z pass's Nyquist units: blocks [6][Hz][tz] like the
+// column tiles', column c of block b holding row q = b tz + c (rows q >= Py/2
+// zero), and one extra block that is block 0 with row Py/2 in column 0 (the
+// mirrored rows' q = 0).
+__global__ void nyquist_copy_kernel(float* spec, int half, int Hz, int tz, int ntz, int nblk, long long tn_off) {
+    const long long e = (long long)blockIdx.x * kNT + threadIdx.x;
+    const long long per = 6LL * Hz * tz;
+    if (e >= (nblk + 1) * per) return;
+    const int b = (int)(e / per);
+    const int r = (int)(e - b * per);
+    const int c6 = r / (Hz * tz), kzo = (r / tz) % Hz, c = r % tz;
+    const int q = b < nblk ? b * tz + c : c;
+    const int kyo = (b == nblk && c == 0) ? half : q;
+    spec[tn_off + e] = (q < half || kyo == half)
+                           ? spec[(((long long)kyo * ntz + ntz - 1) * 6 + c6) * Hz * tz + (long long)kzo * tz]
+                           : 0.0f;
+}
+
 hipError_t build_tensor_spectrum(const Plan& pl, void* spectrum, void* scratch, hipStream_t s) {
     const int nx = pl.nx, ny = pl.ny, nz = pl.nz;
     const long long n = (long long)nx * ny * nz;
@@ -334,6 +353,15 @@ hipError_t build_tensor_spectrum(const Plan& pl, void* spectrum, void* scratch, 
                                static_cast<double*>(spectrum), Q, J, K, pl.Pz, pl.lgPz, kOddZ, sc, offdiag,
                                (long long)pl.Hy * pl.Hx * nz, pl.Hx, pl.tz, (long long)pl.ntz);
         }
+        if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+    }
+    // the Nyquist column kx = Hx - 1 (column 0 of the last tile) once more, in
+    // blocks along ky for the z pass's Nyquist units
+    if (pl.nyqpack) {
+        const int half = pl.Py / 2, nblk = (half + pl.tz - 1) / pl.tz;
+        const long long n = (nblk + 1) * 6LL * pl.Hz * pl.tz;
+        hipLaunchKernelGGL(nyquist_copy_kernel, dim3((unsigned)((n + kNT - 1) / kNT)), dim3(kNT), 0, s,
+                           static_cast<float*>(spectrum), half, pl.Hz, pl.tz, pl.ntz, nblk, pl.tn_off);
         if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
     }
     return hipSuccess;

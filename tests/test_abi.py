@@ -58,8 +58,9 @@ def test_sizes_of_workloads():
     N = 512 * 512 * 32
     assert s["field_bytes"] == 3 * N * 4
     # [Hy][ntz][6][Hz][tz]: single precision with Pz = 64 takes 32-column
-    # tiles (17 for Hx = 513), double precision 16-column tiles (33)
-    assert s["spectrum_bytes"] == 6 * 33 * 513 * (17 * 32) * 4
+    # tiles (17 for Hx = 513) plus a copy of the Nyquist column in 16 + 1
+    # such blocks along ky, double precision 16-column tiles (33)
+    assert s["spectrum_bytes"] == (6 * 33 * 513 * (17 * 32) + 17 * 6 * 33 * 32) * 4
     assert s["tape_bytes_per_step"] == 28 * N * 4
     s64 = magx.magx_sizes((512, 512, 32), (2.5e-9,) * 3, magx.F64)
     assert s64["spectrum_bytes"] == 6 * 33 * 513 * (33 * 16) * 8
