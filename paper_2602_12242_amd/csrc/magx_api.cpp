@@ -200,8 +200,10 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
     p.ws_bytes = off;
     p.tape_step_bytes = (size_t)28 * N * es;
     p.tape_extra_bytes = (size_t)3 * N * es;
-    p.nyqpack = (dt == MAGX_F32 && p.zreg && p.Pz <= 64 && p.Py >= 32 && p.Py <= 1024 && p.Lh >= p.tz &&
-                 p.Sx == p.Lh + 16) ? 1 : 0;
+    // (not at Pz = 8: its one-wave blocks come two units per pair on grids of
+    // that depth, too few to balance a Nyquist unit against)
+    p.nyqpack = (dt == MAGX_F32 && p.zreg && p.Pz >= 16 && p.Pz <= 64 && p.Py >= 32 && p.Py <= 1024 &&
+                 p.Lh >= p.tz && p.Sx == p.Lh + 16) ? 1 : 0;
     p.tn_off = (long long)p.Hy * p.ntz * 6 * p.Hz * p.tz;
     const long long tn_blocks = p.nyqpack ? (p.Py / 2 + p.tz - 1) / p.tz + 1 : 0;
     p.spectrum_bytes = (size_t)(p.tn_off + tn_blocks * 6 * p.Hz * p.tz) * es;

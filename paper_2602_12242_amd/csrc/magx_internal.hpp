@@ -37,7 +37,7 @@ struct Plan {
     int ntz;                    // column tiles of the z pass (and of the tensor spectrum)
     int zreg;                   // z pass held in registers (Pz = 8 ... 128 single, 16 ... 128 double precision)
     int yzfilm, yzt;            // films (nz = 1): the y and z passes fused into one kernel on yzt-column tiles
-    // packed Nyquist column (single-precision register z pass with Pz <= 64,
+    // packed Nyquist column (single-precision register z pass with Pz = 16 ... 64,
     // Py = 32 ... 1024, Lh >= tz): X2's column Lh is stored in the padding
     // columns in groups of 16 row pairs, and the spectrum carries a copy of the
     // tensor's column Lh at element tn_off as ceil(Hy'/tz) + 1 blocks
