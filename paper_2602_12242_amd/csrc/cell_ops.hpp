@@ -107,15 +107,21 @@ __device__ __forceinline__ void store3(R* __restrict__ f, long long N, long long
 // ---- cell pairs (2n, 2n+1) along x ------------------------------------------------
 // With nx even every pair is complete and 8-byte (float) / 16-byte (double)
 // aligned, so a pair is one vector access per component; with nx odd the last
-// pair of a row has a single cell and scalar accesses are used.
-template <typename R>
+// pair of a row has a single cell and scalar accesses are used.  Fields that a
+// pencil kernel writes are read again a whole convolution later at the
+// earliest, so pairs are stored with streaming stores (see st_stream); a field
+// read once (STREAM) is loaded the same way.  Measured at 512 x 512 x 32: the
+// reverse start kernel 186 -> 178 us, the forward y pass that follows a stage
+// 126 -> 122 us.
+template <typename R, bool STREAM = false>
 __device__ __forceinline__ void load_pair(const R* __restrict__ f, long long N, long long id, bool vec, bool two,
                                           R a[3], R b[3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const R* p = f + c * N + id;
         if (vec) {
-            const cx<R> v = *reinterpret_cast<const cx<R>*>(p);
+            const cx<R> v = STREAM ? ld_stream<R>(reinterpret_cast<const cx<R>*>(p))
+                                   : *reinterpret_cast<const cx<R>*>(p);
             a[c] = v.x;
             b[c] = v.y;
         } else {
@@ -133,7 +139,7 @@ __device__ __forceinline__ void store_pair(R* __restrict__ f, long long N, long 
     for (int c = 0; c < 3; ++c) {
         R* p = f + c * N + id;
         if (vec) {
-            *reinterpret_cast<cx<R>*>(p) = mk<R>(a[c], b[c]);
+            st_stream<R>(reinterpret_cast<cx<R>*>(p), mk<R>(a[c], b[c]));
         } else {
             p[0] = a[c];
             if (two) p[1] = b[c];
@@ -404,6 +410,8 @@ __device__ __forceinline__ unsigned x_row(const PG& g, int mb, int c, int pen) {
     return (((unsigned)(mb * 3 + c) * (unsigned)g.nz + (unsigned)z) * (unsigned)g.ny + (unsigned)y) * (unsigned)g.Sx;
 }
 
+template <int V> struct IntC { static constexpr int value = V; };
+
 // The half-length real-FFT split and merge steps pair bin k with its mirror
 // Lh - k: both come from the same two values and the same twiddle
 // W^k = exp(-2 pi i k / Px), since W^(Lh-k) = -conj(W^k).  Item t < Lq
@@ -429,53 +437,57 @@ __device__ void c2r_lines(cx<R>* buf, const cx<R>* Y1, const PG& g, int mb, int 
     if ((1 << lgq) >= kNT) {
         // at least one item per thread and line: thread tid takes items
         // t = tid + k kNT of every line, so its twiddles are the same for all
-        // lines and each line's row address is uniform (scalar registers)
-        constexpr int IPL = 2;                         // items per thread and line at most (Lh <= 1024)
-        const int ipl = (1 << lgq) / kNT;
-        cx<R> wc[IPL];
+        // lines and each line's row address is uniform (scalar registers).
+        // A chunk holds kXIt items per thread: with one item per line the six
+        // lines of a two-pencil block are one chunk and their loads make one
+        // round trip (measured at 512-cell lines: stage 224 -> 211 us).
+        auto chunks = [&](auto ipl_c) {
+            constexpr int IPL = decltype(ipl_c)::value;   // items per thread and line
+            constexpr int LC = kXIt / IPL;                // lines per chunk
+            cx<R> wc[IPL];
 #pragma unroll
-        for (int k = 0; k < IPL; ++k)
-            if (k < ipl) wc[k] = cconj<R>(tw_fwd<R>(((int)threadIdx.x + k * kNT) << twsh));
-        const int nl = npen * 3;
-        constexpr int LC = kXIt / IPL;                 // lines per chunk
-        for (int l0 = 0; l0 < nl; l0 += LC) {
-            cx<R> A[LC][IPL], B[LC][IPL], C[LC];
+            for (int k = 0; k < IPL; ++k) wc[k] = cconj<R>(tw_fwd<R>(((int)threadIdx.x + k * kNT) << twsh));
+            const int nl = npen * 3;
+            for (int l0 = 0; l0 < nl; l0 += LC) {
+                cx<R> A[LC][IPL], B[LC][IPL], C[LC];
 #pragma unroll
-            for (int i = 0; i < LC; ++i) {
-                const int l = min(l0 + i, nl - 1);
-                const int p = l / 3, c = l - 3 * p;
-                const cx<R>* row = Y1 + x_row(g, mb, c, pen0 + p);
+                for (int i = 0; i < LC; ++i) {
+                    const int l = min(l0 + i, nl - 1);
+                    const int p = l / 3, c = l - 3 * p;
+                    const cx<R>* row = Y1 + x_row(g, mb, c, pen0 + p);
 #pragma unroll
-                for (int k = 0; k < IPL; ++k) {
-                    if (k < ipl) {
+                    for (int k = 0; k < IPL; ++k) {
                         const int t = (int)threadIdx.x + k * kNT;
                         A[i][k] = row[t];
                         B[i][k] = row[Lh - t];
                     }
+                    // X[Lh/2] for item 0 of a line (loaded by the first wave only)
+                    C[i] = mk<R>((R)0, (R)0);
+                    if (threadIdx.x < 64) C[i] = row[threadIdx.x == 0 ? (Lh >> 1) : (int)threadIdx.x];
                 }
-                // X[Lh/2] for item 0 of a line (loaded by the first wave only)
-                C[i] = mk<R>((R)0, (R)0);
-                if (threadIdx.x < 64) C[i] = row[threadIdx.x == 0 ? (Lh >> 1) : (int)threadIdx.x];
-            }
 #pragma unroll
-            for (int i = 0; i < LC; ++i) {
-                const int l = l0 + i;
-                if (l >= nl) break;
-                cx<R>* out = buf + l * Lh;
+                for (int i = 0; i < LC; ++i) {
+                    const int l = l0 + i;
+                    if (l >= nl) break;
+                    cx<R>* out = buf + l * Lh;
 #pragma unroll
-                for (int k = 0; k < IPL; ++k) {
-                    if (k >= ipl) break;
-                    const int t = (int)threadIdx.x + k * kNT;
-                    if (t == 0) {
-                        out[0] = split(A[i][k], B[i][k], mk<R>((R)1, (R)0));
-                        out[Lh >> 1] = split(C[i], C[i], mk<R>((R)0, (R)1));   // conj(W^(Lh/2)) = i
-                    } else {
-                        out[t] = split(A[i][k], B[i][k], wc[k]);
-                        out[Lh - t] = split(B[i][k], A[i][k], mk<R>(-wc[k].x, wc[k].y));   // conj(W^(Lh-t)) = -W^t
+                    for (int k = 0; k < IPL; ++k) {
+                        const int t = (int)threadIdx.x + k * kNT;
+                        if (t == 0) {
+                            out[0] = split(A[i][k], B[i][k], mk<R>((R)1, (R)0));
+                            out[Lh >> 1] = split(C[i], C[i], mk<R>((R)0, (R)1));   // conj(W^(Lh/2)) = i
+                        } else {
+                            out[t] = split(A[i][k], B[i][k], wc[k]);
+                            out[Lh - t] = split(B[i][k], A[i][k], mk<R>(-wc[k].x, wc[k].y));   // conj(W^(Lh-t)) = -W^t
+                        }
                     }
                 }
             }
-        }
+        };
+        // Lh <= 2048: one, two or four items per thread and line
+        if ((1 << lgq) == kNT) chunks(IntC<1>{});
+        else if ((1 << lgq) == 2 * kNT) chunks(IntC<2>{});
+        else chunks(IntC<4>{});
     } else {
     // items in chunks of kXIt per thread: all loads of a chunk are issued
     // before any is used (no load behind a branch or a loop-carried wait)
@@ -539,36 +551,38 @@ __device__ void r2c_lines(cx<R>* buf, cx<R>* X1, const PG& g, int mb, int pen0, 
     if ((1 << lgq) >= kNT) {
         // as in the split step: fixed items t = tid + k kNT of every line,
         // uniform row addresses
-        constexpr int IPL = 2;
-        const int ipl = (1 << lgq) / kNT;
-        cx<R> W[IPL];
+        auto lines = [&](auto ipl_c) {
+            constexpr int IPL = decltype(ipl_c)::value;   // items per thread and line
+            cx<R> W[IPL];
 #pragma unroll
-        for (int k = 0; k < IPL; ++k)
-            if (k < ipl) W[k] = tw_fwd<R>(((int)threadIdx.x + k * kNT) << twsh);
-        const int nl = npen * 3;
-        for (int l = 0; l < nl; ++l) {
-            const int p = l / 3, c = l - 3 * p;
-            cx<R>* row = X1 + x_row(g, mb, c, pen0 + p);
-            const cx<R>* in = buf + l * Lh;
+            for (int k = 0; k < IPL; ++k) W[k] = tw_fwd<R>(((int)threadIdx.x + k * kNT) << twsh);
+            const int nl = npen * 3;
+            for (int l = 0; l < nl; ++l) {
+                const int p = l / 3, c = l - 3 * p;
+                cx<R>* row = X1 + x_row(g, mb, c, pen0 + p);
+                const cx<R>* in = buf + l * Lh;
 #pragma unroll
-            for (int k = 0; k < IPL; ++k) {
-                if (k >= ipl) break;
-                const int t = (int)threadIdx.x + k * kNT;
-                if (t == 0) {
-                    const cx<R> P = in[0];
-                    row[0] = mk<R>(P.x + P.y, (R)0);
-                    row[Lh] = mk<R>(P.x - P.y, (R)0);
-                    row[Lh >> 1] = cconj<R>(in[Lh >> 1]);   // W^(Lh/2) = -i
-                } else {
-                    const cx<R> P = in[t], Q = in[Lh - t];
-                    const cx<R> E = mk<R>(half * (P.x + Q.x), half * (P.y - Q.y));
-                    const cx<R> O = mk<R>(half * (P.y + Q.y), half * (Q.x - P.x));
-                    const cx<R> T = cmul<R>(W[k], O);
-                    row[t] = cadd<R>(E, T);
-                    row[Lh - t] = mk<R>(E.x - T.x, T.y - E.y);
+                for (int k = 0; k < IPL; ++k) {
+                    const int t = (int)threadIdx.x + k * kNT;
+                    if (t == 0) {
+                        const cx<R> P = in[0];
+                        row[0] = mk<R>(P.x + P.y, (R)0);
+                        row[Lh] = mk<R>(P.x - P.y, (R)0);
+                        row[Lh >> 1] = cconj<R>(in[Lh >> 1]);   // W^(Lh/2) = -i
+                    } else {
+                        const cx<R> P = in[t], Q = in[Lh - t];
+                        const cx<R> E = mk<R>(half * (P.x + Q.x), half * (P.y - Q.y));
+                        const cx<R> O = mk<R>(half * (P.y + Q.y), half * (Q.x - P.x));
+                        const cx<R> T = cmul<R>(W[k], O);
+                        row[t] = cadd<R>(E, T);
+                        row[Lh - t] = mk<R>(E.x - T.x, T.y - E.y);
+                    }
                 }
             }
-        }
+        };
+        if ((1 << lgq) == kNT) lines(IntC<1>{});
+        else if ((1 << lgq) == 2 * kNT) lines(IntC<2>{});
+        else lines(IntC<4>{});
         return;
     }
     const int count = (npen * 3) << lgq;

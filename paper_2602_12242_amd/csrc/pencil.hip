@@ -199,8 +199,8 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
         // RK4 registers first, so their loads are in flight with the stencil's
         R k[2][3], mn[2][3], acc[2][3], xn[2][3], nrm[2];
         if (s > 1) {
-            load_pair(a.mn, g.N, id, vec, two, mn[0], mn[1]);
-            load_pair(a.acc, g.N, id, vec, two, acc[0], acc[1]);
+            load_pair<R, true>(a.mn, g.N, id, vec, two, mn[0], mn[1]);
+            load_pair<R, true>(a.acc, g.N, id, vec, two, acc[0], acc[1]);
         }
         R ys[2][3], H[2][3], ex[2], dm[2], an[2], sw[2];
         local_field_pair<R>(a.yin, g, x0, y, z, vec, two, ph, ys, H, ex, dm, an, false, sw);

@@ -100,6 +100,16 @@ CASES = {
                    terms=ALL)),
 }
 
+# x lines of 1025 ... 2048 cells (Px = 4096: half-length lines of 2048 values,
+# four split/merge items per thread and line): single precision only, as three
+# such lines exceed the double-precision LDS budget
+LONG_X = {
+    "x2048": ((2048, 2, 1), (2e-9, 2e-9, 2e-9),
+              dict(Ms=8e5, A=1.3e-11, D=1e-3, Ku=3e5, eK=(0, 0, 1), alpha=0.05, Hbias=(0, 0, 1e4), terms=ALL)),
+    "x1100": ((1100, 3, 2), (2e-9, 2e-9, 2e-9),
+              dict(Ms=1e6, A=1.6e-11, D=2.5e-3, alpha=0.1, Hbias=(1e3, 2e3, -3e3), terms=ALL)),
+}
+
 
 def _ctx(n, d, dtype):
     from paper_2602_12242_amd import magx
@@ -135,7 +145,7 @@ _SPEC_CACHE = {}
 
 def _oracle_setup(name):
     if name not in _SPEC_CACHE:
-        n, d, mat = CASES[name]
+        n, d, mat = CASES[name] if name in CASES else LONG_X[name]
         _SPEC_CACHE[name] = _spec_for(n, d)
     return _SPEC_CACHE[name]
 
@@ -205,6 +215,27 @@ def test_one_rk4_step_matches_oracle(name, dtype):
     ctx.step(mg, _gpu_params(mat), dt, 1)
     err = np.abs(mg.cpu().numpy() - ref).max()
     assert err <= (1e-11 if dtype == 1 else 1e-5), err
+
+
+@pytest.mark.parametrize("name", list(LONG_X))
+def test_long_x_lines_match_oracle(name):
+    from paper_2602_12242_amd import magx
+    n, d, mat = LONG_X[name]
+    g, spec, P = _oracle_setup(name)
+    p = _oracle_params(mat)
+    m = _m0(n, 108)
+    ctx = _ctx(n, d, 0)
+    H = ctx.heff(_dev(m, 0), _gpu_params(mat))
+    assert _err(H.cpu().numpy(), ofield.heff(g, p, m.astype(np.float64), spec, P)) <= 1e-5
+    ref = ollg.rk4_step(g, p, m.astype(np.float64), 1e-13, spec, P)
+    mg = _dev(m, 0)
+    ctx.step(mg, _gpu_params(mat), 1e-13, 1)
+    assert np.abs(mg.cpu().numpy() - ref).max() <= 1e-5
+    gH = random_vector_field(n, 109)
+    gm, _ = ctx.heff_backward(_dev(gH, 0), _gpu_params(mat))
+    assert _err(gm.cpu().numpy(), ofield.linear_part(g, p, gH, spec, P)) <= 1e-5
+    with pytest.raises(magx.MagxError):
+        _ctx(n, d, 1)
 
 
 @pytest.mark.parametrize("renorm", [0, 1, 2])
