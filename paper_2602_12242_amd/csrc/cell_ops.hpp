@@ -25,6 +25,8 @@ struct PG {
     int lgLq;
     int bpm;                                                 // blocks per member
     int zmajor;                                              // block order: z fastest (see block_pencils)
+    int stream;                                              // streaming cell-pair stores (see store_pair;
+                                                             // kernels read it once, as stream_of)
     long long N;                                             // cells of one member
     FastDiv div_ny, div_hx;                                  // n / ny and n / Hx
 };
@@ -59,6 +61,14 @@ __device__ __forceinline__ void pg_fix(PG& g) {
     }
 }
 
+// The streaming flag of a kernel, read once into a register: the 32-element
+// register budget (BIG) leaves no room for the second store path, so those
+// kernels never stream.
+template <bool BIG>
+__device__ __forceinline__ bool stream_of(const PG& g) {
+    return !BIG && g.stream != 0;
+}
+
 inline PG make_pg(const Plan& pl) {
     PG g;
     g.nx = pl.nx; g.ny = pl.ny; g.nz = pl.nz;
@@ -68,6 +78,8 @@ inline PG make_pg(const Plan& pl) {
     g.div_ny = make_fastdiv(pl.ny);
     g.div_hx = make_fastdiv(pl.Hx);
     g.zmajor = pl.pencil_zmajor;
+    // fields of 64 MiB and more (a batch counts whole) are far larger than the caches
+    g.stream = !pencil_big(pl) && 3.0 * (double)pl.ncell * pl.nbatch * pl.esize >= 64.0 * (1 << 20) ? 1 : 0;
     return g;
 }
 
@@ -109,18 +121,20 @@ __device__ __forceinline__ void store3(R* __restrict__ f, long long N, long long
 // aligned, so a pair is one vector access per component; with nx odd the last
 // pair of a row has a single cell and scalar accesses are used.  Fields that a
 // pencil kernel writes are read again a whole convolution later at the
-// earliest, so pairs are stored with streaming stores (see st_stream); a field
-// read once (STREAM) is loaded the same way.  Measured at 512 x 512 x 32: the
+// earliest; on grids whose fields are far larger than the caches (PG::stream)
+// pairs are stored with streaming stores (see st_stream), and a field read
+// once (stream) is loaded the same way.  Measured at 512 x 512 x 32: the
 // reverse start kernel 186 -> 178 us, the forward y pass that follows a stage
-// 126 -> 122 us.
-template <typename R, bool STREAM = false>
+// 126 -> 122 us; at 256 x 256 x 16, whose fields stay in the caches, the same
+// accesses cost 3 % of an RK4 step.
+template <typename R>
 __device__ __forceinline__ void load_pair(const R* __restrict__ f, long long N, long long id, bool vec, bool two,
-                                          R a[3], R b[3]) {
+                                          R a[3], R b[3], bool stream = false) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         const R* p = f + c * N + id;
         if (vec) {
-            const cx<R> v = STREAM ? ld_stream<R>(reinterpret_cast<const cx<R>*>(p))
+            const cx<R> v = stream ? ld_stream<R>(reinterpret_cast<const cx<R>*>(p))
                                    : *reinterpret_cast<const cx<R>*>(p);
             a[c] = v.x;
             b[c] = v.y;
@@ -134,12 +148,13 @@ __device__ __forceinline__ void load_pair(const R* __restrict__ f, long long N, 
 
 template <typename R>
 __device__ __forceinline__ void store_pair(R* __restrict__ f, long long N, long long id, bool vec, bool two,
-                                           const R a[3], const R b[3]) {
+                                           const R a[3], const R b[3], bool stream = false) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
         R* p = f + c * N + id;
         if (vec) {
-            st_stream<R>(reinterpret_cast<cx<R>*>(p), mk<R>(a[c], b[c]));
+            if (stream) st_stream<R>(reinterpret_cast<cx<R>*>(p), mk<R>(a[c], b[c]));
+            else *reinterpret_cast<cx<R>*>(p) = mk<R>(a[c], b[c]);
         } else {
             p[0] = a[c];
             if (two) p[1] = b[c];

@@ -24,6 +24,7 @@ __global__ void __launch_bounds__(kNT) mri_slow_kernel(const cx<R>* __restrict__
                                                        PG g, Phys<R> ph, int has_demag, R* __restrict__ S_out,
                                                        const R* __restrict__ Sa, const R* __restrict__ Sb, R wa,
                                                        R wb, R wn, R* __restrict__ r_out) {
+    const bool stream = stream_of<BIG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -77,8 +78,8 @@ __global__ void __launch_bounds__(kNT) mri_slow_kernel(const cx<R>* __restrict__
             for (int c = 0; c < 3; ++c) { r[0][c] += wb * b0[c]; r[1][c] += wb * b1[c]; }
         }
         if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(r[0]) || (two && any_nonfinite<R, 3>(r[1])));
-        if (S_out) store_pair(S_out, g.N, id, vec, two, S[0], S[1]);
-        store_pair(r_out, g.N, id, vec, two, r[0], r[1]);
+        if (S_out) store_pair(S_out, g.N, id, vec, two, S[0], S[1], stream);
+        store_pair(r_out, g.N, id, vec, two, r[0], r[1], stream);
     }
 }
 
@@ -89,6 +90,7 @@ __global__ void __launch_bounds__(kNT) mri_fast_kernel(const R* __restrict__ v, 
                                                        R* __restrict__ qbuf, const R* __restrict__ rbuf, PG g,
                                                        Phys<R> ph, R Ak, R Bk, R h, int first, int norm, int fwd,
                                                        cx<R>* __restrict__ X1) {
+    const bool stream = stream_of<BIG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
@@ -143,8 +145,8 @@ __global__ void __launch_bounds__(kNT) mri_fast_kernel(const R* __restrict__ v, 
             }
         }
         if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(xn[0]) || (two && any_nonfinite<R, 3>(xn[1])));
-        store_pair(qbuf, g.N, id, vec, two, q[0], q[1]);
-        store_pair(vout, g.N, id, vec, two, xn[0], xn[1]);
+        store_pair(qbuf, g.N, id, vec, two, q[0], q[1], stream);
+        store_pair(vout, g.N, id, vec, two, xn[0], xn[1], stream);
         if (fwd) {
             // demag source of the next slow stage: Ms(r) m = Ms s m
 #pragma unroll

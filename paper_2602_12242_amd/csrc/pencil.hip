@@ -67,6 +67,7 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
                                                     int with_bias, int energy, int sum_input,
                                                     double* __restrict__ partials) {
     pg_fix<LG>(g);
+    const bool stream = stream_of<BIG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
@@ -126,7 +127,7 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
         }
         if (!energy) {
             if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(out[0]) || (two && any_nonfinite<R, 3>(out[1])));
-            store_pair(H, g.N, id, vec, two, out[0], out[1]);
+            store_pair(H, g.N, id, vec, two, out[0], out[1], stream);
         }
     }
     if (energy && ph.nf) note_nonfinite(ph.nf, !isfinite(acc[0] + acc[1] + acc[2] + acc[3] + acc[4]));
@@ -147,6 +148,7 @@ template <typename R, bool BIG, int LG>
 __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, PG g,
                                                     Phys<R> ph, StageArgs<R> a, int has_demag) {
     pg_fix<LG>(g);
+    const bool stream = stream_of<BIG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     // logical block -> member mb and its first pencil; members own contiguous block ranges
@@ -199,8 +201,8 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
         // RK4 registers first, so their loads are in flight with the stencil's
         R k[2][3], mn[2][3], acc[2][3], xn[2][3], nrm[2];
         if (s > 1) {
-            load_pair<R, true>(a.mn, g.N, id, vec, two, mn[0], mn[1]);
-            load_pair<R, true>(a.acc, g.N, id, vec, two, acc[0], acc[1]);
+            load_pair(a.mn, g.N, id, vec, two, mn[0], mn[1], stream);
+            load_pair(a.acc, g.N, id, vec, two, acc[0], acc[1], stream);
         }
         R ys[2][3], H[2][3], ex[2], dm[2], an[2], sw[2];
         local_field_pair<R>(a.yin, g, x0, y, z, vec, two, ph, ys, H, ex, dm, an, false, sw);
@@ -214,8 +216,8 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
                 if (ph.terms & MAGX_ZEEMAN) H[q][c] += inside * hbv[c];
             }
         }
-        if (a.tapeH) store_pair(a.tapeH, g.N, id, vec, two, H[0], H[1]);
-        if (a.tapeYin) store_pair(a.tapeYin, g.N, id, vec, two, ys[0], ys[1]);
+        if (a.tapeH) store_pair(a.tapeH, g.N, id, vec, two, H[0], H[1], stream);
+        if (a.tapeYin) store_pair(a.tapeYin, g.N, id, vec, two, ys[0], ys[1], stream);
 #pragma unroll
         for (int q = 0; q < 2; ++q) llg_rhs<R>(ys[q], H[q], ph.a, ph.alpha, k[q]);
         if (s <= 1) {
@@ -250,13 +252,13 @@ __global__ void __launch_bounds__(kNT) stage_kernel(const cx<R>* Y1, cx<R>* X1, 
         if (ph.nf)
             note_nonfinite(ph.nf, any_nonfinite<R, 3>(xn[0]) || any_nonfinite<R, 3>(H[0]) ||
                                       (two && (any_nonfinite<R, 3>(xn[1]) || any_nonfinite<R, 3>(H[1]))));
-        if (s >= 1 && s < 4) store_pair(a.acc, g.N, id, vec, two, acc[0], acc[1]);
+        if (s >= 1 && s < 4) store_pair(a.acc, g.N, id, vec, two, acc[0], acc[1], stream);
         if (a.tapeNx) {
             if (vec) *reinterpret_cast<cx<R>*>(a.tapeNx + id) = mk<R>(nrm[0], nrm[1]);
             else { a.tapeNx[id] = nrm[0]; if (two) a.tapeNx[id + 1] = nrm[1]; }
         }
-        store_pair(a.yout, g.N, id, vec, two, xn[0], xn[1]);
-        if (a.yout2) store_pair(a.yout2, g.N, id, vec, two, xn[0], xn[1]);
+        store_pair(a.yout, g.N, id, vec, two, xn[0], xn[1], stream);
+        if (a.yout2) store_pair(a.yout2, g.N, id, vec, two, xn[0], xn[1], stream);
         if (fwd) {
             // demag source of the next stage: Ms(r) m = Ms s m
 #pragma unroll
@@ -272,6 +274,7 @@ template <typename R, bool BIG, int LG>
 __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG g, Phys<R> ph, StartArgs<R> a,
                                                      int has_demag, double* __restrict__ partials) {
     pg_fix<LG>(g);
+    const bool stream = stream_of<BIG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
@@ -341,10 +344,10 @@ __global__ void __launch_bounds__(kNT) bstart_kernel(cx<R>* __restrict__ X1, PG 
             rhs_mu<R>(y4[q], kap[q], ph.a, ph.alpha, mu[q]);
         }
         if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(xi[0]) || (two && any_nonfinite<R, 3>(xi[1])));
-        store_pair(a.xi5, g.N, id, vec, two, xi[0], xi[1]);
-        store_pair(a.gm, g.N, id, vec, two, xi[0], xi[1]);
-        store_pair(a.kap, g.N, id, vec, two, kap[0], kap[1]);
-        store_pair(a.muout, g.N, id, vec, two, mu[0], mu[1]);
+        store_pair(a.xi5, g.N, id, vec, two, xi[0], xi[1], stream);
+        store_pair(a.gm, g.N, id, vec, two, xi[0], xi[1], stream);
+        store_pair(a.kap, g.N, id, vec, two, kap[0], kap[1], stream);
+        store_pair(a.muout, g.N, id, vec, two, mu[0], mu[1], stream);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const R m1 = two ? mu[1][c] : (R)0;
@@ -367,6 +370,7 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
                                                      Phys<R> ph, BackArgs<R> a, int has_demag,
                                                      double* __restrict__ partials) {
     pg_fix<LG>(g);
+    const bool stream = stream_of<BIG>(g);
     extern __shared__ unsigned char smem_raw[];
     cx<R>* buf = reinterpret_cast<cx<R>*>(smem_raw);
     __shared__ double red[kNT];
@@ -471,9 +475,9 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
                 rhs_mu<R>(yp[q], kp[q], ph.a, ph.alpha, mup[q]);
             }
             if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(lam[0]) || (two && any_nonfinite<R, 3>(lam[1])));
-            store_pair(a.gm, g.N, id, vec, two, lam[0], lam[1]);
-            store_pair(a.kap, g.N, id, vec, two, kp[0], kp[1]);
-            store_pair(a.muout, g.N, id, vec, two, mup[0], mup[1]);
+            store_pair(a.gm, g.N, id, vec, two, lam[0], lam[1], stream);
+            store_pair(a.kap, g.N, id, vec, two, kp[0], kp[1], stream);
+            store_pair(a.muout, g.N, id, vec, two, mup[0], mup[1], stream);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 const R m1 = two ? mup[1][c] : (R)0;
@@ -486,7 +490,7 @@ __global__ void __launch_bounds__(kNT) bstage_kernel(const cx<R>* Y1, cx<R>* X1,
 #pragma unroll
                 for (int c = 0; c < 3; ++c) lam[q][c] += yb[q][c];
             if (ph.nf) note_nonfinite(ph.nf, any_nonfinite<R, 3>(lam[0]) || (two && any_nonfinite<R, 3>(lam[1])));
-            store_pair(a.gm, g.N, id, vec, two, lam[0], lam[1]);
+            store_pair(a.gm, g.N, id, vec, two, lam[0], lam[1], stream);
         }
     }
     if (s > 1 && (ph.terms & MAGX_ZEEMAN)) {

@@ -95,6 +95,12 @@ CASES = {
     "sq512": ((512, 512, 2), (2.5e-9, 2.5e-9, 2.5e-9),
               dict(Ms=8e5, A=1.3e-11, D=1e-3, Ku=3e5, eK=(0.0, 0.6, 0.8), alpha=0.5, Hbias=(2e3, -1e3, 4e3),
                    terms=ALL)),
+    # 257 ... 512 cells along x with no compile-time geometry (Lh = 512, the
+    # split and merge steps with the first / last radix-2 pass inside); odd nx
+    # ends every row with a single cell
+    "x301": ((301, 5, 3), (2e-9, 2e-9, 2e-9),
+             dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, eK=(0.0, 0.6, 0.8), alpha=0.1, Hbias=(1e3, -2e3, 5e3),
+                  terms=ALL)),
     "sq256": ((256, 256, 4), (2e-9, 2e-9, 2e-9),
               dict(Ms=1e6, A=1.6e-11, D=2.5e-3, Ku=8e5, eK=(0, 0, 1), alpha=0.1, Hbias=(1e3, 2e3, -3e3),
                    terms=ALL)),
@@ -202,7 +208,7 @@ def test_llg_rhs_matches_oracle(dtype):
 
 
 @pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "film", "line", "cell", "tiles", "thick", "long_y",
-                                  "pow2_256", "pow2_1024", "sq512", "sq256", "slab40", "slab64", "y2048"])
+                                  "pow2_256", "pow2_1024", "sq512", "sq256", "slab40", "slab64", "y2048", "x301"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_one_rk4_step_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -277,7 +283,7 @@ def test_energy_matches_oracle(name, dtype):
 
 
 @pytest.mark.parametrize("name", ["tiny_all", "ragged_dmi", "tiles", "thick", "pow2_256", "sq512", "sq256", "slab40",
-                                  "y2048"])
+                                  "y2048", "x301"])
 @pytest.mark.parametrize("dtype", [1, 0])
 def test_heff_backward_matches_oracle(name, dtype):
     n, d, mat = CASES[name]
@@ -293,7 +299,7 @@ def test_heff_backward_matches_oracle(name, dtype):
 
 
 @pytest.mark.parametrize("renorm", [0, 1, 2])
-@pytest.mark.parametrize("name", ["tiny_all", "tiles", "pow2_256", "sq512", "sq256"])
+@pytest.mark.parametrize("name", ["tiny_all", "tiles", "pow2_256", "sq512", "sq256", "x301"])
 def test_step_backward_matches_oracle(name, renorm):
     n, d, mat = CASES[name]
     mat = dict(mat, renorm=renorm)
