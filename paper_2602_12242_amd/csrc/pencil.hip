@@ -60,12 +60,16 @@ __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R
     r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
 
-// mode: 0 -> write H (with bias if with_bias); 1 -> energy partials (m.H_term)
-template <typename R, bool BIG, int LG>
-__global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1, const R* __restrict__ f,
-                                                    R* __restrict__ H, PG g, Phys<R> ph, int has_demag,
-                                                    int with_bias, int energy, int sum_input,
-                                                    double* __restrict__ partials) {
+// mode: 0 -> write H (with bias if with_bias); 1 -> energy partials (m.H_term).
+// RED: the block sums (energy, or the sum of the input field) are wanted; the
+// plain field evaluation is a kernel of its own without their accumulators,
+// which keeps it within the registers of five waves per SIMD.
+template <typename R, bool BIG, int LG, bool RED>
+__device__ __forceinline__ void field_body(const cx<R>* __restrict__ Y1, const R* __restrict__ f,
+                                           R* __restrict__ H, PG g, Phys<R> ph, int has_demag,
+                                           int with_bias, int energy, int sum_input,
+                                           double* __restrict__ partials) {
+    if constexpr (!RED) energy = sum_input = 0;
     pg_fix<LG>(g);
     const bool stream = stream_of<BIG>(g);
     extern __shared__ unsigned char smem_raw[];
@@ -142,6 +146,22 @@ __global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1
             if (threadIdx.x == 0) partials[lb * 8 + v] += sm;
         }
     }
+}
+
+template <typename R, bool BIG, int LG>
+__global__ void __launch_bounds__(kNT) field_kernel(const cx<R>* __restrict__ Y1, const R* __restrict__ f,
+                                                    R* __restrict__ H, PG g, Phys<R> ph, int has_demag,
+                                                    int with_bias, int energy, int sum_input,
+                                                    double* __restrict__ partials) {
+    field_body<R, BIG, LG, false>(Y1, f, H, g, ph, has_demag, with_bias, energy, sum_input, partials);
+}
+
+template <typename R, bool BIG, int LG>
+__global__ void __launch_bounds__(kNT) field_reduce_kernel(const cx<R>* __restrict__ Y1, const R* __restrict__ f,
+                                                           R* __restrict__ H, PG g, Phys<R> ph, int has_demag,
+                                                           int with_bias, int energy, int sum_input,
+                                                           double* __restrict__ partials) {
+    field_body<R, BIG, LG, true>(Y1, f, H, g, ph, has_demag, with_bias, energy, sum_input, partials);
 }
 
 template <typename R, bool BIG, int LG>
@@ -601,7 +621,10 @@ template <typename R>
 hipError_t launch_field(const Plan& pl, const Phys<R>& ph, const void* Y1, const R* f, R* H, int with_bias,
                         int energy, int sum_input, double* partials, hipStream_t s) {
     const int has_demag = (ph.terms & MAGX_DEMAG) ? 1 : 0;
-    MAGX_PENCIL_LAUNCH(field_kernel, static_cast<const cx<R>*>(Y1), f, H, make_pg(pl), ph, has_demag, with_bias, energy, sum_input, partials);
+    if (energy || sum_input)
+        MAGX_PENCIL_LAUNCH(field_reduce_kernel, static_cast<const cx<R>*>(Y1), f, H, make_pg(pl), ph, has_demag, with_bias, energy, sum_input, partials);
+    else
+        MAGX_PENCIL_LAUNCH(field_kernel, static_cast<const cx<R>*>(Y1), f, H, make_pg(pl), ph, has_demag, with_bias, energy, sum_input, partials);
     return hipGetLastError();
 }
 
