@@ -224,6 +224,18 @@ def oracle_rates(w, max_cells=(128, 128)):
 CONFIG_NAMES = ("film", "dmi", "demag", "adjoint", "large")
 
 
+def _reps_for(fn, seconds, lo=3, hi=5000):
+    """Repetitions of fn that take about `seconds` (one call timed after a warm-up)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    one = max(time.perf_counter() - a, 1e-7)
+    return int(max(lo, min(hi, seconds / one)))
+
+
 def config_measurements(magx, torch, timeit, names=CONFIG_NAMES, oracle=True):
     """Every workload in float32 and float64: rates, roofline fractions under
     the bytes model, errors against the oracle and between precisions."""
@@ -246,11 +258,12 @@ def config_measurements(magx, torch, timeit, names=CONFIG_NAMES, oracle=True):
             ctx = magx.Context(w.n, w.d, dt_code)
             m = m0.to(ctx.tdtype)
             H = ctx.field()
-            reps = 3 if name == "large" else 10
-            t_h = timeit(lambda: ctx.heff(m, p, out=H), reps)
+            # repetitions for about 50 ms of calls (at least 3): a film's call
+            # lasts tens of microseconds, so a few calls would time the host
+            t_h = timeit(lambda: ctx.heff(m, p, out=H), _reps_for(lambda: ctx.heff(m, p, out=H), 0.05))
             y = m.clone()
             nst = 2 if name == "large" else 5
-            t_s = timeit(lambda: ctx.step(y, p, w.dt, nst), 2) / nst
+            t_s = timeit(lambda: ctx.step(y, p, w.dt, nst), _reps_for(lambda: ctx.step(y, p, w.dt, nst), 0.05)) / nst
             m1 = m.clone()
             ctx.step(m1, p, w.dt, 1)
             H = ctx.heff(m, p)
