@@ -174,14 +174,17 @@ int make_plan(const magx_grid* g, magx_dtype dt, int nbatch, Plan* pl) {
     }
     // pencils per block: up to 1024/Lh (one block holds 3 np lines of Lh
     // complex values); fewer on small grids, so that a member has at least
-    // 256 blocks when it has enough pencils (a block's instruction stream, not
-    // the traffic, bounds a small grid's kernels).  Independent of the batch
-    // size: a member's block partition, and so the order of its block sums,
-    // is the same in a batch as alone.
+    // 1024 blocks in single precision (four per CU, within the five resident
+    // at the stage kernel's registers) and 256 in double precision (whose
+    // kernels hold fewer blocks per CU) when it has enough pencils: a block's
+    // chain of memory round trips, not the traffic, bounds a small grid's
+    // kernels.  Independent of the batch size: a member's block partition,
+    // and so the order of its block sums, is the same in a batch as alone.
     const int npen = p.ny * p.nz;
+    const int min_blocks = dt == MAGX_F32 ? 1024 : 256;
     p.np = std::max(1, 1024 / p.Lh);
     if (p.np > npen) p.np = npen;
-    while (p.np > 1 && (npen + p.np - 1) / p.np < 256) p.np >>= 1;
+    while (p.np > 1 && (npen + p.np - 1) / p.np < min_blocks) p.np >>= 1;
     // pencil blocks never straddle two members (the last one of a member may be
     // ragged); with ny >= np and nz > 1 a block holds np rows of one plane and
     // blocks run through z fastest
