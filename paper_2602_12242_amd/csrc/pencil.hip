@@ -38,24 +38,40 @@ __global__ void __launch_bounds__(kNT) xfwd_kernel(const R* __restrict__ f, cx<R
     block_pencils(g, lb - mb * g.bpm, pen0, npen);
     const long long mo = (long long)mb * 3 * g.N;   // member offset of vector fields
     f += mo;
-    for (int e = threadIdx.x; e < npen << g.lgLq; e += kNT) {
+    const bool vec = (g.nx & 1) == 0;
+    const int nitem = npen << g.lgLq;
+    // every cell pair of this thread is loaded first (one 8-byte load per
+    // component when nx is even), so that their latencies overlap; the LDS
+    // line entries are written afterwards
+    R va[maxslot<BIG>()][3], vb[maxslot<BIG>()][3], s0[maxslot<BIG>()], s1[maxslot<BIG>()];
+#pragma unroll
+    for (int i = 0; i < maxslot<BIG>(); ++i) {
+        const int e = threadIdx.x + i * kNT;
+        s0[i] = s1[i] = (R)1;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) va[i][c] = vb[i][c] = (R)0;
+        if (e >= nitem) continue;
         const int p = e >> g.lgLq, n = e & ((1 << g.lgLq) - 1);
+        const int x0 = 2 * n;
+        if (x0 >= g.nx) continue;
         int y, z;
         pen_coords<R>(g, pen0 + p, y, z);
-        const long long row = ((long long)z * g.ny + y) * g.nx;
-        const int x0 = 2 * n, x1 = 2 * n + 1;
+        const long long id = ((long long)z * g.ny + y) * g.nx + x0;
+        const bool two = x0 + 1 < g.nx;
+        load_pair(f, g.N, id, vec, two, va[i], vb[i]);
         // the demag source is Ms(r) m = Ms s m with a magnetisation profile
-        R s0 = (R)1, s1 = (R)1;
         if (msp) {
-            s0 = x0 < g.nx ? msp[row + x0] : (R)0;
-            s1 = x1 < g.nx ? msp[row + x1] : (R)0;
+            s0[i] = msp[id];
+            s1[i] = two ? msp[id + 1] : (R)0;
         }
+    }
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const R a = x0 < g.nx ? f[c * g.N + row + x0] : (R)0;
-            const R b = x1 < g.nx ? f[c * g.N + row + x1] : (R)0;
-            buf[(3 * p + c) * g.Lh + n] = mk<R>(s0 * a, s1 * b);
-        }
+    for (int i = 0; i < maxslot<BIG>(); ++i) {
+        const int e = threadIdx.x + i * kNT;
+        if (e >= nitem) continue;
+        const int p = e >> g.lgLq, n = e & ((1 << g.lgLq) - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) buf[(3 * p + c) * g.Lh + n] = mk<R>(s0[i] * va[i][c], s1[i] * vb[i][c]);
     }
     r2c_lines<R, BIG>(buf, X1, g, mb, pen0, npen);
 }
